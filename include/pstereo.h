@@ -1,0 +1,156 @@
+/*
+ * pstereo.h -- C ABI of the MI355X (gfx950) pseudo-stereo DIBR library.
+ *
+ * One 2D RGB frame in, a stereo pair (left view, right view) and a red-cyan
+ * anaglyph out, by the conversion scheme of "3D Pseudo Stereo Visualization
+ * with GPGPU Support" (Section 3, Fig. 1; Section 4, the seven steps):
+ *
+ *   depth map from block colour / edge / region cues
+ *   -> cross-bilateral filtering of the depth map, guided by luma
+ *   -> left and right frame reconstruction by the depth -> shift rule of the
+ *      Fig. 3 code (threshold 150, half of the stereo base per view), written
+ *      as a row-wise z-buffered forward warp
+ *   -> inpainting of the holes (nearest background pixel of the row)
+ *   -> stereo formatting (anaglyph: red from the left view, green and blue
+ *      from the right view, as the Fig. 3 code builds its result).
+ *
+ * Conventions shared by every entry point:
+ *  - Images are contiguous uint8 RGB24, [h][w][3], row pitch 3*w bytes, in
+ *    DEVICE memory of the context's GPU (for example torch uint8 CUDA tensors).
+ *    Host pointers are rejected with PSTEREO_E_INVALID.
+ *  - The caller owns every image buffer; the context owns all scratch memory,
+ *    allocated once in pstereo_create.  No call after create allocates device
+ *    memory, so the launch sequence can be captured into a HIP graph.
+ *  - Calls enqueue work on params->stream (a hipStream_t, NULL = the context's
+ *    own stream) and return; outputs are valid once that stream has reached
+ *    the work (synchronise it, or set PSTEREO_SYNC).
+ *  - Every call returns a status code; nothing is thrown across the ABI.
+ *    Errors are not sticky.  The message of the last failure is kept per
+ *    context (pstereo_last_error).  A context is not thread-safe: use one per
+ *    host thread.
+ */
+#ifndef PSTEREO_H
+#define PSTEREO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define PSTEREO_OK 0
+#define PSTEREO_E_INVALID (-1)     /* bad argument: size, range, null or host pointer */
+#define PSTEREO_E_NOMEM (-2)       /* device allocation failed (create only) */
+#define PSTEREO_E_DEVICE (-3)      /* a HIP runtime call or kernel launch failed */
+#define PSTEREO_E_ALIAS (-4)       /* output buffers overlap each other or an input */
+#define PSTEREO_E_UNSUPPORTED (-5) /* valid request this build cannot run (e.g. too wide for LDS) */
+#define PSTEREO_E_BUSY (-6)        /* server: request not admitted now, retry later */
+
+/* Flags. */
+#define PSTEREO_DEPTH_EXTERNAL 0x1u /* depth_in replaces the generated depth map */
+#define PSTEREO_SYNC 0x2u           /* block until the outputs are complete */
+#define PSTEREO_PROFILE 0x4u        /* record per-kernel HIP events (pstereo_profile_collect) */
+
+/* Largest number of depth blocks per frame (region grouping runs in one
+ * workgroup's LDS). */
+#define PSTEREO_MAX_BLOCKS 32768
+
+/*
+ * Parameters of one synthesis.  Initialise with pstereo_params_init, then
+ * override fields.  The paper fixes only the threshold 150 and the half-base
+ * per view (Section 4, Fig. 3); every other constant is the library's reading.
+ */
+typedef struct pstereo_params {
+    uint32_t struct_size;     /* must be sizeof(pstereo_params) (ABI version check) */
+    int32_t max_disparity;    /* B: maximum total parallax in px, 0..255 ("Base"
+                                 of the Fig. 3 code); -1 = round(0.02 * w) */
+    int32_t depth_threshold;  /* T: depths above T shift crossed (in front of the
+                                 screen), others uncrossed; 150 in the paper;
+                                 -1..255, -1 = linear mode (depth 0 at the screen) */
+    int32_t block_size;       /* K: depth block edge in px, one of 4, 8, 16, 32, 64;
+                                 0 = smallest of 8, 16, 32, 64 giving at most
+                                 PSTEREO_MAX_BLOCKS blocks */
+    int32_t edge_thresh;      /* g: a block is an edge block when some forward luma
+                                 step inside it exceeds g; 0..255, default 24 */
+    int32_t link_thresh;      /* tau: neighbouring non-edge blocks join one region
+                                 when their mean colours differ by <= tau (sum of
+                                 |dR|+|dG|+|dB|); 0..765, default 24 */
+    int32_t cbf_radius;       /* r: cross-bilateral window (2r+1)^2, 0..3, default 2;
+                                 spatial sigma 1.5 px, range sigma 12 luma levels */
+    uint32_t flags;           /* PSTEREO_DEPTH_EXTERNAL | PSTEREO_SYNC | PSTEREO_PROFILE */
+    const uint8_t *depth_in;  /* device uint8 [h][w]: depth map (255 = nearest) used
+                                 instead of the generated one when
+                                 PSTEREO_DEPTH_EXTERNAL is set; filtered like it */
+    uint8_t *out_depth;       /* optional device uint8 [h][w]: filtered depth */
+    uint8_t *out_depth_raw;   /* optional device uint8 [h][w]: depth before filtering */
+    void *stream;             /* hipStream_t to enqueue on; NULL = context stream */
+} pstereo_params;
+
+typedef struct pstereo_ctx pstereo_ctx;
+
+/* Fill *p with the defaults above (B = -1, T = 150, K = 0, g = 24, tau = 24,
+ * r = 2, no flags, no optional buffers, stream NULL).  Returns PSTEREO_OK, or
+ * PSTEREO_E_INVALID for a null pointer. */
+int pstereo_params_init(pstereo_params *p);
+
+/* Create a context on HIP device `device` for frames up to max_w x max_h
+ * (1 <= max_w <= 65535, 1 <= max_h <= 65535).  Allocates the context's stream
+ * and all scratch memory.  On success *out receives the context.  Errors:
+ * PSTEREO_E_INVALID (bad device or sizes, out == NULL), PSTEREO_E_NOMEM,
+ * PSTEREO_E_DEVICE. */
+int pstereo_create(pstereo_ctx **out, int device, int max_w, int max_h);
+
+/* Synthesize the left view, right view and anaglyph of one frame.
+ *   frame        device RGB24 [h][w][3], read only
+ *   w, h         frame size, 1 <= w <= max_w, 1 <= h <= max_h
+ *   p            parameters (NULL = defaults)
+ *   out_left     device RGB24 [h][w][3] (may be NULL to skip)
+ *   out_right    device RGB24 [h][w][3] (may be NULL to skip)
+ *   out_anaglyph device RGB24 [h][w][3] (may be NULL to skip)
+ * Outputs must not overlap each other, the frame or the depth buffers
+ * (PSTEREO_E_ALIAS).  Returns PSTEREO_E_UNSUPPORTED when the frame is too
+ * wide for the row renderer's LDS budget (about 8900 px at r = 2). */
+int pstereo_synthesize(pstereo_ctx *ctx, const uint8_t *frame, int w, int h,
+                       const pstereo_params *p, uint8_t *out_left,
+                       uint8_t *out_right, uint8_t *out_anaglyph);
+
+/* Release the context, its stream and its scratch memory.  NULL is a no-op.
+ * Waits for the context's outstanding work first. */
+int pstereo_destroy(pstereo_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none); ctx may be NULL for
+ * failures of pstereo_create.  The string lives until the next call on ctx. */
+const char *pstereo_last_error(const pstereo_ctx *ctx);
+
+/*
+ * Per-block intermediate results of the last pstereo_synthesize on ctx with a
+ * generated depth map (for inspection and parity tests).  Waits for that
+ * call's stream.  Host buffers of `cap` entries each (any may be NULL):
+ *   stats   uint32 per block: mean R | mean G << 8 | mean B << 16 | edge << 24
+ *   labels  int32 per block: region label = smallest block index of the region
+ *   dblk    uint8 per block: region depth
+ * *gw, *gh receive the block grid (row-major, gw blocks per row).  Returns
+ * PSTEREO_E_INVALID if cap < gw*gh or no generated-depth call was made.
+ */
+int pstereo_debug_blocks(pstereo_ctx *ctx, uint32_t *stats, int32_t *labels,
+                         uint8_t *dblk, int cap, int *gw, int *gh);
+
+/*
+ * Kernel timing.  Each pstereo_synthesize with PSTEREO_PROFILE records HIP
+ * events on its stream around its three kernels (block statistics, region
+ * grouping, row renderer).  This call waits for the recorded events, writes
+ * the summed kernel durations in milliseconds to ms_sum[0..2] and the number
+ * of profiled calls to *count, and clears the record.  If per_call_ms is not
+ * NULL it receives, in call order, up to cap per-call durations (first event
+ * to last event of the call, ms).  At most 4096 calls are kept between
+ * collections; older ones are dropped and not counted.
+ */
+int pstereo_profile_collect(pstereo_ctx *ctx, double ms_sum[3], int *count,
+                            double *per_call_ms, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSTEREO_H */

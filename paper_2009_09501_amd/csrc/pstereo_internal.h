@@ -1,0 +1,48 @@
+// Internal interface between the C ABI layer and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pstereo.h"
+
+namespace pstereo {
+
+// Everything one frame's kernels need, passed by value as a kernel argument.
+struct FrameDesc {
+    const uint8_t* frame;    // RGB24 [h][w][3]
+    uint8_t* out_l;          // RGB24 outputs, any may be null
+    uint8_t* out_r;
+    uint8_t* out_a;
+    const uint8_t* depth_in; // external depth map (u8 [h][w]) or null
+    uint8_t* out_df;         // optional filtered-depth dump
+    uint8_t* out_d0;         // optional raw-depth dump
+    uint32_t* stats;         // per block: mean R | G << 8 | B << 16 | edge << 24
+    uint2* binfo;            // per block: {stats, region depth}
+    int32_t* labels;         // per block: region label
+    int w, h;
+    int K, gw, gh;           // depth block size and grid
+    int B, T, g, tau, r;     // method parameters
+    int aligned;             // w % 4 == 0 and every RGB24 pointer 4-byte aligned
+};
+
+// Launch shape of the row renderer for one frame size.
+struct RenderShape {
+    int threads;        // workgroup size (multiple of 64, <= 1024)
+    int quads;          // quads (4 px) per thread per row: 1, 2 or 4
+    int rows_per_band;  // image rows per workgroup
+    int bands;          // number of bands = ceil(h / rows_per_band)
+    int grid;           // launched workgroups (bands rounded up to a multiple of 8)
+    size_t lds_bytes;   // dynamic LDS per workgroup
+};
+
+// Host-side launch helpers (pstereo_kernels.hip).  Each returns hipSuccess or
+// the launch error.
+size_t render_lds_bytes(int w, int r, int threads, int quads);
+bool render_shape(int w, int h, int r, int rows_per_band, RenderShape* out);
+hipError_t launch_blockstats(const FrameDesc& f, hipStream_t s);
+hipError_t launch_regions(const FrameDesc& f, hipStream_t s);
+hipError_t launch_render(const FrameDesc& f, const RenderShape& rs, hipStream_t s);
+hipError_t prepare_kernels(int device);
+
+}  // namespace pstereo

@@ -1,0 +1,210 @@
+"""ctypes binding of libpstereo.so (the C ABI declared in include/pstereo.h).
+
+Argument marshalling only: every step of the pipeline runs in the library's
+HIP kernels.  Functions carry the C names; tensors may be passed wherever the
+C ABI takes a device pointer (their ``data_ptr()`` is used).  PyTorch serves
+for device memory and streams.  If the library is not built this module
+raises on first use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpstereo.so")
+
+PSTEREO_OK = 0
+PSTEREO_E_INVALID = -1
+PSTEREO_E_NOMEM = -2
+PSTEREO_E_DEVICE = -3
+PSTEREO_E_ALIAS = -4
+PSTEREO_E_UNSUPPORTED = -5
+PSTEREO_E_BUSY = -6
+
+PSTEREO_DEPTH_EXTERNAL = 0x1
+PSTEREO_SYNC = 0x2
+PSTEREO_PROFILE = 0x4
+
+PSTEREO_MAX_BLOCKS = 32768
+
+_CODES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_ALIAS",
+          -5: "E_UNSUPPORTED", -6: "E_BUSY"}
+
+# Every symbol the header declares; tests check the library exports them all.
+EXPORTED = [
+    "pstereo_params_init", "pstereo_create", "pstereo_synthesize", "pstereo_destroy",
+    "pstereo_last_error", "pstereo_debug_blocks", "pstereo_profile_collect",
+]
+
+
+class PstereoParams(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("max_disparity", ctypes.c_int32),
+        ("depth_threshold", ctypes.c_int32),
+        ("block_size", ctypes.c_int32),
+        ("edge_thresh", ctypes.c_int32),
+        ("link_thresh", ctypes.c_int32),
+        ("cbf_radius", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("depth_in", ctypes.c_void_p),
+        ("out_depth", ctypes.c_void_p),
+        ("out_depth_raw", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class PstereoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load libpstereo.so from the package directory; raise if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc for gfx950) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ci, cu = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32
+    P = ctypes.POINTER(PstereoParams)
+    lib.pstereo_params_init.argtypes = [P]
+    lib.pstereo_params_init.restype = ci
+    lib.pstereo_create.argtypes = [ctypes.POINTER(vp), ci, ci, ci]
+    lib.pstereo_create.restype = ci
+    lib.pstereo_synthesize.argtypes = [vp, vp, ci, ci, P, vp, vp, vp]
+    lib.pstereo_synthesize.restype = ci
+    lib.pstereo_destroy.argtypes = [vp]
+    lib.pstereo_destroy.restype = ci
+    lib.pstereo_last_error.argtypes = [vp]
+    lib.pstereo_last_error.restype = ctypes.c_char_p
+    lib.pstereo_debug_blocks.argtypes = [vp, vp, vp, vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    lib.pstereo_debug_blocks.restype = ci
+    lib.pstereo_profile_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ci),
+                                            ctypes.POINTER(ctypes.c_double), ci]
+    lib.pstereo_profile_collect.restype = ci
+    _ = cu
+    _lib = lib
+    return lib
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _check(rc: int, ctx=None):
+    if rc != PSTEREO_OK:
+        msg = load_library().pstereo_last_error(ctx)
+        raise PstereoError(rc, msg.decode() if msg else "")
+    return rc
+
+
+# ----------------------------------------------------------------- C names
+def pstereo_params_init(**overrides) -> PstereoParams:
+    """Defaults of the C library, then keyword overrides (field names)."""
+    p = PstereoParams()
+    _check(load_library().pstereo_params_init(ctypes.byref(p)))
+    for k, v in overrides.items():
+        if k in ("depth_in", "out_depth", "out_depth_raw", "stream"):
+            v = _ptr(v) if k != "stream" else v
+        setattr(p, k, v)
+    return p
+
+
+def pstereo_create(device: int, max_w: int, max_h: int) -> int:
+    h = ctypes.c_void_p()
+    _check(load_library().pstereo_create(ctypes.byref(h), device, max_w, max_h), None)
+    return h.value
+
+
+def pstereo_synthesize(ctx: int, frame, w: int, h: int, params: Optional[PstereoParams],
+                       out_left, out_right, out_anaglyph, check: bool = True) -> int:
+    rc = load_library().pstereo_synthesize(
+        ctx, _ptr(frame), w, h, ctypes.byref(params) if params is not None else None,
+        _ptr(out_left), _ptr(out_right), _ptr(out_anaglyph))
+    return _check(rc, ctx) if check else rc
+
+
+def pstereo_destroy(ctx: int) -> int:
+    return load_library().pstereo_destroy(ctx)
+
+
+def pstereo_last_error(ctx: Optional[int]) -> str:
+    m = load_library().pstereo_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def pstereo_debug_blocks(ctx: int, cap: int = PSTEREO_MAX_BLOCKS):
+    """(stats uint32, labels int32, dblk uint8) numpy arrays shaped [gh, gw]."""
+    import numpy as np
+    st = np.empty(cap, np.uint32)
+    lab = np.empty(cap, np.int32)
+    db = np.empty(cap, np.uint8)
+    gw, gh = ctypes.c_int(), ctypes.c_int()
+    _check(load_library().pstereo_debug_blocks(
+        ctx, st.ctypes.data, lab.ctypes.data, db.ctypes.data, cap, ctypes.byref(gw), ctypes.byref(gh)), ctx)
+    n = gw.value * gh.value
+    shape = (gh.value, gw.value)
+    return st[:n].reshape(shape), lab[:n].reshape(shape), db[:n].reshape(shape)
+
+
+def pstereo_profile_collect(ctx: int, cap: int = 4096):
+    """(ms per kernel [blockstats, regions, render] summed, number of calls,
+    list of per-call durations in ms)."""
+    arr = (ctypes.c_double * 3)()
+    per = (ctypes.c_double * cap)()
+    n = ctypes.c_int()
+    _check(load_library().pstereo_profile_collect(ctx, arr, ctypes.byref(n), per, cap), ctx)
+    return [arr[0], arr[1], arr[2]], n.value, [per[i] for i in range(min(n.value, cap))]
+
+
+# ------------------------------------------------------- torch convenience
+class Context:
+    """One library context on a GPU; frames and outputs are torch uint8 CUDA
+    tensors [h, w, 3].  Work goes on torch's current stream unless a stream
+    is given."""
+
+    def __init__(self, device: int = 0, max_w: int = 7680, max_h: int = 4320):
+        self.device = device
+        self.handle = pstereo_create(device, max_w, max_h)
+
+    def close(self):
+        if self.handle:
+            pstereo_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def synthesize(self, frame, out=None, stream=None, depth=None, out_depth=None,
+                   out_depth_raw=None, flags: int = 0, **params):
+        import torch
+        h, w, c = frame.shape
+        assert c == 3 and frame.dtype == torch.uint8 and frame.is_contiguous()
+        if out is None:
+            out = tuple(torch.empty_like(frame) for _ in range(3))
+        if stream is None:
+            stream = torch.cuda.current_stream(frame.device)
+        p = pstereo_params_init(**params)
+        p.flags = flags | (PSTEREO_DEPTH_EXTERNAL if depth is not None else 0)
+        p.depth_in = _ptr(depth)
+        p.out_depth = _ptr(out_depth)
+        p.out_depth_raw = _ptr(out_depth_raw)
+        p.stream = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        pstereo_synthesize(self.handle, frame, w, h, p, *out)
+        return out

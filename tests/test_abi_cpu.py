@@ -1,0 +1,58 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads and exports
+every function include/pstereo.h declares, and the binding's parameter struct
+matches the header's layout."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pstereo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pstereo_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2009_09501_amd.pstereo import LIB_PATH, load_library
+    if not os.path.exists(LIB_PATH):
+        from paper_2009_09501_amd.build import build_library
+        build_library()
+    return load_library()
+
+
+def test_header_declares_core_calls():
+    d = _declared()
+    for name in ("pstereo_create", "pstereo_synthesize", "pstereo_destroy"):
+        assert name in d
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2009_09501_amd.pstereo import EXPORTED
+    declared = _declared()
+    assert sorted(EXPORTED) == declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_params_struct_layout(lib):
+    from paper_2009_09501_amd.pstereo import PstereoParams
+    p = PstereoParams()
+    assert lib.pstereo_params_init(ctypes.byref(p)) == 0
+    assert p.struct_size == ctypes.sizeof(PstereoParams)
+    assert (p.max_disparity, p.depth_threshold, p.block_size, p.edge_thresh,
+            p.link_thresh, p.cbf_radius, p.flags) == (-1, 150, 0, 24, 24, 2, 0)
+
+
+def test_null_and_bad_args_without_gpu(lib):
+    """Argument checks that return before touching a device."""
+    assert lib.pstereo_params_init(None) == -1
+    assert lib.pstereo_synthesize(None, None, 1, 1, None, None, None, None) == -1
+    assert lib.pstereo_destroy(None) == 0
+    h = ctypes.c_void_p()
+    assert lib.pstereo_create(ctypes.byref(h), 0, 0, 10) == -1
+    assert b"out of range" in lib.pstereo_last_error(None)

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle.
+
+Every stage is integer, so every comparison is bit-exact: the three output
+images, the raw and filtered depth maps and the per-block statistics, labels
+and region depths.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2009_09501_amd import Context
+    c = Context(0, 7680, 4320)
+    yield c
+    c.close()
+
+
+def _run(ctx, frame, depth=None, **params):
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(np.ascontiguousarray(frame)).to(dev)
+    h, w, _ = frame.shape
+    d0 = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    df = torch.empty((h, w), dtype=torch.uint8, device=dev)
+    dep = torch.from_numpy(np.ascontiguousarray(depth)).to(dev) if depth is not None else None
+    L, R, A = ctx.synthesize(f, depth=dep, out_depth=df, out_depth_raw=d0, **params)
+    torch.cuda.synchronize()
+    return {"L": L.cpu().numpy(), "R": R.cpu().numpy(), "A": A.cpu().numpy(),
+            "D0": d0.cpu().numpy(), "Df": df.cpu().numpy()}
+
+
+def _compare(case, got, ref, blocks=None):
+    for k in ("D0", "Df", "L", "R", "A"):
+        g, w = got[k], getattr(ref, k)
+        if not np.array_equal(g, w):
+            diff = (g != w) if g.ndim == 2 else (g != w).any(-1)
+            ys, xs = np.nonzero(diff)
+            raise AssertionError(f"{case}: {k} differs at {diff.sum()} pixels, first (y={ys[0]}, x={xs[0]})")
+    if blocks is not None:
+        st, lab, db = blocks
+        assert np.array_equal(st, ref.stats), f"{case}: block stats"
+        assert np.array_equal(lab, ref.labels), f"{case}: labels"
+        assert np.array_equal(db, ref.dblk), f"{case}: region depth"
+
+
+def _check(ctx, oracle_mod, frame, B, T=150, K=0, g=24, tau=24, r=2, depth=None, case=""):
+    from paper_2009_09501_amd import pstereo_debug_blocks
+    print(f"case {case}: {frame.shape[1]}x{frame.shape[0]} B={B} T={T} K={K} r={r} "
+          f"ext={depth is not None}", flush=True)
+    got = _run(ctx, frame, depth=depth, max_disparity=B, depth_threshold=T, block_size=K,
+               edge_thresh=g, link_thresh=tau, cbf_radius=r)
+    ref = oracle_mod.synthesize(frame, B, T, K, g, tau, r, depth=depth)
+    blocks = None if depth is not None else pstereo_debug_blocks(ctx.handle)
+    _compare(case, got, ref, blocks)
+
+
+def test_config0_640x360(ctx, oracle_mod):
+    f = synth.gen_frame(1, 640, 360, 12, 4.0)
+    _check(ctx, oracle_mod, f, 12, case="640x360 seed 1")
+
+
+@pytest.mark.parametrize("w,h,seed", [(1920, 1080, 2), (3840, 2160, 3)])
+def test_config1_full_frames(ctx, oracle_mod, w, h, seed):
+    f = synth.gen_frame(seed, w, h, 40, 4.0)
+    _check(ctx, oracle_mod, f, synth.default_disparity(w), case=f"{w}x{h} seed {seed}")
+
+
+def test_8k_frame(ctx, oracle_mod):
+    f = synth.gen_frame(5001, 7680, 4320, 40, 4.0)
+    _check(ctx, oracle_mod, f, 154, case="8k seed 5001")
+
+
+@pytest.mark.parametrize("w,h", [(333, 191), (1, 1), (5, 3), (17, 1), (1, 9), (64, 64), (130, 7),
+                                 (641, 359), (1023, 17), (4097, 11)])
+def test_ragged_sizes(ctx, oracle_mod, w, h):
+    f = synth.gen_frame(w * 7 + h, w, h, 6, 4.0)
+    _check(ctx, oracle_mod, f, min(12, 255), case=f"ragged {w}x{h}")
+
+
+@pytest.mark.parametrize("K", [4, 8, 16, 32, 64])
+@pytest.mark.parametrize("r", [0, 1, 2, 3])
+def test_block_sizes_and_radii(ctx, oracle_mod, K, r):
+    w, h = 400, 240
+    if (-(-w // K)) * (-(-h // K)) > 32768:
+        pytest.skip("too many blocks")
+    f = synth.gen_frame(K * 10 + r, w, h, 16, 4.0)
+    _check(ctx, oracle_mod, f, 20, K=K, r=r, case=f"K={K} r={r}")
+
+
+@pytest.mark.parametrize("B,T", [(0, 150), (1, 150), (77, 150), (255, 150), (12, -1), (12, 0), (12, 255)])
+def test_disparity_parameters(ctx, oracle_mod, B, T):
+    f = synth.gen_frame(B + T + 3, 320, 96, 12, 4.0)
+    _check(ctx, oracle_mod, f, B, T=T, case=f"B={B} T={T}")
+
+
+@pytest.mark.parametrize("g,tau", [(0, 0), (8, 80), (60, 12), (255, 765)])
+def test_cue_thresholds(ctx, oracle_mod, g, tau):
+    f = synth.gen_frame(g + tau, 256, 144, 20, 4.0)
+    _check(ctx, oracle_mod, f, 12, g=g, tau=tau, case=f"g={g} tau={tau}")
+
+
+def test_external_depth_worked_rows(ctx, oracle_mod):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "worked_rows.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, dep, Ls, Rs = [s.strip() for s in line.split("|")]
+        dep = np.array([[int(v) for v in dep.split()]], np.uint8)
+        Ls = [int(v) for v in Ls.split()]
+        Rs = [int(v) for v in Rs.split()]
+        w = dep.shape[1]
+        f = np.zeros((1, w, 3), np.uint8)
+        f[0, :, 0] = np.arange(w) * 10
+        f[0, :, 1] = 255 - np.arange(w) * 10
+        f[0, :, 2] = 7
+        got = _run(ctx, f, depth=dep, max_disparity=12, cbf_radius=0)
+        assert np.array_equal(got["L"][0], f[0, Ls]), name
+        assert np.array_equal(got["R"][0], f[0, Rs]), name
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_external_random_depth(ctx, oracle_mod, seed):
+    rng = np.random.default_rng(seed)
+    f = synth.gen_frame(seed, 517, 203, 10, 4.0)
+    dep = rng.integers(0, 256, (203, 517)).astype(np.uint8)
+    _check(ctx, oracle_mod, f, 40, depth=dep, case=f"external depth seed {seed}")
+
+
+def test_zero_base_identity(ctx):
+    f = synth.gen_frame(9, 640, 360, 12, 4.0)
+    got = _run(ctx, f, max_disparity=0)
+    for k in ("L", "R", "A"):
+        assert np.array_equal(got[k], f)
+
+
+def test_deterministic_repeat(ctx):
+    f = synth.gen_frame(21, 1920, 1080, 40, 4.0)
+    a = _run(ctx, f, max_disparity=38)
+    b = _run(ctx, f, max_disparity=38)
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+
+
+def test_misaligned_buffers(ctx, oracle_mod):
+    """Frame and outputs at odd byte offsets take the bytewise path."""
+    from paper_2009_09501_amd import pstereo_params_init, pstereo_synthesize
+    w, h = 320, 48
+    frame = synth.gen_frame(31, w, h, 8, 4.0)
+    n = w * h * 3
+    dev = torch.device("cuda:0")
+    big = torch.zeros(4 * n + 16, dtype=torch.uint8, device=dev)
+    fsrc = big[1:1 + n]
+    fsrc.copy_(torch.from_numpy(frame.reshape(-1)).to(dev))
+    outs = [big[n + 3 + i * n: 2 * n + 3 + i * n] for i in range(3)]
+    p = pstereo_params_init(max_disparity=12)
+    p.stream = torch.cuda.current_stream().cuda_stream
+    pstereo_synthesize(ctx.handle, fsrc, w, h, p, *outs)
+    torch.cuda.synchronize()
+    ref = oracle_mod.synthesize(frame, 12)
+    for o, want in zip(outs, (ref.L, ref.R, ref.A)):
+        assert np.array_equal(o.cpu().numpy().reshape(h, w, 3), want)
+
+
+def test_error_codes(ctx):
+    from paper_2009_09501_amd import pstereo_params_init, pstereo_synthesize
+    from paper_2009_09501_amd.pstereo import (PSTEREO_E_ALIAS, PSTEREO_E_INVALID,
+                                              PSTEREO_E_UNSUPPORTED)
+    dev = torch.device("cuda:0")
+    w, h = 64, 32
+    f = torch.zeros((h, w, 3), dtype=torch.uint8, device=dev)
+    o = [torch.empty_like(f) for _ in range(3)]
+    hp = np.zeros((h, w, 3), np.uint8)
+    p = pstereo_params_init()
+    # host pointer
+    assert pstereo_synthesize(ctx.handle, hp.ctypes.data, w, h, p, *o, check=False) == PSTEREO_E_INVALID
+    # outputs overlapping
+    assert pstereo_synthesize(ctx.handle, f, w, h, p, o[0], o[0], o[2], check=False) == PSTEREO_E_ALIAS
+    assert pstereo_synthesize(ctx.handle, f, w, h, p, f, o[1], o[2], check=False) == PSTEREO_E_ALIAS
+    # sizes and parameter ranges
+    assert pstereo_synthesize(ctx.handle, f, 0, h, p, *o, check=False) == PSTEREO_E_INVALID
+    assert pstereo_synthesize(ctx.handle, f, 8000, h, p, *o, check=False) == PSTEREO_E_INVALID
+    for field, val in (("max_disparity", 256), ("depth_threshold", -2), ("cbf_radius", 4),
+                       ("block_size", 12), ("edge_thresh", 300), ("link_thresh", 766)):
+        q = pstereo_params_init(**{field: val})
+        assert pstereo_synthesize(ctx.handle, f, w, h, q, *o, check=False) == PSTEREO_E_INVALID, field
+    q = pstereo_params_init()
+    q.struct_size = 4
+    assert pstereo_synthesize(ctx.handle, f, w, h, q, *o, check=False) == PSTEREO_E_INVALID
+    # too many blocks for explicit K
+    q = pstereo_params_init(block_size=4)
+    big = torch.zeros((1080, 1920, 3), dtype=torch.uint8, device=dev)
+    ob = [torch.empty_like(big) for _ in range(3)]
+    assert pstereo_synthesize(ctx.handle, big, 1920, 1080, q, *ob, check=False) == PSTEREO_E_INVALID
+    # the context still works after errors
+    pstereo_synthesize(ctx.handle, f, w, h, p, *o)
+    torch.cuda.synchronize()
+    _ = PSTEREO_E_UNSUPPORTED
