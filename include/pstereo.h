@@ -110,8 +110,8 @@ int pstereo_create(pstereo_ctx **out, int device, int max_w, int max_h);
  *   out_right    device RGB24 [h][w][3] (may be NULL to skip)
  *   out_anaglyph device RGB24 [h][w][3] (may be NULL to skip)
  * Outputs must not overlap each other, the frame or the depth buffers
- * (PSTEREO_E_ALIAS).  Returns PSTEREO_E_UNSUPPORTED when the frame is too
- * wide for the row renderer's LDS budget (about 8900 px at r = 2). */
+ * (PSTEREO_E_ALIAS).  Returns PSTEREO_E_UNSUPPORTED when the frame is wider
+ * than the warp kernel's row buffers allow (16384 px). */
 int pstereo_synthesize(pstereo_ctx *ctx, const uint8_t *frame, int w, int h,
                        const pstereo_params *p, uint8_t *out_left,
                        uint8_t *out_right, uint8_t *out_anaglyph);
@@ -139,15 +139,15 @@ int pstereo_debug_blocks(pstereo_ctx *ctx, uint32_t *stats, int32_t *labels,
 
 /*
  * Kernel timing.  Each pstereo_synthesize with PSTEREO_PROFILE records HIP
- * events on its stream around its three kernels (block statistics, region
- * grouping, row renderer).  This call waits for the recorded events, writes
- * the summed kernel durations in milliseconds to ms_sum[0..2] and the number
+ * events on its stream around its four kernels (block statistics, region
+ * grouping, depth filter, warp).  This call waits for the recorded events,
+ * writes the summed kernel durations in milliseconds to ms_sum[0..3] and the number
  * of profiled calls to *count, and clears the record.  If per_call_ms is not
  * NULL it receives, in call order, up to cap per-call durations (first event
  * to last event of the call, ms).  At most 4096 calls are kept between
  * collections; older ones are dropped and not counted.
  */
-int pstereo_profile_collect(pstereo_ctx *ctx, double ms_sum[3], int *count,
+int pstereo_profile_collect(pstereo_ctx *ctx, double ms_sum[4], int *count,
                             double *per_call_ms, int cap);
 
 #ifdef __cplusplus

@@ -12,12 +12,12 @@
 #include "pstereo_internal.h"
 
 using pstereo::FrameDesc;
-using pstereo::RenderShape;
+using pstereo::WarpShape;
 
 namespace {
 
 constexpr int kProfSets = 4096;
-constexpr int kProfEvents = 4;  // before blockstats, after blockstats, after regions, after render
+constexpr int kProfEvents = 5;  // before blockstats, after blockstats, after regions, after cbf, after warp
 
 thread_local std::string g_create_error;
 
@@ -30,6 +30,7 @@ struct pstereo_ctx {
     uint32_t* d_stats = nullptr;
     uint2* d_binfo = nullptr;
     int32_t* d_labels = nullptr;
+    uint8_t* d_df = nullptr;  // filtered depth, max_w * max_h bytes
     std::string err;
     // last generated-depth call, for pstereo_debug_blocks
     bool have_blocks = false;
@@ -125,7 +126,8 @@ int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
     c->max_w = max_w;
     c->max_h = max_h;
     hipError_t e = hipSetDevice(device);
-    if (e == hipSuccess) e = pstereo::prepare_kernels(device);
+    if (e == hipSuccess) e = pstereo::prepare_depth_kernels();
+    if (e == hipSuccess) e = pstereo::prepare_render_kernels();
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete c;
@@ -134,7 +136,8 @@ int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
     const size_t nb = PSTEREO_MAX_BLOCKS;
     if (hipMalloc(&c->d_stats, nb * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_binfo, nb * sizeof(uint2)) != hipSuccess ||
-        hipMalloc(&c->d_labels, nb * sizeof(int32_t)) != hipSuccess) {
+        hipMalloc(&c->d_labels, nb * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->d_df, (size_t)max_w * max_h) != hipSuccess) {
         (void)hipGetLastError();
         pstereo_destroy(c);
         return fail(nullptr, PSTEREO_E_NOMEM, "scratch allocation failed");
@@ -151,6 +154,7 @@ int pstereo_destroy(pstereo_ctx* c) {
     (void)hipFree(c->d_stats);
     (void)hipFree(c->d_binfo);
     (void)hipFree(c->d_labels);
+    (void)hipFree(c->d_df);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     (void)hipGetLastError();
     delete c;
@@ -211,10 +215,9 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
             if (overlap(rout[i], rout[j])) return fail(c, PSTEREO_E_ALIAS, "%s overlaps %s", rout[i].name, rout[j].name);
     }
 
-    RenderShape rs;
-    if (!pstereo::render_shape(w, h, p.cbf_radius, 0, &rs))
-        return fail(c, PSTEREO_E_UNSUPPORTED, "width %d exceeds the row renderer's LDS budget at r=%d", w,
-                    p.cbf_radius);
+    WarpShape ws;
+    if (!pstereo::warp_shape(w, &ws))
+        return fail(c, PSTEREO_E_UNSUPPORTED, "width %d exceeds the warp kernel's LDS budget", w);
 
     FrameDesc f{};
     f.frame = frame;
@@ -227,6 +230,7 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
     f.stats = c->d_stats;
     f.binfo = c->d_binfo;
     f.labels = c->d_labels;
+    f.df = c->d_df;
     f.w = w;
     f.h = h;
     f.K = K;
@@ -272,9 +276,12 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
         (void)hipEventRecord(ev[1], s);
         (void)hipEventRecord(ev[2], s);
     }
-    if ((e = pstereo::launch_render(f, rs, s)) != hipSuccess)
-        return fail(c, PSTEREO_E_DEVICE, "row renderer launch: %s", hipGetErrorString(e));
+    if ((e = pstereo::launch_cbf(f, s)) != hipSuccess)
+        return fail(c, PSTEREO_E_DEVICE, "depth filter launch: %s", hipGetErrorString(e));
     if (prof) (void)hipEventRecord(ev[3], s);
+    if ((e = pstereo::launch_warp(f, ws, s)) != hipSuccess)
+        return fail(c, PSTEREO_E_DEVICE, "warp launch: %s", hipGetErrorString(e));
+    if (prof) (void)hipEventRecord(ev[4], s);
     if (!ext) {
         c->have_blocks = true;
         c->last_gw = gw;
@@ -312,10 +319,10 @@ int pstereo_debug_blocks(pstereo_ctx* c, uint32_t* stats, int32_t* labels, uint8
     return PSTEREO_OK;
 }
 
-int pstereo_profile_collect(pstereo_ctx* c, double ms_sum[3], int* count, double* per_call_ms, int cap) {
+int pstereo_profile_collect(pstereo_ctx* c, double ms_sum[4], int* count, double* per_call_ms, int cap) {
     if (!c || !ms_sum || !count) return PSTEREO_E_INVALID;
     c->err.clear();
-    ms_sum[0] = ms_sum[1] = ms_sum[2] = 0.0;
+    ms_sum[0] = ms_sum[1] = ms_sum[2] = ms_sum[3] = 0.0;
     *count = 0;
     if (c->prof_head == 0) return PSTEREO_OK;
     (void)hipSetDevice(c->device);
@@ -323,20 +330,22 @@ int pstereo_profile_collect(pstereo_ctx* c, double ms_sum[3], int* count, double
     for (long long k = c->prof_head - n; k < c->prof_head; ++k) {
         const int slot = (int)(k % kProfSets);
         hipEvent_t* ev = &c->prof_ev[(size_t)slot * kProfEvents];
-        hipError_t e = hipEventSynchronize(ev[3]);
+        hipError_t e = hipEventSynchronize(ev[4]);
         if (e != hipSuccess) return fail(c, PSTEREO_E_DEVICE, "event synchronize: %s", hipGetErrorString(e));
-        float a = 0.f, b = 0.f, d = 0.f;
+        float a = 0.f, b = 0.f, d = 0.f, q = 0.f;
         if (c->prof_has_depth[slot]) {
             (void)hipEventElapsedTime(&a, ev[0], ev[1]);
             (void)hipEventElapsedTime(&b, ev[1], ev[2]);
         }
         (void)hipEventElapsedTime(&d, ev[2], ev[3]);
+        (void)hipEventElapsedTime(&q, ev[3], ev[4]);
         ms_sum[0] += a;
         ms_sum[1] += b;
         ms_sum[2] += d;
+        ms_sum[3] += q;
         if (per_call_ms && *count < cap) {
             float tot = 0.f;
-            (void)hipEventElapsedTime(&tot, ev[0], ev[3]);
+            (void)hipEventElapsedTime(&tot, ev[0], ev[4]);
             per_call_ms[*count] = tot;
         }
         ++*count;

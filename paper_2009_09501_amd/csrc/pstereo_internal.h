@@ -20,29 +20,29 @@ struct FrameDesc {
     uint32_t* stats;         // per block: mean R | G << 8 | B << 16 | edge << 24
     uint2* binfo;            // per block: {stats, region depth}
     int32_t* labels;         // per block: region label
+    uint8_t* df;             // filtered depth scratch, u8 [h][w] (4-byte aligned)
     int w, h;
     int K, gw, gh;           // depth block size and grid
     int B, T, g, tau, r;     // method parameters
     int aligned;             // w % 4 == 0 and every RGB24 pointer 4-byte aligned
 };
 
-// Launch shape of the row renderer for one frame size.
-struct RenderShape {
+// Launch shape of the warp kernel (one image row per workgroup).
+struct WarpShape {
     int threads;        // workgroup size (multiple of 64, <= 1024)
-    int quads;          // quads (4 px) per thread per row: 1, 2 or 4
-    int rows_per_band;  // image rows per workgroup
-    int bands;          // number of bands = ceil(h / rows_per_band)
-    int grid;           // launched workgroups (bands rounded up to a multiple of 8)
+    int quads;          // quads (4 px) per lane: 1, 2 or 4
     size_t lds_bytes;   // dynamic LDS per workgroup
 };
 
 // Host-side launch helpers (pstereo_kernels.hip).  Each returns hipSuccess or
 // the launch error.
-size_t render_lds_bytes(int w, int r, int threads, int quads);
-bool render_shape(int w, int h, int r, int rows_per_band, RenderShape* out);
+bool warp_shape(int w, WarpShape* out);
 hipError_t launch_blockstats(const FrameDesc& f, hipStream_t s);
 hipError_t launch_regions(const FrameDesc& f, hipStream_t s);
-hipError_t launch_render(const FrameDesc& f, const RenderShape& rs, hipStream_t s);
-hipError_t prepare_kernels(int device);
+hipError_t launch_cbf(const FrameDesc& f, hipStream_t s);
+hipError_t launch_warp(const FrameDesc& f, const WarpShape& ws, hipStream_t s);
+size_t regions_lds_bytes(int nb);
+hipError_t prepare_depth_kernels();
+hipError_t prepare_render_kernels();
 
 }  // namespace pstereo

@@ -161,13 +161,13 @@ def pstereo_debug_blocks(ctx: int, cap: int = PSTEREO_MAX_BLOCKS):
 
 
 def pstereo_profile_collect(ctx: int, cap: int = 4096):
-    """(ms per kernel [blockstats, regions, render] summed, number of calls,
+    """(ms per kernel [blockstats, regions, cbf, warp] summed, number of calls,
     list of per-call durations in ms)."""
-    arr = (ctypes.c_double * 3)()
+    arr = (ctypes.c_double * 4)()
     per = (ctypes.c_double * cap)()
     n = ctypes.c_int()
     _check(load_library().pstereo_profile_collect(ctx, arr, ctypes.byref(n), per, cap), ctx)
-    return [arr[0], arr[1], arr[2]], n.value, [per[i] for i in range(min(n.value, cap))]
+    return [arr[i] for i in range(4)], n.value, [per[i] for i in range(min(n.value, cap))]
 
 
 # ------------------------------------------------------- torch convenience
