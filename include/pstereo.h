@@ -150,6 +150,69 @@ int pstereo_debug_blocks(pstereo_ctx *ctx, uint32_t *stats, int32_t *labels,
 int pstereo_profile_collect(pstereo_ctx *ctx, double ms_sum[4], int *count,
                             double *per_call_ms, int cap);
 
+/*
+ * Video: the frame's launch sequence captured once as a HIP graph and
+ * replayed per frame (the paper converts video frame by frame, Section 5;
+ * there is no state between frames).  pstereo_video_begin fixes the frame
+ * size and parameters (generated depth only: no PSTEREO_DEPTH_EXTERNAL, no
+ * depth dumps); the graph runs on p->stream (NULL = context stream).
+ * pstereo_video_frame validates the buffers like pstereo_synthesize, writes
+ * their pointers into the graph's kernel arguments and launches it; it may
+ * wait for the replay made four frames earlier.  Frames on one video run in
+ * order on its stream and share the context's scratch, so a context drives
+ * one video (or plain calls on the same stream) at a time.
+ * pstereo_video_end waits for the stream and frees the graphs.
+ * Errors as for pstereo_synthesize; PSTEREO_E_UNSUPPORTED for the excluded
+ * parameters.
+ */
+typedef struct pstereo_video pstereo_video;
+int pstereo_video_begin(pstereo_ctx *ctx, int w, int h, const pstereo_params *p, pstereo_video **out);
+int pstereo_video_frame(pstereo_video *v, const uint8_t *frame, uint8_t *out_left, uint8_t *out_right,
+                        uint8_t *out_anaglyph);
+int pstereo_video_end(pstereo_video *v);
+
+/*
+ * Batched form: many frames of uneven size through ONE persistent, fused
+ * kernel launch.  Each of its workgroups (one per compute unit) claims
+ * tasks in a dependency order (per frame: block statistics, region grouping,
+ * depth filter, warp) from a device counter, so the region grouping of one
+ * frame overlaps the streaming work of the others.  Every frame's output is
+ * byte-identical to pstereo_synthesize with the same parameters.
+ *
+ * pstereo_batch_create: a batch object on ctx's device for up to max_jobs
+ *   frames of max_pixels pixels in total; allocates all per-frame scratch
+ *   (about 0.5 MiB per job plus one byte per pixel) and pinned staging.
+ * pstereo_batch_prepare: validates the jobs and uploads the task tables on
+ *   p->stream (NULL = context stream).  Shared parameters come from p; each
+ *   job has its own max_disparity (-1 = round(0.02 w)).  Requirements:
+ *   generated depth (no PSTEREO_DEPTH_EXTERNAL, no depth dumps), widths a
+ *   multiple of 4 and at most 16384, 4-byte aligned device buffers, outputs
+ *   disjoint from every frame and from each other (PSTEREO_E_ALIAS).
+ * pstereo_batch_launch: enqueues the prepared batch on `stream` (a
+ *   hipStream_t; NULL = the prepare stream): a counter-reset kernel and the
+ *   persistent kernel; no copies and no allocation, so it can be captured
+ *   into a HIP graph and replayed.  A prepared batch can be launched any
+ *   number of times; launches of one batch object must not overlap.
+ * pstereo_batch_run: prepare + launch (+ wait if PSTEREO_SYNC).
+ * pstereo_batch_last_error: message of the last failure on the batch.
+ */
+typedef struct pstereo_job {
+    const uint8_t *frame;   /* device RGB24 [h][w][3] */
+    int32_t w, h;
+    uint8_t *out_left;      /* device RGB24 [h][w][3] or NULL */
+    uint8_t *out_right;
+    uint8_t *out_anaglyph;
+    int32_t max_disparity;  /* -1 = round(0.02 w) */
+} pstereo_job;
+
+typedef struct pstereo_batch pstereo_batch;
+int pstereo_batch_create(pstereo_ctx *ctx, int max_jobs, int64_t max_pixels, pstereo_batch **out);
+int pstereo_batch_prepare(pstereo_batch *b, const pstereo_job *jobs, int n, const pstereo_params *p);
+int pstereo_batch_launch(pstereo_batch *b, void *stream);
+int pstereo_batch_run(pstereo_batch *b, const pstereo_job *jobs, int n, const pstereo_params *p);
+int pstereo_batch_destroy(pstereo_batch *b);
+const char *pstereo_batch_last_error(const pstereo_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

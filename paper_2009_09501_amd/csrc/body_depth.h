@@ -1,0 +1,451 @@
+// Device bodies of the depth-map stages: block statistics and region grouping
+// (used by the per-frame kernels and by the persistent batch kernel).
+//
+// The depth map follows the paper's conversion scheme (Section 3, Fig. 1:
+// the depth map is the first of the six components; Section 4: it is the
+// "iterative" stage) built from block colour and edge cues (Section 2 and
+// Table 1: edge / region-boundary information, block processing).  The exact
+// cues, thresholds and region-depth rule are the library's readings.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace pstereo {
+
+// ---------------------------------------------------------------------------
+// block statistics: per K x K block, rounded mean colour and edge flag.
+//
+// Tiles of 64 px x TH rows (TH = max(16, K)), 256 lanes: lane = one quad
+// (4 px) of one row, so K | 64 and K | TH keep every block inside one tile.
+// Horizontal luma steps use the next pixel's bytes; vertical steps go through
+// an LDS tile of packed luma that also holds the first row below the tile.
+// The lanes of one block reduce by cross-lane xor within the wave, then one
+// LDS atomic per wave and block.
+template <int K>
+struct BsTile {
+    static constexpr int TH = K > 16 ? K : 16;  // tile rows
+    static constexpr int RPT = TH / 16;         // rows per lane
+    static constexpr int BC = 64 / K;           // block columns per tile
+    static constexpr int BR = TH / K;           // block rows per tile
+    static constexpr int QB = K / 4;            // quads per block row
+    static constexpr int kLdsWords = (TH + 1) * 16 + BC * BR * 4;
+};
+
+// One 64 x TH tile (tile_x, tile_y) on 256 lanes t = 0..255 (a multiple of
+// four whole waves).  lds: BsTile<K>::kLdsWords words.  Inactive lanes groups
+// (active == false) do no memory work but pass the same two barriers.
+template <int K, bool ALIGNED>
+__device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile_y, int t, uint32_t* lds,
+                                        bool active) {
+    constexpr int TH = BsTile<K>::TH, RPT = BsTile<K>::RPT, BC = BsTile<K>::BC, BR = BsTile<K>::BR;
+    constexpr int QB = BsTile<K>::QB;
+    uint32_t* ytile = lds;
+    uint32_t* acc = lds + (TH + 1) * 16;
+    const int W = f.w, H = active ? f.h : 0;
+    const int lane = t & 63, wave = t >> 6;
+    const int qx = t & 15, tr = t >> 4;
+    const int tx0 = tile_x * 64, ty0 = tile_y * TH;
+    const int x0 = tx0 + 4 * qx;
+    const int n = min(4, W - x0);
+    for (int i = t; i < BC * BR * 4; i += 256) acc[i] = 0;
+
+    uint32_t sr = 0, sg = 0, sb = 0;
+    int edge = 0;
+    uint32_t yq[RPT];  // packed luma bytes of the lane's quad, one word per row
+    const uint32_t g = (uint32_t)f.g;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int y = ty0 + tr + 16 * k;
+        yq[k] = 0;
+        if (y < H && x0 < W) {
+            const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
+            if (ALIGNED) {
+                // four pixels = three dwords; sums and luma by byte dot products
+                const uint3 v = *reinterpret_cast<const uint3*>(p);
+                sr = __builtin_amdgcn_udot4(v.x, 0x01000001u, sr, false);
+                sr = __builtin_amdgcn_udot4(v.y, 0x00010000u, sr, false);
+                sr = __builtin_amdgcn_udot4(v.z, 0x00000100u, sr, false);
+                sg = __builtin_amdgcn_udot4(v.x, 0x00000100u, sg, false);
+                sg = __builtin_amdgcn_udot4(v.y, 0x01000001u, sg, false);
+                sg = __builtin_amdgcn_udot4(v.z, 0x00010000u, sg, false);
+                sb = __builtin_amdgcn_udot4(v.x, 0x00010000u, sb, false);
+                sb = __builtin_amdgcn_udot4(v.y, 0x00000100u, sb, false);
+                sb = __builtin_amdgcn_udot4(v.z, 0x01000001u, sb, false);
+                constexpr uint32_t wlo = 77u | (150u << 8) | (29u << 16);
+                const uint32_t Y0 = __builtin_amdgcn_udot4(v.x, wlo, 128u, false) >> 8;
+                const uint32_t Y1 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(v.y, v.x, 3), wlo, 128u, false) >> 8;
+                const uint32_t Y2 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(v.z, v.y, 2), wlo, 128u, false) >> 8;
+                const uint32_t Y3 = __builtin_amdgcn_udot4(v.z, wlo << 8, 128u, false) >> 8;
+                uint32_t Yn = Y3;  // no step past the last column
+                if (x0 + 4 < W) {
+                    const uint32_t nx = *reinterpret_cast<const uint32_t*>(p + 12);
+                    Yn = __builtin_amdgcn_udot4(nx, wlo, 128u, false) >> 8;
+                }
+                const uint32_t hmax = max(max(__builtin_amdgcn_sad_u16(Y1, Y0, 0u), __builtin_amdgcn_sad_u16(Y2, Y1, 0u)),
+                                          max(__builtin_amdgcn_sad_u16(Y3, Y2, 0u), __builtin_amdgcn_sad_u16(Yn, Y3, 0u)));
+                if (hmax > g) edge = 1;
+                yq[k] = Y0 | (Y1 << 8) | (Y2 << 16) | (Y3 << 24);
+            } else {
+                int r[4], gg[4], b[4], Y[4];
+                load_quad<false>(p, n, r, gg, b);
+                int ynext = 0;
+                if (x0 + 4 < W) ynext = luma(p[12], p[13], p[14]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) Y[j] = luma(r[j], gg[j], b[j]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (j < n) {
+                        sr += r[j]; sg += gg[j]; sb += b[j];
+                        yq[k] |= (uint32_t)Y[j] << (8 * j);
+                        if (x0 + j + 1 < W && iabs((j < 3 ? Y[j + 1] : ynext) - Y[j]) > f.g) edge = 1;
+                    }
+                }
+            }
+        }
+        ytile[(tr + 16 * k) * 16 + qx] = yq[k];
+    }
+    if (tr == 0) {
+        // the first row below the tile, for the vertical steps of its last row
+        const int y = ty0 + TH;
+        uint32_t v = 0;
+        if (y < H && x0 < W) {
+            int r[4], gg[4], b[4];
+            load_quad<ALIGNED>(f.frame + ((size_t)y * W + x0) * 3, n, r, gg, b);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) if (j < n) v |= (uint32_t)luma(r[j], gg[j], b[j]) << (8 * j);
+        }
+        ytile[TH * 16 + qx] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int y = ty0 + tr + 16 * k;
+        if (y + 1 < H && x0 < W) {
+            const uint32_t below = ytile[(tr + 16 * k + 1) * 16 + qx];
+            uint32_t vmax = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j < n) vmax = max(vmax, __builtin_amdgcn_sad_u16((below >> (8 * j)) & 255u, (yq[k] >> (8 * j)) & 255u, 0u));
+            if (vmax > g) edge = 1;
+        }
+    }
+    // combine the lanes of one block: quads of a block row, and the four rows
+    // a wave covers (all inside one block row since K >= 4)
+#pragma unroll
+    for (int o = 1; o < QB && o < 16; o <<= 1) {
+        sr += __shfl_xor(sr, o); sg += __shfl_xor(sg, o); sb += __shfl_xor(sb, o); edge |= __shfl_xor(edge, o);
+    }
+#pragma unroll
+    for (int o = 16; o < 64; o <<= 1) {
+        sr += __shfl_xor(sr, o); sg += __shfl_xor(sg, o); sb += __shfl_xor(sb, o); edge |= __shfl_xor(edge, o);
+    }
+    if (lane < 16 && (qx % QB) == 0) {
+        const int blk = (qx / QB) + BC * ((4 * wave) / K % BR);
+        atomicAdd(&acc[4 * blk + 0], sr);
+        atomicAdd(&acc[4 * blk + 1], sg);
+        atomicAdd(&acc[4 * blk + 2], sb);
+        if (edge) atomicOr(&acc[4 * blk + 3], 1u);
+    }
+    __syncthreads();
+    for (int i = t; i < BC * BR; i += 256) {
+        const int bx = tile_x * BC + i % BC, by = tile_y * BR + i / BC;
+        if (active && bx < f.gw && by < f.gh) {
+            const uint32_t cnt = (uint32_t)((min(bx * K + K, W) - bx * K) * (min(by * K + K, H) - by * K));
+            const uint32_t mr = (acc[4 * i + 0] + cnt / 2) / cnt;
+            const uint32_t mg = (acc[4 * i + 1] + cnt / 2) / cnt;
+            const uint32_t mb = (acc[4 * i + 2] + cnt / 2) / cnt;
+            f.stats[by * f.gw + bx] = mr | (mg << 8) | (mb << 16) | (acc[4 * i + 3] << 24);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// region grouping, one workgroup of 1024 lanes per frame.
+//
+// Links join right / down neighbours that are both non-edge blocks and whose
+// mean colours differ by at most tau (sum of absolute channel differences).
+// A region is a connected component of the link graph; its label is its
+// smallest block index.  Lane t owns the 32 contiguous blocks [32t, 32t+32).
+//
+//  1. link and edge bits of every block into LDS bitmaps;
+//  2. row segments (maximal runs of right-linked blocks): a block-wide prefix
+//     max of segment starts gives each block its segment; the parent array
+//     starts as one star per segment;
+//  3. lock-free union-find over the down links, only where the pair of
+//     segments changes along the row; roots hook by a fixed pseudo-random
+//     priority, so trees stay shallow whatever the order of the unions;
+//  4. the smallest block index of every tree (atomic minimum at its root) is
+//     the label; the parent array is then reused as the per-label block
+//     count / background key and as the per-label lowest block row.
+constexpr int kRegionThreads = 1024;
+constexpr int kRegionPer = PSTEREO_MAX_BLOCKS / kRegionThreads;  // 32 blocks per lane
+
+__device__ __forceinline__ uint32_t lds_load(const uint32_t* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
+__device__ __forceinline__ void lds_store(uint32_t* p, uint32_t v) { __atomic_store_n(p, v, __ATOMIC_RELAXED); }
+
+// Bijective 32-bit mix: distinct blocks get distinct hooking priorities.
+__device__ __forceinline__ uint32_t hook_prio(uint32_t x) {
+    x *= 0x9E3779B1u;
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    return x;
+}
+
+__device__ __forceinline__ int mean_l1(uint32_t s, uint32_t n) {
+    return iabs((int)(s & 255) - (int)(n & 255)) + iabs((int)((s >> 8) & 255) - (int)((n >> 8) & 255)) +
+           iabs((int)((s >> 16) & 255) - (int)((n >> 16) & 255));
+}
+
+// LDS index of block b in the parent array: one pad word every 32 blocks, so
+// the 64 lanes of a wave, each at its own run of 32 blocks, hit 64 distinct
+// banks instead of one.
+__device__ __forceinline__ uint32_t pidx(uint32_t b) { return b + (b >> 5); }
+
+__device__ __forceinline__ uint32_t uf_find_s(uint32_t* parent, uint32_t x) {
+    while (true) {
+        const uint32_t p = lds_load(&parent[pidx(x)]);
+        if (p == x) return x;
+        const uint32_t gp = lds_load(&parent[pidx(p)]);
+        if (gp != p) lds_store(&parent[pidx(x)], gp);
+        x = gp;
+    }
+}
+
+__device__ __forceinline__ void uf_unite_s(uint32_t* parent, uint32_t a, uint32_t b) {
+    while (true) {
+        a = uf_find_s(parent, a);
+        b = uf_find_s(parent, b);
+        if (a == b) return;
+        if (hook_prio(a) > hook_prio(b)) { const uint32_t t = a; a = b; b = t; }
+        if (atomicCAS(&parent[pidx(a)], a, b) == a) return;
+    }
+}
+
+// Region grouping of one frame on a whole 1024-lane workgroup; lds: the
+// regions_lds_bytes(gw * gh) bytes of dynamic LDS.
+__device__ __forceinline__ void regions_body(const FrameDesc& f, uint32_t* lds) {
+    const int gw = f.gw, gh = f.gh, nb = gw * gh;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int NW = kRegionThreads / 64;
+    uint32_t* parent = lds;                           // pidx(nb) words
+    uint32_t* lrb = parent + pidx((uint32_t)nb) + 1;  // right-link bits, word j = blocks 32j..32j+31
+    uint32_t* ldb = lrb + kRegionThreads;             // down-link bits
+    uint32_t* eb = ldb + kRegionThreads;              // edge bits
+    uint32_t* scan = eb + kRegionThreads;             // NW words
+    uint32_t* misc = scan + NW;                       // [0]: background key
+
+    // 1. link / edge bits, strided over the blocks so the loads coalesce; a
+    // wave's 64 bits go to two bitmap words through ballots.  The block column
+    // advances by 1024 mod gw per step (no division in the loop).
+    const int step_x = kRegionThreads % gw;
+    int bx = t % gw;
+#pragma unroll 8
+    for (int i = 0; i < kRegionPer; ++i) {
+        const int b = i * kRegionThreads + t;
+        bool e = true, lr = false, ld = false;
+        if (b < nb) {
+            const uint32_t s = f.stats[b];
+            parent[pidx(b)] = b;
+            e = (s >> 24) != 0;
+            if (!e && bx + 1 < gw) {
+                const uint32_t n = f.stats[b + 1];
+                lr = !(n >> 24) && mean_l1(s, n) <= f.tau;
+            }
+            if (!e && b + gw < nb) {
+                const uint32_t n = f.stats[b + gw];
+                ld = !(n >> 24) && mean_l1(s, n) <= f.tau;
+            }
+        }
+        bx += step_x;
+        if (bx >= gw) bx -= gw;
+        const unsigned long long mr = __ballot(lr), md = __ballot(ld), me = __ballot(e);
+        if (lane == 0) {
+            const int w0 = (i * kRegionThreads + wave * 64) >> 5;
+            lrb[w0] = (uint32_t)mr; lrb[w0 + 1] = (uint32_t)(mr >> 32);
+            ldb[w0] = (uint32_t)md; ldb[w0 + 1] = (uint32_t)(md >> 32);
+            eb[w0] = (uint32_t)me; eb[w0 + 1] = (uint32_t)(me >> 32);
+        }
+    }
+    if (t == 0) misc[0] = 0;
+    __syncthreads();
+
+    // from here on lane t owns the 32 contiguous blocks [32t, 32t+32)
+    const int b0 = t * kRegionPer;
+    const int nown = max(0, min(kRegionPer, nb - b0));
+    const int bx0 = b0 % gw, by0 = b0 / gw;
+    const uint32_t lr = lrb[t], ld = ldb[t], emask = eb[t];
+
+    // 2. segments: start(b) = b is not right-linked from b - 1 (a row's first
+    // block never is: the last block of a row has no right link)
+    const uint32_t prev_lr = t > 0 ? lrb[t - 1] : 0u;
+    const uint32_t linked_from_left = (lr << 1) | (prev_lr >> 31);
+    const uint32_t own_mask = nown >= 32 ? 0xFFFFFFFFu : ((1u << nown) - 1u);
+    const uint32_t starts = ~linked_from_left & own_mask;
+    const int last_start = starts ? b0 + 31 - __clz(starts) : -1;
+    int incl = last_start;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl = max(incl, v);
+    }
+    if (lane == 63) scan[wave] = (uint32_t)(incl + 1);
+    __syncthreads();
+    int carry = __shfl_up(incl, 1);
+    if (lane == 0) carry = -1;
+    for (int v = 0; v < wave; ++v) carry = max(carry, (int)scan[v] - 1);
+    uint32_t node[kRegionPer];  // segment, then root, then label of each owned block
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i) {
+        if ((starts >> i) & 1u) carry = b0 + i;
+        node[i] = (uint32_t)carry;
+    }
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown) parent[pidx(b0 + i)] = node[i];
+    __syncthreads();
+
+    // 3. unions across rows, only where the segment pair changes along the row:
+    // skip b when b - 1 is in the same segment, also links down, and the
+    // blocks below b - 1 and b are right-linked too
+    {
+        const int c0 = b0 + gw;  // first block below the owned run
+        uint32_t below_lr = 0;
+        if (ld) {
+            const int w = c0 >> 5, sh = c0 & 31;
+            const uint32_t lo = lrb[w];
+            const uint32_t hi = (w + 1 < kRegionThreads) ? lrb[w + 1] : 0u;
+            below_lr = sh ? (lo >> sh) | (hi << (32 - sh)) : lo;  // bit i = right link of block c0 + i
+        }
+        // skip bit i (i >= 1): ld(i-1) & lr(i-1) & below_lr(i-1)
+        uint32_t todo = ld & ~((ld & lr & below_lr) << 1);
+        while (todo) {
+            const int i = __ffs(todo) - 1;
+            todo &= todo - 1;
+            uf_unite_s(parent, (uint32_t)(b0 + i), (uint32_t)(b0 + i + gw));
+        }
+    }
+    __syncthreads();
+
+    // roots: only segment starts search their tree; after a barrier each start
+    // records its root in its own entry and every other block reads the root
+    // off its segment start
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown && ((starts >> i) & 1u)) node[i] = uf_find_s(parent, b0 + i);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown && ((starts >> i) & 1u)) parent[pidx(b0 + i)] = node[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown && !((starts >> i) & 1u)) node[i] = parent[pidx(node[i])];
+    __syncthreads();
+
+    // 4. label = smallest block index of the tree, kept at the root as 0x10000 | min
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown && node[i] == (uint32_t)(b0 + i)) parent[pidx(b0 + i)] = 0xFFFFFFFFu;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown && (i == 0 || node[i] != node[i - 1]))
+            atomicMin(&parent[pidx(node[i])], 0x10000u | (uint32_t)(b0 + i));
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown) node[i] = parent[pidx(node[i])] & 0xFFFFu;
+    __syncthreads();
+
+    // background key per label: (non-edge block count << 16) | (0xFFFF - label);
+    // the largest key is the largest region, ties to the smaller label
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown) parent[pidx(b0 + i)] = 0;
+    __syncthreads();
+    {
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < kRegionPer; ++i) {
+            if (i >= nown) break;
+            if (!((emask >> i) & 1u)) ++run;
+            const bool flush = i + 1 == nown || i + 1 == kRegionPer || node[i + 1 < kRegionPer ? i + 1 : i] != node[i];
+            if (flush && run) {
+                atomicAdd(&parent[pidx(node[i])], run << 16);
+                atomicOr(&parent[pidx(node[i])], 0xFFFFu - node[i]);
+            }
+            if (flush) run = 0;
+        }
+    }
+    __syncthreads();
+    uint32_t best = 0;
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown) best = max(best, parent[pidx(b0 + i)]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) best = max(best, (uint32_t)__shfl_xor((int)best, o));
+    if (lane == 0 && best) atomicMax(&misc[0], best);
+    __syncthreads();
+    const uint32_t bgkey = misc[0];
+    const int bg = bgkey ? (int)(0xFFFFu - (bgkey & 0xFFFFu)) : -1;
+
+    // lowest block row (+1) per label, one atomic per run of equal labels
+    // (rows never decrease along the owned blocks)
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown) parent[pidx(b0 + i)] = 0;
+    __syncthreads();
+    {
+        int by = by0, bx = bx0;
+        uint32_t run_row = 0;
+#pragma unroll
+        for (int i = 0; i < kRegionPer; ++i) {
+            if (i >= nown) break;
+            if (!((emask >> i) & 1u)) run_row = (uint32_t)(by + 1);
+            const bool flush = i + 1 == nown || i + 1 == kRegionPer || node[i + 1 < kRegionPer ? i + 1 : i] != node[i];
+            if (flush && run_row) atomicMax(&parent[pidx(node[i])], run_row);
+            if (flush) run_row = 0;
+            if (++bx == gw) { bx = 0; ++by; }
+        }
+    }
+    __syncthreads();
+
+    // region depth: background and edge blocks follow the row ramp, any other
+    // region sits at the ramp of its lowest block row (ground contact).
+    // Packed (label << 8 | depth) per block, then written out in a strided
+    // pass so the global stores coalesce.
+    {
+        int by = by0, bx = bx0;
+#pragma unroll
+        for (int i = 0; i < kRegionPer; ++i) {
+            if (i >= nown) break;
+            int d;
+            if (((emask >> i) & 1u) || (int)node[i] == bg) d = ramp(by, gh);
+            else d = ramp((int)parent[pidx(node[i])] - 1, gh);
+            node[i] = (node[i] << 8) | (uint32_t)d;
+            if (++bx == gw) { bx = 0; ++by; }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i < nown) parent[pidx(b0 + i)] = node[i];
+    __syncthreads();
+#pragma unroll 8
+    for (int i = 0; i < kRegionPer; ++i) {
+        const int b = i * kRegionThreads + t;
+        if (b < nb) {
+            const uint32_t v = parent[pidx(b)];
+            f.binfo[b] = make_uint2(f.stats[b], v & 255u);
+            f.labels[b] = (int32_t)(v >> 8);
+        }
+    }
+}
+
+__host__ __device__ constexpr size_t regions_lds_bytes_c(int nb) {
+    return (size_t)(nb + nb / 32 + 1 + 3 * kRegionThreads + kRegionThreads / 64 + 4) * 4;
+}
+
+}  // namespace pstereo

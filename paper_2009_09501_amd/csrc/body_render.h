@@ -1,0 +1,608 @@
+// Device bodies of the stereo rendering: filtered depth, then both views
+// (used by the per-frame kernels and by the persistent batch kernel).
+//
+//   k_cbf   pixel depth (from the block tables) and its cross-bilateral
+//           filter guided by luma (Section 3: filtered depth map; Section 4:
+//           GPU cross-bilateral filtering), on 64 x 16 pixel tiles with a
+//           halo in LDS.  Windows whose depths are all equal take the exact
+//           shortcut; the other quads are compacted into a workgroup list so
+//           that only they pay for the weighted sum.  Output: filtered depth,
+//           one byte per pixel, in a scratch buffer.
+//   k_warp  one image row per workgroup: left / right frame reconstruction
+//           (Section 4, Fig. 3 code: depth -> shift, threshold T, half the
+//           stereo base per view) as a forward warp whose z-buffer is an LDS
+//           atomic max on (depth << 24 | RGB) -- the nearer source wins and
+//           its colour travels in the key; then inpainting of the holes
+//           (Section 3: post-processed frames) from the nearer valid pixel
+//           of the row, found with wave ballots; then anaglyph composition
+//           (Fig. 3 code: red from the left view, green and blue from the
+//           right) and RGB24 stores.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "device_common.h"
+
+namespace pstereo {
+
+// Distinct squared distances dx^2 + dy^2 inside a (2r+1)^2 window, r <= 3.
+__host__ __device__ constexpr int k_value(int i) {
+    return i == 0 ? 0 : i == 1 ? 1 : i == 2 ? 2 : i == 3 ? 4 : i == 4 ? 5 : i == 5 ? 8
+         : i == 6 ? 9 : i == 7 ? 10 : i == 8 ? 13 : 18;
+}
+__host__ __device__ constexpr int k_index(int k) {
+    return k == 0 ? 0 : k == 1 ? 1 : k == 2 ? 2 : k == 4 ? 3 : k == 5 ? 4 : k == 8 ? 5
+         : k == 9 ? 6 : k == 10 ? 7 : k == 13 ? 8 : 9;
+}
+__host__ __device__ constexpr int k_count(int r) { return r == 0 ? 1 : r == 1 ? 3 : r == 2 ? 6 : 10; }
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int i) { return (w >> (8 * i)) & 255u; }
+
+// Depth -> (left offset, right offset) of the Fig. 3 rule with the rounding
+// reading: P = round(B*m/255), m = D when D > T (crossed) else 255 - D
+// (uncrossed); the left view moves by ceil(P/2), the right view by floor(P/2),
+// in opposite directions.  Packed as (oL & 0xFFFF) | (oR << 16).
+__device__ __forceinline__ uint32_t shift_entry(int d, int B, int T) {
+    const bool crossed = d > T;
+    const int m = crossed ? d : 255 - d;
+    const int P = (B * m + 127) / 255;
+    const int a = (P + 1) >> 1, b = P >> 1;
+    const int oL = crossed ? a : -a;
+    const int oR = crossed ? -b : b;
+    return ((uint32_t)oL & 0xFFFFu) | ((uint32_t)oR << 16);
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Packed-integer helpers (single gfx950 instructions).
+__device__ __forceinline__ uint32_t dot2_u16(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b), c, false);
+}
+__device__ __forceinline__ uint32_t absdiff16(uint32_t a, uint32_t b) { return __builtin_amdgcn_sad_u16(a, b, 0u); }
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) { return __builtin_amdgcn_perm(hi, lo, sel); }
+__device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s) { return __builtin_amdgcn_alignbyte(hi, lo, s); }
+
+// The four RGB24 pixels of a quad held in three dwords, as four R | G << 8 |
+// B << 16 words (top byte zero).
+__device__ __forceinline__ void quad_colours(uint3 v, uint32_t (&c)[4]) {
+    c[0] = v.x & 0xFFFFFFu;
+    c[1] = alignbyte(v.y, v.x, 3) & 0xFFFFFFu;
+    c[2] = alignbyte(v.z, v.y, 2) & 0xFFFFFFu;
+    c[3] = v.z >> 8;
+}
+
+// Luma of the four pixels of an aligned quad, doubled, as u16 pairs
+// (2Y0 | 2Y1 << 16, 2Y2 | 2Y3 << 16).  Luma = byte 1 of 77R + 150G + 29B + 128.
+__device__ __forceinline__ void quad_luma2(uint3 v, uint32_t& y01, uint32_t& y23) {
+    constexpr uint32_t wlo = 77u | (150u << 8) | (29u << 16);  // R, G, B in bytes 0..2
+    constexpr uint32_t whi = wlo << 8;                         // R, G, B in bytes 1..3
+    const uint32_t r0 = __builtin_amdgcn_udot4(v.x, wlo, 128u, false);
+    const uint32_t r1 = __builtin_amdgcn_udot4(alignbyte(v.y, v.x, 3), wlo, 128u, false);
+    const uint32_t r2 = __builtin_amdgcn_udot4(alignbyte(v.z, v.y, 2), wlo, 128u, false);
+    const uint32_t r3 = __builtin_amdgcn_udot4(v.z, whi, 128u, false);
+    y01 = perm(r1, r0, 0x0c050c01u) << 1;
+    y23 = perm(r3, r2, 0x0c050c01u) << 1;
+}
+
+// Raw depth of the four pixels of a quad: the region depth of their block, or
+// for an edge block that of the non-edge 3x3 neighbour block whose mean colour
+// is nearest (L1), first strict minimum in raster order; with no candidate
+// the ramp of the block row.  col[j] = R | G << 8 | B << 16 of pixel j; the
+// L1 distance to a block mean (stats word, edge byte zero for candidates) is
+// one v_sad_u8.  The nine neighbour loads are unconditional (clamped) so they
+// are all in flight together.
+__device__ __forceinline__ void quad_depth(const FrameDesc& f, int x0, int yy, const uint32_t (&col)[4],
+                                           uint32_t (&D)[4]) {
+    const int bx = x0 / f.K, by = yy / f.K;
+    const uint2 own = f.binfo[by * f.gw + bx];
+    if (!(own.x >> 24)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) D[j] = own.y;
+        return;
+    }
+    uint2 c[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = min(max(bx + k % 3 - 1, 0), f.gw - 1);
+        const int cy = min(max(by + k / 3 - 1, 0), f.gh - 1);
+        c[k] = f.binfo[cy * f.gw + cx];
+    }
+    uint32_t best[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    const uint32_t fallback = (uint32_t)ramp(by, f.gh);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) D[j] = fallback;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = bx + k % 3 - 1, cy = by + k / 3 - 1;
+        if (cx < 0 || cx >= f.gw || cy < 0 || cy >= f.gh || (c[k].x >> 24)) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t dd = __builtin_amdgcn_sad_u8(col[j], c[k].x, 0u);
+            if (dd < best[j]) { best[j] = dd; D[j] = c[k].y; }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_cbf: 64 x 32 pixel tiles, 256 lanes; lane = one quad in each of two tile
+// rows (ty and ty + 16).  LDS holds, for the tile and a 4 px / R row halo,
+// doubled luma and raw depth as u16 pairs (two dwords per quad).  A window of
+// quad x0 reads the six dwords of columns x0-4 .. x0+7 per row.
+constexpr int kTileQ = 16;                   // quads per tile row
+constexpr int kTileW = 4 * kTileQ;           // 64 px
+constexpr int kTileH = 32;                   // rows
+constexpr int kTileQuads = kTileQ + 2;       // quads per LDS row: one extra each side
+constexpr int kRowWords = 2 * kTileQuads;    // 36 dwords per LDS row and plane
+
+// Filtered depth of the four pixels x0..x0+3 of one row.  yw / dw: six dwords
+// per window row = columns x0-4 .. x0+7 as u16 pairs.  Tap (dx, dy) of pixel
+// j reads column c = 4 + j + dx; taps are paired (dx, dx+1) so the weighted
+// depth sum and the weight sum each take one dot2 per pair.  CLIP: some
+// window column lies outside the image and gets weight 0.
+template <int R, bool CLIP>
+__device__ __forceinline__ void cbf_quad(const uint32_t (&yw)[2 * R + 1][6], const uint32_t (&dw)[2 * R + 1][6],
+                                         uint32_t rows_ok, int x0, int W, const uint16_t* wtab, uint32_t (&df)[4]) {
+    const uint8_t* wt = reinterpret_cast<const uint8_t*>(wtab);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t yp = (yw[R][(4 + j) >> 1] >> (16 * ((4 + j) & 1))) & 0xFFFFu;
+        uint32_t acc = 0, wsum = 0;
+#pragma unroll
+        for (int dy = -R; dy <= R; ++dy) {
+            if (!((rows_ok >> (dy + R)) & 1u)) continue;
+            const uint32_t(&yr)[6] = yw[dy + R];
+            const uint32_t(&dr)[6] = dw[dy + R];
+#pragma unroll
+            for (int dx = -R; dx <= R; dx += 2) {
+                const int c = 4 + j + dx;
+                const bool pair = dx + 1 <= R;
+                const uint32_t y0 = (yr[c >> 1] >> (16 * (c & 1))) & 0xFFFFu;
+                // weight table: u16 entries indexed by |dY|, i.e. byte offset 2|dY|
+                uint32_t w0 = *reinterpret_cast<const uint16_t*>(wt + k_index(dx * dx + dy * dy) * 512 + absdiff16(y0, yp));
+                uint32_t w1 = 0;
+                if (pair) {
+                    const uint32_t y1 = (yr[(c + 1) >> 1] >> (16 * ((c + 1) & 1))) & 0xFFFFu;
+                    w1 = *reinterpret_cast<const uint16_t*>(wt + k_index((dx + 1) * (dx + 1) + dy * dy) * 512 + absdiff16(y1, yp));
+                }
+                if (CLIP) {
+                    if ((unsigned)(x0 + j + dx) >= (unsigned)W) w0 = 0;
+                    if ((unsigned)(x0 + j + dx + 1) >= (unsigned)W) w1 = 0;
+                }
+                const uint32_t wp = w0 | (w1 << 16);
+                const uint32_t dp = (c & 1) ? alignbyte(dr[(c + 1) >> 1], dr[c >> 1], 2) : dr[c >> 1];
+                acc = dot2_u16(wp, dp, acc);
+                wsum = dot2_u16(wp, 0x00010001u, wsum);
+            }
+        }
+        df[j] = div_small_quotient(acc + (wsum >> 1), wsum);
+    }
+}
+
+template <int R>
+struct CbfTile {
+    static constexpr int TR = kTileH + 2 * R;  // LDS rows incl. halo
+    static constexpr int NK = k_count(R);
+    // tY, tD: TR * kRowWords words each; wtab: NK * 256 u16; work: 512 u16; nwork
+    static constexpr int kLdsWords = 2 * TR * kRowWords + NK * 128 + 256 + 1;
+};
+
+// One 64 x 32 tile (tile_x, tile_y) on 256 lanes t = 0..255 (four whole
+// waves).  lds: CbfTile<R>::kLdsWords words.  Inactive lane groups do no
+// memory work but pass the same two barriers.
+template <int R, bool ALIGNED>
+__device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int tile_y, int t, uint32_t* lds,
+                                         bool active) {
+    constexpr int S = 2 * R + 1;
+    constexpr int TR = CbfTile<R>::TR;
+    constexpr int NK = CbfTile<R>::NK;
+    uint32_t* tY = lds;
+    uint32_t* tD = tY + TR * kRowWords;
+    uint16_t* wtab = reinterpret_cast<uint16_t*>(tD + TR * kRowWords);
+    uint16_t* work = wtab + NK * 256;
+    int* nwork_p = reinterpret_cast<int*>(work + 512);
+    int& nwork = *nwork_p;
+
+    const int W = f.w, H = active ? f.h : 0;
+    const int tx0 = tile_x * kTileW, ty0 = tile_y * kTileH;
+
+    // product weights ws[k] * wr[d] per distinct squared distance k
+    for (int i = t; i < NK * 256; i += 256) wtab[i] = (uint16_t)(spatial_w(k_value(i >> 8)) * range_w(i & 255));
+    if (t == 0) nwork = 0;
+
+    // doubled luma + raw depth of the tile and its halo (columns tx0-4 .. tx0+67)
+    for (int i = t; i < TR * kTileQuads; i += 256) {
+        const int tr = i / kTileQuads, tq = i - tr * kTileQuads;
+        const int yy = ty0 - R + tr;
+        const int x0 = tx0 - 4 + 4 * tq;
+        uint32_t y01 = 0, y23 = 0, d01 = 0, d23 = 0;
+        if (yy >= 0 && yy < H && x0 >= 0 && x0 < W) {
+            const int n = min(4, W - x0);
+            const uint8_t* p = f.frame + ((size_t)yy * W + x0) * 3;
+            uint32_t col[4], D[4];
+            if (ALIGNED) {
+                const uint3 v = *reinterpret_cast<const uint3*>(p);
+                quad_luma2(v, y01, y23);
+                quad_colours(v, col);
+            } else {
+                uint32_t Y[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (j < n) {
+                        Y[j] = 2u * (uint32_t)luma(p[3 * j], p[3 * j + 1], p[3 * j + 2]);
+                        col[j] = p[3 * j] | ((uint32_t)p[3 * j + 1] << 8) | ((uint32_t)p[3 * j + 2] << 16);
+                    } else {
+                        Y[j] = 0;
+                        col[j] = 0;
+                    }
+                }
+                y01 = Y[0] | (Y[1] << 16);
+                y23 = Y[2] | (Y[3] << 16);
+            }
+            if (f.depth_in) {
+                const uint8_t* dp = f.depth_in + (size_t)yy * W + x0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) D[j] = j < n ? dp[j] : 0u;
+            } else {
+                quad_depth(f, x0, yy, col, D);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) if (j >= n) D[j] = 0;
+            d01 = D[0] | (D[1] << 16);
+            d23 = D[2] | (D[3] << 16);
+            if (f.out_d0 && tr >= R && tr < R + kTileH && tq >= 1 && tq <= kTileQ) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (j < n) f.out_d0[(size_t)yy * W + x0 + j] = (uint8_t)D[j];
+            }
+        }
+        tY[tr * kRowWords + 2 * tq] = y01;
+        tY[tr * kRowWords + 2 * tq + 1] = y23;
+        tD[tr * kRowWords + 2 * tq] = d01;
+        tD[tr * kRowWords + 2 * tq + 1] = d23;
+    }
+    __syncthreads();
+
+    auto window = [&](int qx_, int ty_, uint32_t (&yw)[S][6], uint32_t (&dw)[S][6], uint32_t& rows_ok) {
+        const int y_ = ty0 + ty_;
+        rows_ok = 0;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const int yy = y_ + i - R;
+            if (yy >= 0 && yy < H) rows_ok |= 1u << i;
+            const int base = (ty_ + i) * kRowWords + 2 * qx_;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) { yw[i][k] = tY[base + k]; dw[i][k] = tD[base + k]; }
+        }
+    };
+    auto store_df = [&](int x0_, int y_, const uint32_t (&df)[4]) {
+        const int n = min(4, W - x0_);
+        const size_t o = (size_t)y_ * W + x0_;
+        if (ALIGNED) {
+            *reinterpret_cast<uint32_t*>(f.df + o) = df[0] | (df[1] << 8) | (df[2] << 16) | (df[3] << 24);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) if (j < n) f.df[o + j] = (uint8_t)df[j];
+        }
+        if (f.out_df) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) if (j < n) f.out_df[o + j] = (uint8_t)df[j];
+        }
+    };
+
+    const int qx = t & (kTileQ - 1);
+    const int lane = t & 63;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int ty = (t >> 4) + 16 * half;
+        const int x0 = tx0 + 4 * qx, y = ty0 + ty;
+        bool needs = false;
+        if (x0 < W && y < H) {
+            // exact shortcut: all in-window depths equal -> the normalised
+            // weighted sum is that depth (columns x0-R .. x0+3+R, valid rows)
+            const uint32_t c = tD[(ty + R) * kRowWords + 2 * qx + 2] & 0xFFFFu;
+            uint32_t bad = 0;
+            const uint32_t splat = c | (c << 16);
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                const int yy = y + i - R;
+                if (yy < 0 || yy >= H) continue;
+                const int base = (ty + i) * kRowWords + 2 * qx;
+#pragma unroll
+                for (int k = (4 - R) >> 1; k <= (7 + R) >> 1; ++k) {
+                    const uint32_t mask = ((2 * k >= 4 - R) ? 0xFFFFu : 0u) | ((2 * k + 1 <= 7 + R) ? 0xFFFF0000u : 0u);
+                    bad |= (tD[base + k] ^ splat) & mask;
+                }
+            }
+            if (!bad) {
+                const uint32_t df[4] = {c, c, c, c};
+                store_df(x0, y, df);
+            } else {
+                needs = true;
+            }
+        }
+        // compact the quads that need the full filter
+        const unsigned long long m = __ballot(needs);
+        if (m) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&nwork, __popcll(m));
+            base = __shfl(base, 0);
+            if (needs) work[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)(t + 256 * half);
+        }
+    }
+    __syncthreads();
+    const int nw = nwork;
+    for (int i = t; i < nw; i += 256) {
+        const int q = work[i];
+        const int qx_ = q & (kTileQ - 1), ty_ = (q & 255) / kTileQ + 16 * (q >> 8);
+        const int x0_ = tx0 + 4 * qx_, y_ = ty0 + ty_;
+        uint32_t yw[S][6], dw[S][6], rows_ok, df[4];
+        window(qx_, ty_, yw, dw, rows_ok);
+        if (x0_ - R >= 0 && x0_ + 3 + R < W) cbf_quad<R, false>(yw, dw, rows_ok, x0_, W, wtab, df);
+        else cbf_quad<R, true>(yw, dw, rows_ok, x0_, W, wtab, df);
+        store_df(x0_, y_, df);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_warp: one image row per workgroup.  Lane t owns the quads t, t + NT,
+// t + 2 NT, ... (Q of them), so the lanes of a wave always touch consecutive
+// quads: coalesced global traffic.  Quad iteration qi of wave w covers the
+// 256-pixel chunk c = qi * NW + w, and chunks follow each other along the
+// row, which is what the hole search walks.  The z-buffer index of pixel x is
+// swizzled to x + x / 32 so that the four pixels of the lanes' quads spread
+// over all LDS banks.
+__device__ __forceinline__ int kidx(int x) { return x + (x >> 5); }
+
+__host__ __device__ constexpr size_t warp_lds_bytes(int w, int threads, int q) {
+    return (size_t)(2 * (((w + 3) & ~3) + ((w + 3) & ~3) / 32 + 1) * 4 + 256 * 4 + ((w + 3) & ~3) +
+                    4 * q * (threads / 64) * 4);
+}
+
+// Image row y on NT lanes t = 0..NT-1 (whole waves).  lds: warp_lds_bytes(w,
+// NT, Q) bytes.  Inactive lane groups do no memory work but pass the same
+// three barriers.
+template <bool ALIGNED, int Q>
+__device__ __forceinline__ void warp_row(const FrameDesc& f, int y, int t, int NT, uint32_t* lds, bool active) {
+    const int W = active ? f.w : 0;
+    const int lane = t & 63, wave = t >> 6, NW = NT >> 6;
+    const int NC = Q * NW;  // chunks per row
+    const int W4 = (W + 3) & ~3;
+    const int KW = kidx(W4) + 1;
+    uint32_t* keyL = lds;
+    uint32_t* keyR = keyL + KW;
+    uint32_t* lut = keyR + KW;                                        // 256 entries
+    uint8_t* drow_l = reinterpret_cast<uint8_t*>(lut + 256);          // the row's filtered depth, W4 bytes
+    int* pub = reinterpret_cast<int*>(drow_l + W4);                   // per chunk: last L, first L, last R, first R
+
+    for (int d = t; d < 256; d += NT) lut[d] = shift_entry(d, f.B, f.T);
+    for (int i = t; i < KW; i += NT) { keyL[i] = 0; keyR[i] = 0; }
+    __syncthreads();
+
+    // ---- forward warp of the row's pixels into both views; the key carries
+    // the depth above the colour, so the atomic max keeps the nearer source
+    // and its colour
+    const uint8_t* drow = f.df + (size_t)y * W;
+    uint32_t col[4 * Q];  // own source colours, R | G << 8 | B << 16
+#pragma unroll
+    for (int qi = 0; qi < Q; ++qi) {
+        const int x0 = 4 * (qi * NT + t);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) col[4 * qi + j] = 0;
+        if (x0 >= W) continue;
+        const int n = min(4, W - x0);
+        uint32_t dq = 0;
+        uint32_t c[4];
+        if (ALIGNED) {
+            quad_colours(*reinterpret_cast<const uint3*>(f.frame + ((size_t)y * W + x0) * 3), c);
+            dq = *reinterpret_cast<const uint32_t*>(drow + x0);
+        } else {
+            const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                c[j] = j < n ? (p[3 * j] | ((uint32_t)p[3 * j + 1] << 8) | ((uint32_t)p[3 * j + 2] << 16)) : 0u;
+                if (j < n) dq |= (uint32_t)drow[x0 + j] << (8 * j);
+            }
+        }
+        *reinterpret_cast<uint32_t*>(drow_l + x0) = dq;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            col[4 * qi + j] = c[j];
+            if (j >= n) continue;
+            const int x = x0 + j;
+            const uint32_t d = (dq >> (8 * j)) & 255u;
+            const uint32_t lv = lut[d];
+            const int xl = x + (int)(int16_t)(lv & 0xFFFFu);
+            const int xr = x + (int)(int16_t)(lv >> 16);
+            const uint32_t key = (d << 24) | c[j];
+            if ((unsigned)xl < (unsigned)W) atomicMax(&keyL[kidx(xl)], key);
+            if ((unsigned)xr < (unsigned)W) atomicMax(&keyR[kidx(xr)], key);
+        }
+    }
+    __syncthreads();
+
+    // ---- validity: a landed source has a non-zero key, except a black source
+    // of depth 0, whose key is 0; such a source is the only one that can land
+    // on a zero key, so zero keys check it directly
+    uint32_t kl[4 * Q], kr[4 * Q];
+    uint32_t vL = 0, vR = 0, own = 0;  // bit 4 qi + j
+#pragma unroll
+    for (int qi = 0; qi < Q; ++qi) {
+        const int x0 = 4 * (qi * NT + t);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = x0 + j;
+            kl[4 * qi + j] = x < W ? keyL[kidx(x)] : 0u;
+            kr[4 * qi + j] = x < W ? keyR[kidx(x)] : 0u;
+            if (x < W) {
+                own |= 1u << (4 * qi + j);
+                if (kl[4 * qi + j]) vL |= 1u << (4 * qi + j);
+                if (kr[4 * qi + j]) vR |= 1u << (4 * qi + j);
+            }
+        }
+    }
+    if (__ballot((own & ~(vL & vR)) != 0)) {
+        const uint32_t lv0 = lut[0];
+        const int o0L = (int)(int16_t)(lv0 & 0xFFFFu), o0R = (int)(int16_t)(lv0 >> 16);
+        uint32_t zl = own & ~vL, zr = own & ~vR;
+        while (zl) {
+            const int i = __ffs(zl) - 1;
+            zl &= zl - 1;
+            const int s0 = 4 * ((i >> 2) * NT + t) + (i & 3) - o0L;
+            if ((unsigned)s0 < (unsigned)W && drow_l[s0] == 0) vL |= 1u << i;
+        }
+        while (zr) {
+            const int i = __ffs(zr) - 1;
+            zr &= zr - 1;
+            const int s0 = 4 * ((i >> 2) * NT + t) + (i & 3) - o0R;
+            if ((unsigned)s0 < (unsigned)W && drow_l[s0] == 0) vR |= 1u << i;
+        }
+    }
+    // per chunk: ballot of the quads holding a valid pixel; the chunk's
+    // extremes go to LDS for the other chunks
+    unsigned long long anyL[Q], anyR[Q];
+#pragma unroll
+    for (int qi = 0; qi < Q; ++qi) {
+        const int x0 = 4 * (qi * NT + t);
+        const uint32_t ql = (vL >> (4 * qi)) & 15u, qr = (vR >> (4 * qi)) & 15u;
+        anyL[qi] = __ballot(ql != 0);
+        anyR[qi] = __ballot(qr != 0);
+        const int lastL = ql ? x0 + 31 - __clz(ql) : -1, firstL = ql ? x0 + __ffs(ql) - 1 : W;
+        const int lastR = qr ? x0 + 31 - __clz(qr) : -1, firstR = qr ? x0 + __ffs(qr) - 1 : W;
+        const int a = __builtin_amdgcn_readlane(lastL, anyL[qi] ? 63 - __clzll(anyL[qi]) : 0);
+        const int b = __builtin_amdgcn_readlane(firstL, anyL[qi] ? __ffsll(anyL[qi]) - 1 : 0);
+        const int c = __builtin_amdgcn_readlane(lastR, anyR[qi] ? 63 - __clzll(anyR[qi]) : 0);
+        const int d = __builtin_amdgcn_readlane(firstR, anyR[qi] ? __ffsll(anyR[qi]) - 1 : 0);
+        if (lane == 0) {
+            const int ch = qi * NW + wave;
+            pub[4 * ch + 0] = anyL[qi] ? a : -1;
+            pub[4 * ch + 1] = anyL[qi] ? b : W;
+            pub[4 * ch + 2] = anyR[qi] ? c : -1;
+            pub[4 * ch + 3] = anyR[qi] ? d : W;
+        }
+    }
+    __syncthreads();
+
+    // ---- inpainting: a hole copies the nearer valid pixel of the warped row
+    // with the smaller depth (background); equal depths go left in the left
+    // view, right in the right view; a row without valid pixels keeps the
+    // source pixel
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long above = ~((2ull << lane) - 1ull);
+    uint32_t cl[4 * Q], cr[4 * Q];
+#pragma unroll
+    for (int i = 0; i < 4 * Q; ++i) {
+        cl[i] = kl[i] & 0xFFFFFFu;
+        cr[i] = kr[i] & 0xFFFFFFu;
+    }
+#pragma unroll
+    for (int qi = 0; qi < Q; ++qi) {
+        const uint32_t ql = (vL >> (4 * qi)) & 15u, qr = (vR >> (4 * qi)) & 15u;
+        const uint32_t oq = (own >> (4 * qi)) & 15u;
+        const bool holes = (oq & ~(ql & qr)) != 0;
+        if (!__ballot(holes)) continue;  // wave-uniform
+        const int x0 = 4 * (qi * NT + t);
+        const int ch = qi * NW + wave;
+        // nearest valid x outside the quad: in the chunk through the ballots
+        // (shuffles run on all lanes of the wave), else in other chunks
+        const int lastL = ql ? x0 + 31 - __clz(ql) : -1, firstL = ql ? x0 + __ffs(ql) - 1 : W;
+        const int lastR = qr ? x0 + 31 - __clz(qr) : -1, firstR = qr ? x0 + __ffs(qr) - 1 : W;
+        const unsigned long long lb = anyL[qi] & below, rb = anyR[qi] & below;
+        const unsigned long long la = anyL[qi] & above, ra = anyR[qi] & above;
+        int exL = __shfl(lastL, lb ? 63 - __clzll(lb) : lane);
+        int exR = __shfl(lastR, rb ? 63 - __clzll(rb) : lane);
+        int efL = __shfl(firstL, la ? __ffsll(la) - 1 : lane);
+        int efR = __shfl(firstR, ra ? __ffsll(ra) - 1 : lane);
+        if (!holes) continue;
+        if (!lb) exL = -1;
+        if (!rb) exR = -1;
+        if (!la) efL = W;
+        if (!ra) efR = W;
+        for (int c = ch - 1; c >= 0 && (exL < 0 || exR < 0); --c) {
+            if (exL < 0) exL = pub[4 * c + 0];
+            if (exR < 0) exR = pub[4 * c + 2];
+        }
+        for (int c = ch + 1; c < NC && (efL >= W || efR >= W); ++c) {
+            if (efL >= W) efL = pub[4 * c + 1];
+            if (efR >= W) efR = pub[4 * c + 3];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!((oq >> j) & 1u)) break;
+            const int i = 4 * qi + j;
+            const uint32_t lowmask = (1u << j) - 1u, highmask = ~((2u << j) - 1u) & 15u;
+            if (!((ql >> j) & 1u)) {
+                const uint32_t lo = ql & lowmask, hi = ql & highmask;
+                const int a = lo ? x0 + 31 - __clz(lo) : exL;
+                const int b = hi ? x0 + __ffs(hi) - 1 : efL;
+                uint32_t k;
+                if (a >= 0 && b < W) {
+                    const uint32_t ka = keyL[kidx(a)], kb = keyL[kidx(b)];
+                    k = (kb >> 24) < (ka >> 24) ? kb : ka;
+                } else if (a >= 0) {
+                    k = keyL[kidx(a)];
+                } else if (b < W) {
+                    k = keyL[kidx(b)];
+                } else {
+                    k = col[i];
+                }
+                cl[i] = k & 0xFFFFFFu;
+            }
+            if (!((qr >> j) & 1u)) {
+                const uint32_t lo = qr & lowmask, hi = qr & highmask;
+                const int a = lo ? x0 + 31 - __clz(lo) : exR;
+                const int b = hi ? x0 + __ffs(hi) - 1 : efR;
+                uint32_t k;
+                if (a >= 0 && b < W) {
+                    const uint32_t ka = keyR[kidx(a)], kb = keyR[kidx(b)];
+                    k = (ka >> 24) < (kb >> 24) ? ka : kb;
+                } else if (a >= 0) {
+                    k = keyR[kidx(a)];
+                } else if (b < W) {
+                    k = keyR[kidx(b)];
+                } else {
+                    k = col[i];
+                }
+                cr[i] = k & 0xFFFFFFu;
+            }
+        }
+    }
+
+    // ---- anaglyph and stores: four R | G << 8 | B << 16 words -> three dwords
+#pragma unroll
+    for (int qi = 0; qi < Q; ++qi) {
+        const int x0 = 4 * (qi * NT + t);
+        if (x0 >= W) continue;
+        const int n = min(4, W - x0);
+        const size_t off = ((size_t)y * W + x0) * 3;
+        auto store4 = [&](uint8_t* out, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
+            if (!out) return;
+            if (ALIGNED) {
+                uint3 v;
+                v.x = perm(c1, c0, 0x04020100u);
+                v.y = perm(c2, c1, 0x05040201u);
+                v.z = perm(c3, c2, 0x06050402u);
+                *reinterpret_cast<uint3*>(out + off) = v;
+            } else {
+                const uint32_t c[4] = {c0, c1, c2, c3};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (j < n) {
+                        out[off + 3 * j] = (uint8_t)c[j];
+                        out[off + 3 * j + 1] = (uint8_t)(c[j] >> 8);
+                        out[off + 3 * j + 2] = (uint8_t)(c[j] >> 16);
+                    }
+                }
+            }
+        };
+        store4(f.out_l, cl[4 * qi], cl[4 * qi + 1], cl[4 * qi + 2], cl[4 * qi + 3]);
+        store4(f.out_r, cr[4 * qi], cr[4 * qi + 1], cr[4 * qi + 2], cr[4 * qi + 3]);
+        // anaglyph: red from the left view, green and blue from the right
+        store4(f.out_a, (cl[4 * qi] & 0xFFu) | (cr[4 * qi] & 0xFFFF00u),
+               (cl[4 * qi + 1] & 0xFFu) | (cr[4 * qi + 1] & 0xFFFF00u),
+               (cl[4 * qi + 2] & 0xFFu) | (cr[4 * qi + 2] & 0xFFFF00u),
+               (cl[4 * qi + 3] & 0xFFu) | (cr[4 * qi + 3] & 0xFFFF00u));
+    }
+}
+
+}  // namespace pstereo

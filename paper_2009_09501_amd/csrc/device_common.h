@@ -29,10 +29,23 @@ __device__ __forceinline__ int luma(int r, int g, int b) {
     return (77 * r + 150 * g + 29 * b + 128) >> 8;
 }
 
+// Exact floor(num / den) for num < 2^31, 0 < den < 2^22 and a quotient below
+// 2^8: a single-precision reciprocal estimate is within 1 of the quotient,
+// and one integer correction step makes it exact.
+__device__ __forceinline__ uint32_t div_small_quotient(uint32_t num, uint32_t den) {
+    const float qf = (float)num * __builtin_amdgcn_rcpf((float)den);
+    int q = (int)qf;
+    const int rem = (int)num - q * (int)den;
+    if (rem < 0) --q;
+    else if (rem >= (int)den) ++q;
+    return (uint32_t)q;
+}
+
 // Row ramp of the region depth: 0 (far) at block row 0, 255 (near) at the
-// bottom block row, rounded half up.
+// bottom block row, rounded half up (quotient <= 255, so the reciprocal
+// division above is exact).
 __device__ __forceinline__ int ramp(int row, int gh) {
-    return gh > 1 ? (255 * row + (gh - 1) / 2) / (gh - 1) : 0;
+    return gh > 1 ? (int)div_small_quotient((uint32_t)(255 * row + (gh - 1) / 2), (uint32_t)(gh - 1)) : 0;
 }
 
 __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }

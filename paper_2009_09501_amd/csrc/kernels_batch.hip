@@ -1,0 +1,195 @@
+// Persistent, fused batch kernel: many frames of uneven size in one launch.
+//
+// Every workgroup (1024 lanes, one per CU) loops: claim the next task from a
+// global counter, wait until the task's inputs are complete, run it, signal
+// completion.  Tasks are numbered in a topological order:
+//   for each frame: its block-statistics tasks, then its region task;
+//   then for each frame: its depth-filter tasks, then its warp tasks.
+// A task is four 64-px tiles (block statistics, depth filter: four 256-lane
+// groups), 1024/G image rows (warp: groups of G lanes), or the whole frame
+// (region grouping: all 1024 lanes).  A workgroup only waits on tasks that
+// were claimed before its own, i.e. by running workgroups, so the loop cannot
+// deadlock whatever the number of resident workgroups.  Completion counters
+// use agent-scope release / acquire so results written through one XCD's L2
+// are visible to the others.
+#include <hip/hip_runtime.h>
+
+#include "body_depth.h"
+#include "body_render.h"
+#include "pstereo_batch.h"
+
+namespace pstereo {
+
+constexpr int kBatchThreads = 1024;
+// task-index broadcast slot at the end of the dynamic LDS
+constexpr size_t kBatchLdsBytes = kMaxLds;
+constexpr size_t kBatchSlotOffset = kMaxLds - 16;
+
+__device__ __forceinline__ uint32_t load_acquire(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Lanes per row group and quads per lane of the warp stage for a row width.
+// At most two quads per lane below 8K: the fused kernel runs 1024-lane
+// workgroups, which caps a lane at 128 VGPRs for all stages together.
+__host__ __device__ inline void warp_group(int w, int& group, int& quads) {
+    const int q4 = (w + 3) / 4;
+    if (q4 <= 256) { group = 256; quads = 1; }
+    else if (q4 <= 512) { group = 256; quads = 2; }
+    else if (q4 <= 1024) { group = 512; quads = 2; }
+    else if (q4 <= 2048) { group = 1024; quads = 2; }
+    else { group = 1024; quads = 4; }
+}
+
+// One task of each stage, as separate (not inlined) functions: each gets its
+// own register allocation instead of the union of all four stages.
+__device__ __noinline__ void task_blockstats(const FrameDesc* fp, int k, int items, int gx, uint32_t* lds) {
+    const FrameDesc f = *fp;
+    const int tid = threadIdx.x;
+    const int g = tid >> 8, t = tid & 255;
+    const int item = 4 * k + g;
+    const bool active = item < items;
+    const int tx = active ? item % gx : 0, ty = active ? item / gx : 0;
+    switch (f.K) {
+        case 4: bs_tile<4, true>(f, tx, ty, t, lds + g * BsTile<4>::kLdsWords, active); break;
+        case 8: bs_tile<8, true>(f, tx, ty, t, lds + g * BsTile<8>::kLdsWords, active); break;
+        case 16: bs_tile<16, true>(f, tx, ty, t, lds + g * BsTile<16>::kLdsWords, active); break;
+        case 32: bs_tile<32, true>(f, tx, ty, t, lds + g * BsTile<32>::kLdsWords, active); break;
+        default: bs_tile<64, true>(f, tx, ty, t, lds + g * BsTile<64>::kLdsWords, active); break;
+    }
+}
+
+__device__ __noinline__ void task_regions(const FrameDesc* fp, uint32_t* lds) {
+    const FrameDesc f = *fp;
+    regions_body(f, lds);
+}
+
+template <int R>
+__device__ __noinline__ void task_cbf(const FrameDesc* fp, int k, int items, int gx, uint32_t* lds) {
+    const FrameDesc f = *fp;
+    const int tid = threadIdx.x;
+    const int g = tid >> 8, t = tid & 255;
+    const int item = 4 * k + g;
+    const bool active = item < items;
+    const int tx = active ? item % gx : 0, ty = active ? item / gx : 0;
+    cbf_tile<R, true>(f, tx, ty, t, lds + g * CbfTile<R>::kLdsWords, active);
+}
+
+__device__ __noinline__ void task_warp(const FrameDesc* fp, int k, uint32_t* lds) {
+    const FrameDesc f = *fp;
+    const int tid = threadIdx.x;
+    int group, quads;
+    warp_group(f.w, group, quads);
+    const int per = kBatchThreads / group;
+    const int g = tid / group, t = tid - g * group;
+    const int y = per * k + g;
+    const bool active = y < f.h;
+    const size_t stride = (warp_lds_bytes(f.w, group, quads) + 15) / 16 * 16;
+    uint32_t* l = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(lds) + g * stride);
+    if (quads == 1) warp_row<true, 1>(f, active ? y : 0, t, group, l, active);
+    else if (quads == 2) warp_row<true, 2>(f, active ? y : 0, t, group, l, active);
+    else warp_row<true, 4>(f, active ? y : 0, t, group, l, active);
+}
+
+template <int R>
+__global__ void __launch_bounds__(kBatchThreads) k_batch(BatchDesc bd) {
+    extern __shared__ uint32_t lds[];
+    int* slot = reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(lds) + kBatchSlotOffset);
+    const int tid = threadIdx.x;
+    int seg = 0;
+    while (true) {
+        if (tid == 0) slot[0] = (int)atomicAdd(&bd.ctr[0], 1u);
+        __syncthreads();
+        const int task = slot[0];
+        __syncthreads();
+        if (task >= bd.ntask) break;
+        while (task >= bd.segs[seg].first + bd.segs[seg].ntask) ++seg;
+        const BatchSeg sg = bd.segs[seg];
+        const FrameDesc* fp = bd.frames + sg.frame;
+        const int k = task - sg.first;  // task index inside the segment
+        // wait for the inputs of this phase of this frame
+        if (sg.phase > 0) {
+            if (tid == 0) {
+                const uint32_t* dep = &bd.ctr[1 + 4 * sg.frame + sg.phase - 1];
+                const uint32_t need = (uint32_t)bd.need[4 * sg.frame + sg.phase - 1];
+                while (load_acquire(dep) < need) __builtin_amdgcn_s_sleep(2);
+            }
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        if (sg.phase == 0) task_blockstats(fp, k, sg.items, sg.gx, lds);
+        else if (sg.phase == 1) task_regions(fp, lds);
+        else if (sg.phase == 2) task_cbf<R>(fp, k, sg.items, sg.gx, lds);
+        else task_warp(fp, k, lds);
+        // publish: every lane's stores reach agent scope, then one release add
+        __threadfence();
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_fetch_add(&bd.ctr[1 + 4 * sg.frame + sg.phase], 1u, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void k_batch_reset(uint32_t* ctr, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+int batch_tasks(const FrameDesc& f, int phase, int* items, int* gx) {
+    switch (phase) {
+        case 0: {
+            const int th = f.K > 16 ? f.K : 16;
+            *gx = (f.w + 63) / 64;
+            *items = *gx * ((f.h + th - 1) / th);
+            return (*items + 3) / 4;
+        }
+        case 1:
+            *gx = 1;
+            *items = 1;
+            return 1;
+        case 2:
+            *gx = (f.w + kTileW - 1) / kTileW;
+            *items = *gx * ((f.h + kTileH - 1) / kTileH);
+            return (*items + 3) / 4;
+        default: {
+            int group, quads;
+            warp_group(f.w, group, quads);
+            const int per = kBatchThreads / group;
+            *gx = 1;
+            *items = f.h;
+            return (f.h + per - 1) / per;
+        }
+    }
+}
+
+bool batch_width_ok(int w) {
+    int group, quads;
+    warp_group(w, group, quads);
+    if ((w + 3) / 4 > group * quads) return false;
+    return (size_t)(kBatchThreads / group) * ((warp_lds_bytes(w, group, quads) + 15) / 16 * 16) <= kBatchSlotOffset;
+}
+
+hipError_t prepare_batch_kernels() {
+    hipError_t e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<0>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBatchLdsBytes)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<1>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBatchLdsBytes)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<2>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBatchLdsBytes)) != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<3>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBatchLdsBytes);
+}
+
+hipError_t launch_batch(const BatchDesc& bd, int r, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, bd.ctr, 1 + 4 * bd.nframes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    switch (r) {
+        case 0: hipLaunchKernelGGL(k_batch<0>, dim3(grid), dim3(kBatchThreads), kBatchLdsBytes, s, bd); break;
+        case 1: hipLaunchKernelGGL(k_batch<1>, dim3(grid), dim3(kBatchThreads), kBatchLdsBytes, s, bd); break;
+        case 2: hipLaunchKernelGGL(k_batch<2>, dim3(grid), dim3(kBatchThreads), kBatchLdsBytes, s, bd); break;
+        default: hipLaunchKernelGGL(k_batch<3>, dim3(grid), dim3(kBatchThreads), kBatchLdsBytes, s, bd); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pstereo

@@ -42,6 +42,11 @@ struct pstereo_ctx {
     long long prof_head = 0;
 };
 
+namespace pstereo {
+int ctx_device(const pstereo_ctx* c) { return c->device; }
+hipStream_t ctx_stream(const pstereo_ctx* c) { return c->stream; }
+}  // namespace pstereo
+
 namespace {
 
 int fail(pstereo_ctx* c, int code, const char* fmt, ...) {
@@ -165,10 +170,15 @@ const char* pstereo_last_error(const pstereo_ctx* c) {
     return c ? c->err.c_str() : g_create_error.c_str();
 }
 
-int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo_params* pin,
-                       uint8_t* out_l, uint8_t* out_r, uint8_t* out_a) {
-    if (!c) return PSTEREO_E_INVALID;
-    c->err.clear();
+}  // extern "C"
+
+namespace {
+
+// Validate one synthesis request and build its frame descriptor.  Returns a
+// status code; on success *f, *ws and *stream are filled.
+int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo_params* pin, uint8_t* out_l,
+               uint8_t* out_r, uint8_t* out_a, FrameDesc* fd, WarpShape* ws, hipStream_t* stream, uint32_t* flags,
+               bool check_ptrs = true) {
     pstereo_params p;
     pstereo_params_init(&p);
     if (pin) {
@@ -196,27 +206,27 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
         return fail(c, PSTEREO_E_INVALID, "%dx%d blocks of %d px exceed %d", gw, gh, K, PSTEREO_MAX_BLOCKS);
 
     int rc;
-    if ((rc = check_device_ptr(c, frame, "frame")) != PSTEREO_OK) return rc;
-    if (out_l && (rc = check_device_ptr(c, out_l, "out_left")) != PSTEREO_OK) return rc;
-    if (out_r && (rc = check_device_ptr(c, out_r, "out_right")) != PSTEREO_OK) return rc;
-    if (out_a && (rc = check_device_ptr(c, out_a, "out_anaglyph")) != PSTEREO_OK) return rc;
-    if (ext && (rc = check_device_ptr(c, p.depth_in, "depth_in")) != PSTEREO_OK) return rc;
-    if (p.out_depth && (rc = check_device_ptr(c, p.out_depth, "out_depth")) != PSTEREO_OK) return rc;
-    if (p.out_depth_raw && (rc = check_device_ptr(c, p.out_depth_raw, "out_depth_raw")) != PSTEREO_OK) return rc;
+    if (check_ptrs && (rc = check_device_ptr(c, frame, "frame")) != PSTEREO_OK) return rc;
+    if (check_ptrs) {
+        if (out_l && (rc = check_device_ptr(c, out_l, "out_left")) != PSTEREO_OK) return rc;
+        if (out_r && (rc = check_device_ptr(c, out_r, "out_right")) != PSTEREO_OK) return rc;
+        if (out_a && (rc = check_device_ptr(c, out_a, "out_anaglyph")) != PSTEREO_OK) return rc;
+        if (ext && (rc = check_device_ptr(c, p.depth_in, "depth_in")) != PSTEREO_OK) return rc;
+        if (p.out_depth && (rc = check_device_ptr(c, p.out_depth, "out_depth")) != PSTEREO_OK) return rc;
+        if (p.out_depth_raw && (rc = check_device_ptr(c, p.out_depth_raw, "out_depth_raw")) != PSTEREO_OK) return rc;
+    }
 
     const size_t img = (size_t)w * h * 3, pl = (size_t)w * h;
     const Range rin[2] = {{frame, img, "frame"}, {ext ? p.depth_in : nullptr, pl, "depth_in"}};
     const Range rout[5] = {{out_l, img, "out_left"}, {out_r, img, "out_right"}, {out_a, img, "out_anaglyph"},
                            {p.out_depth, pl, "out_depth"}, {p.out_depth_raw, pl, "out_depth_raw"}};
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; check_ptrs && i < 5; ++i) {
         for (int j = 0; j < 2; ++j)
             if (overlap(rout[i], rin[j])) return fail(c, PSTEREO_E_ALIAS, "%s overlaps %s", rout[i].name, rin[j].name);
         for (int j = i + 1; j < 5; ++j)
             if (overlap(rout[i], rout[j])) return fail(c, PSTEREO_E_ALIAS, "%s overlaps %s", rout[i].name, rout[j].name);
     }
-
-    WarpShape ws;
-    if (!pstereo::warp_shape(w, &ws))
+    if (!pstereo::warp_shape(w, ws))
         return fail(c, PSTEREO_E_UNSUPPORTED, "width %d exceeds the warp kernel's LDS budget", w);
 
     FrameDesc f{};
@@ -241,14 +251,45 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
     f.g = p.edge_thresh;
     f.tau = p.link_thresh;
     f.r = p.cbf_radius;
-    uintptr_t al = (uintptr_t)frame | (uintptr_t)out_l | (uintptr_t)out_r | (uintptr_t)out_a;
+    const uintptr_t al = (uintptr_t)frame | (uintptr_t)out_l | (uintptr_t)out_r | (uintptr_t)out_a;
     f.aligned = (w % 4 == 0) && (al % 4 == 0);
+    *fd = f;
+    *stream = p.stream ? (hipStream_t)p.stream : c->stream;
+    *flags = p.flags;
+    return PSTEREO_OK;
+}
 
-    hipStream_t s = p.stream ? (hipStream_t)p.stream : c->stream;
+// The launch sequence of one frame (block statistics and region grouping
+// only with a generated depth map).
+void frame_specs(const FrameDesc& f, const WarpShape& ws, pstereo::LaunchSpec (&ls)[4], int& n) {
+    n = 0;
+    if (!f.depth_in) {
+        ls[n++] = pstereo::spec_blockstats(f);
+        ls[n++] = pstereo::spec_regions(f);
+    }
+    ls[n++] = pstereo::spec_cbf(f);
+    ls[n++] = pstereo::spec_warp(f, ws);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo_params* pin,
+                       uint8_t* out_l, uint8_t* out_r, uint8_t* out_a) {
+    if (!c) return PSTEREO_E_INVALID;
+    c->err.clear();
+    FrameDesc f;
+    WarpShape ws;
+    hipStream_t s;
+    uint32_t flags;
+    int rc = build_desc(c, frame, w, h, pin, out_l, out_r, out_a, &f, &ws, &s, &flags);
+    if (rc != PSTEREO_OK) return rc;
+    const bool ext = f.depth_in != nullptr;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return fail(c, PSTEREO_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
 
-    const bool prof = (p.flags & PSTEREO_PROFILE) != 0;
+    const bool prof = (flags & PSTEREO_PROFILE) != 0;
     hipEvent_t* ev = nullptr;
     if (prof) {
         if (c->prof_ev.empty()) {
@@ -264,31 +305,29 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
         c->prof_head++;
     }
 
+    pstereo::LaunchSpec ls[4];
+    int n;
+    frame_specs(f, ws, ls, n);
+    // event k is recorded after kernel k-1; frames without the depth kernels
+    // repeat the first event so the depth slots read zero
     if (prof) (void)hipEventRecord(ev[0], s);
-    if (!ext) {
-        if ((e = pstereo::launch_blockstats(f, s)) != hipSuccess)
-            return fail(c, PSTEREO_E_DEVICE, "block statistics launch: %s", hipGetErrorString(e));
-        if (prof) (void)hipEventRecord(ev[1], s);
-        if ((e = pstereo::launch_regions(f, s)) != hipSuccess)
-            return fail(c, PSTEREO_E_DEVICE, "region grouping launch: %s", hipGetErrorString(e));
-        if (prof) (void)hipEventRecord(ev[2], s);
-    } else if (prof) {
+    if (ext && prof) {
         (void)hipEventRecord(ev[1], s);
         (void)hipEventRecord(ev[2], s);
     }
-    if ((e = pstereo::launch_cbf(f, s)) != hipSuccess)
-        return fail(c, PSTEREO_E_DEVICE, "depth filter launch: %s", hipGetErrorString(e));
-    if (prof) (void)hipEventRecord(ev[3], s);
-    if ((e = pstereo::launch_warp(f, ws, s)) != hipSuccess)
-        return fail(c, PSTEREO_E_DEVICE, "warp launch: %s", hipGetErrorString(e));
-    if (prof) (void)hipEventRecord(ev[4], s);
+    static const char* names[4] = {"block statistics", "region grouping", "depth filter", "warp"};
+    for (int i = 0; i < n; ++i) {
+        if ((e = pstereo::launch(ls[i], f, s)) != hipSuccess)
+            return fail(c, PSTEREO_E_DEVICE, "%s launch: %s", names[i + (ext ? 2 : 0)], hipGetErrorString(e));
+        if (prof) (void)hipEventRecord(ev[i + 1 + (ext ? 2 : 0)], s);
+    }
     if (!ext) {
         c->have_blocks = true;
-        c->last_gw = gw;
-        c->last_gh = gh;
+        c->last_gw = f.gw;
+        c->last_gh = f.gh;
         c->last_stream = s;
     }
-    if (p.flags & PSTEREO_SYNC) {
+    if (flags & PSTEREO_SYNC) {
         if ((e = hipStreamSynchronize(s)) != hipSuccess)
             return fail(c, PSTEREO_E_DEVICE, "stream synchronize: %s", hipGetErrorString(e));
     }
@@ -351,6 +390,156 @@ int pstereo_profile_collect(pstereo_ctx* c, double ms_sum[4], int* count, double
         ++*count;
     }
     c->prof_head = 0;
+    return PSTEREO_OK;
+}
+
+
+// ------------------------------------------------------------------ video
+// The frame's launch sequence as a HIP graph, replayed per frame with the
+// frame and output pointers written into the kernel nodes' arguments.  A
+// small ring of instantiated graphs lets the host prepare frame i+1 while
+// frame i runs; an exec is only updated once its previous replay finished.
+struct pstereo_video {
+    static constexpr int kRing = 4;
+    pstereo_ctx* ctx = nullptr;
+    int w = 0, h = 0;
+    pstereo_params params{};
+    hipStream_t stream = nullptr;
+    FrameDesc tmpl{};
+    WarpShape ws{};
+    pstereo::LaunchSpec ls[4];
+    int nk = 0;
+    hipGraph_t graph[kRing] = {};
+    hipGraphExec_t exec[kRing] = {};
+    hipGraphNode_t node[kRing][4] = {};
+    hipEvent_t done[kRing] = {};
+    bool pending[kRing] = {};
+    long long count = 0;
+};
+
+static void video_free(pstereo_video* v) {
+    for (int k = 0; k < pstereo_video::kRing; ++k) {
+        if (v->exec[k]) (void)hipGraphExecDestroy(v->exec[k]);
+        if (v->graph[k]) (void)hipGraphDestroy(v->graph[k]);
+        if (v->done[k]) (void)hipEventDestroy(v->done[k]);
+    }
+    delete v;
+}
+
+static hipKernelNodeParams node_params(const pstereo::LaunchSpec& ls, void** args) {
+    hipKernelNodeParams kp{};
+    kp.blockDim = ls.block;
+    kp.gridDim = ls.grid;
+    kp.func = const_cast<void*>(ls.func);
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    kp.sharedMemBytes = (unsigned)ls.lds;
+    return kp;
+}
+
+int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, pstereo_video** out) {
+    if (!c) return PSTEREO_E_INVALID;
+    c->err.clear();
+    if (!out) return fail(c, PSTEREO_E_INVALID, "out is NULL");
+    *out = nullptr;
+    pstereo_params pp;
+    pstereo_params_init(&pp);
+    if (p) {
+        if (p->struct_size != sizeof(pstereo_params))
+            return fail(c, PSTEREO_E_INVALID, "params.struct_size %u != %zu", p->struct_size, sizeof(pstereo_params));
+        pp = *p;
+    }
+    if (pp.flags & PSTEREO_DEPTH_EXTERNAL)
+        return fail(c, PSTEREO_E_UNSUPPORTED, "video replay generates the depth map (no PSTEREO_DEPTH_EXTERNAL)");
+    if (pp.out_depth || pp.out_depth_raw)
+        return fail(c, PSTEREO_E_UNSUPPORTED, "video replay takes no depth dumps");
+    pstereo_video* v = new (std::nothrow) pstereo_video;
+    if (!v) return fail(c, PSTEREO_E_NOMEM, "host allocation failed");
+    v->ctx = c;
+    v->w = w;
+    v->h = h;
+    v->params = pp;
+    uint32_t flags;
+    // template descriptor: aligned placeholders stand in for the frame buffers
+    uint8_t* ph = c->d_df;
+    int rc = build_desc(c, ph, w, h, &pp, ph + 4, ph + 8, ph + 12, &v->tmpl, &v->ws, &v->stream, &flags, false);
+    if (rc != PSTEREO_OK) {
+        delete v;
+        return rc;
+    }
+    v->tmpl.out_l = v->tmpl.out_r = v->tmpl.out_a = nullptr;
+    v->tmpl.frame = nullptr;
+    v->tmpl.aligned = (w % 4 == 0);
+    frame_specs(v->tmpl, v->ws, v->ls, v->nk);
+    hipError_t e = hipSetDevice(c->device);
+    for (int k = 0; k < pstereo_video::kRing && e == hipSuccess; ++k) {
+        e = hipGraphCreate(&v->graph[k], 0);
+        FrameDesc arg = v->tmpl;
+        void* args[] = {&arg};
+        for (int i = 0; i < v->nk && e == hipSuccess; ++i) {
+            hipKernelNodeParams kp = node_params(v->ls[i], args);
+            e = hipGraphAddKernelNode(&v->node[k][i], v->graph[k], i ? &v->node[k][i - 1] : nullptr, i ? 1 : 0, &kp);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&v->exec[k], v->graph[k], nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&v->done[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        video_free(v);
+        return fail(c, PSTEREO_E_DEVICE, "graph setup: %s", hipGetErrorString(e));
+    }
+    *out = v;
+    return PSTEREO_OK;
+}
+
+int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, uint8_t* out_r, uint8_t* out_a) {
+    if (!v) return PSTEREO_E_INVALID;
+    pstereo_ctx* c = v->ctx;
+    c->err.clear();
+    FrameDesc f;
+    WarpShape ws;
+    hipStream_t s;
+    uint32_t flags;
+    int rc = build_desc(c, frame, v->w, v->h, &v->params, out_l, out_r, out_a, &f, &ws, &s, &flags);
+    if (rc != PSTEREO_OK) return rc;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return fail(c, PSTEREO_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    if (f.aligned != v->tmpl.aligned) {
+        // the captured kernels assume the first frame's alignment; launch directly
+        pstereo::LaunchSpec ls[4];
+        int n;
+        frame_specs(f, ws, ls, n);
+        for (int i = 0; i < n; ++i)
+            if ((e = pstereo::launch(ls[i], f, s)) != hipSuccess)
+                return fail(c, PSTEREO_E_DEVICE, "launch: %s", hipGetErrorString(e));
+        return PSTEREO_OK;
+    }
+    const int k = (int)(v->count % pstereo_video::kRing);
+    if (v->pending[k] && (e = hipEventSynchronize(v->done[k])) != hipSuccess)
+        return fail(c, PSTEREO_E_DEVICE, "event synchronize: %s", hipGetErrorString(e));
+    FrameDesc arg = f;
+    void* args[] = {&arg};
+    for (int i = 0; i < v->nk; ++i) {
+        hipKernelNodeParams kp = node_params(v->ls[i], args);
+        if ((e = hipGraphExecKernelNodeSetParams(v->exec[k], v->node[k][i], &kp)) != hipSuccess)
+            return fail(c, PSTEREO_E_DEVICE, "graph node update: %s", hipGetErrorString(e));
+    }
+    if ((e = hipGraphLaunch(v->exec[k], v->stream)) != hipSuccess)
+        return fail(c, PSTEREO_E_DEVICE, "graph launch: %s", hipGetErrorString(e));
+    (void)hipEventRecord(v->done[k], v->stream);
+    v->pending[k] = true;
+    v->count++;
+    c->have_blocks = true;
+    c->last_gw = f.gw;
+    c->last_gh = f.gh;
+    c->last_stream = v->stream;
+    return PSTEREO_OK;
+}
+
+int pstereo_video_end(pstereo_video* v) {
+    if (!v) return PSTEREO_OK;
+    (void)hipSetDevice(v->ctx->device);
+    (void)hipStreamSynchronize(v->stream);
+    video_free(v);
     return PSTEREO_OK;
 }
 

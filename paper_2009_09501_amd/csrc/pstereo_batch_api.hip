@@ -1,0 +1,300 @@
+// C ABI of the batched form: many frames of uneven size through one
+// persistent kernel launch (kernels_batch.hip).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pstereo.h"
+#include "pstereo_batch.h"
+#include "pstereo_internal.h"
+
+using pstereo::BatchDesc;
+using pstereo::BatchSeg;
+using pstereo::FrameDesc;
+
+struct pstereo_batch {
+    pstereo_ctx* ctx = nullptr;
+    int device = 0;
+    int max_jobs = 0;
+    int64_t max_pixels = 0;
+    int grid = 0;
+    // device tables and per-frame scratch
+    FrameDesc* d_frames = nullptr;
+    BatchSeg* d_segs = nullptr;
+    int* d_need = nullptr;
+    uint32_t* d_ctr = nullptr;
+    uint32_t* d_stats = nullptr;
+    uint2* d_binfo = nullptr;
+    int32_t* d_labels = nullptr;
+    uint8_t* d_df = nullptr;
+    // pinned staging of the tables
+    FrameDesc* h_frames = nullptr;
+    BatchSeg* h_segs = nullptr;
+    int* h_need = nullptr;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+    // the prepared batch
+    int n = 0, ntask = 0, r = 2;
+    bool prepared = false;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int bfail(pstereo_batch* b, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    b->err = buf;
+    return code;
+}
+
+int dev_ptr_ok(const void* p, int device) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == device;
+}
+
+int auto_block_size(int w, int h) {
+    static const int cand[4] = {8, 16, 32, 64};
+    for (int K : cand)
+        if ((long long)((w + K - 1) / K) * ((h + K - 1) / K) <= PSTEREO_MAX_BLOCKS) return K;
+    return -1;
+}
+
+void batch_free(pstereo_batch* b) {
+    (void)hipSetDevice(b->device);
+    if (b->staged) {
+        (void)hipEventSynchronize(b->staged);
+        (void)hipEventDestroy(b->staged);
+    }
+    (void)hipFree(b->d_frames);
+    (void)hipFree(b->d_segs);
+    (void)hipFree(b->d_need);
+    (void)hipFree(b->d_ctr);
+    (void)hipFree(b->d_stats);
+    (void)hipFree(b->d_binfo);
+    (void)hipFree(b->d_labels);
+    (void)hipFree(b->d_df);
+    (void)hipHostFree(b->h_frames);
+    (void)hipHostFree(b->h_segs);
+    (void)hipHostFree(b->h_need);
+    (void)hipGetLastError();
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pstereo_batch_create(pstereo_ctx* ctx, int max_jobs, int64_t max_pixels, pstereo_batch** out) {
+    if (!ctx || !out || max_jobs < 1 || max_jobs > 4096 || max_pixels < 1) return PSTEREO_E_INVALID;
+    *out = nullptr;
+    pstereo_batch* b = new (std::nothrow) pstereo_batch;
+    if (!b) return PSTEREO_E_NOMEM;
+    b->ctx = ctx;
+    b->device = pstereo::ctx_device(ctx);
+    b->max_jobs = max_jobs;
+    b->max_pixels = max_pixels;
+    if (hipSetDevice(b->device) != hipSuccess) {
+        delete b;
+        return PSTEREO_E_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) != hipSuccess || pstereo::prepare_batch_kernels() != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return PSTEREO_E_DEVICE;
+    }
+    b->grid = prop.multiProcessorCount;  // one 1024-lane workgroup per CU
+    const size_t nb = PSTEREO_MAX_BLOCKS;
+    const size_t df_bytes = (size_t)max_pixels + 256 * (size_t)max_jobs;
+    bool ok = hipMalloc(&b->d_frames, sizeof(FrameDesc) * max_jobs) == hipSuccess &&
+              hipMalloc(&b->d_segs, sizeof(BatchSeg) * 4 * max_jobs) == hipSuccess &&
+              hipMalloc(&b->d_need, sizeof(int) * 4 * max_jobs) == hipSuccess &&
+              hipMalloc(&b->d_ctr, sizeof(uint32_t) * (1 + 4 * max_jobs)) == hipSuccess &&
+              hipMalloc(&b->d_stats, sizeof(uint32_t) * nb * max_jobs) == hipSuccess &&
+              hipMalloc(&b->d_binfo, sizeof(uint2) * nb * max_jobs) == hipSuccess &&
+              hipMalloc(&b->d_labels, sizeof(int32_t) * nb * max_jobs) == hipSuccess &&
+              hipMalloc(&b->d_df, df_bytes) == hipSuccess &&
+              hipHostMalloc(&b->h_frames, sizeof(FrameDesc) * max_jobs, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&b->h_segs, sizeof(BatchSeg) * 4 * max_jobs, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&b->h_need, sizeof(int) * 4 * max_jobs, hipHostMallocDefault) == hipSuccess &&
+              hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        batch_free(b);
+        return PSTEREO_E_NOMEM;
+    }
+    *out = b;
+    return PSTEREO_OK;
+}
+
+int pstereo_batch_destroy(pstereo_batch* b) {
+    if (!b) return PSTEREO_OK;
+    batch_free(b);
+    return PSTEREO_OK;
+}
+
+const char* pstereo_batch_last_error(const pstereo_batch* b) { return b ? b->err.c_str() : ""; }
+
+int pstereo_batch_prepare(pstereo_batch* b, const pstereo_job* jobs, int n, const pstereo_params* pin) {
+    if (!b) return PSTEREO_E_INVALID;
+    b->err.clear();
+    b->prepared = false;
+    if (!jobs || n < 1 || n > b->max_jobs) return bfail(b, PSTEREO_E_INVALID, "job count %d outside 1..%d", n, b->max_jobs);
+    pstereo_params p;
+    pstereo_params_init(&p);
+    if (pin) {
+        if (pin->struct_size != sizeof(pstereo_params)) return bfail(b, PSTEREO_E_INVALID, "params.struct_size mismatch");
+        p = *pin;
+    }
+    if (p.flags & PSTEREO_DEPTH_EXTERNAL) return bfail(b, PSTEREO_E_UNSUPPORTED, "batches generate their depth maps");
+    if (p.out_depth || p.out_depth_raw) return bfail(b, PSTEREO_E_UNSUPPORTED, "batches take no depth dumps");
+    if (p.depth_threshold < -1 || p.depth_threshold > 255) return bfail(b, PSTEREO_E_INVALID, "depth_threshold out of range");
+    if (p.cbf_radius < 0 || p.cbf_radius > 3) return bfail(b, PSTEREO_E_INVALID, "cbf_radius out of range");
+    if (p.edge_thresh < 0 || p.edge_thresh > 255) return bfail(b, PSTEREO_E_INVALID, "edge_thresh out of range");
+    if (p.link_thresh < 0 || p.link_thresh > 765) return bfail(b, PSTEREO_E_INVALID, "link_thresh out of range");
+    if (p.block_size && p.block_size != 4 && p.block_size != 8 && p.block_size != 16 && p.block_size != 32 &&
+        p.block_size != 64)
+        return bfail(b, PSTEREO_E_INVALID, "block_size %d not in {4,8,16,32,64}", p.block_size);
+    (void)hipSetDevice(b->device);
+    // the staging buffers may still feed the previous prepare's copies
+    if (b->staged_pending) {
+        if (hipEventSynchronize(b->staged) != hipSuccess) return bfail(b, PSTEREO_E_DEVICE, "event synchronize");
+        b->staged_pending = false;
+    }
+    int64_t px_total = 0;
+    size_t df_off = 0;
+    for (int i = 0; i < n; ++i) {
+        const pstereo_job& j = jobs[i];
+        if (!j.frame || j.w < 1 || j.h < 1) return bfail(b, PSTEREO_E_INVALID, "job %d: bad frame or size", i);
+        if (j.w % 4 != 0) return bfail(b, PSTEREO_E_UNSUPPORTED, "job %d: width %d not a multiple of 4", i, j.w);
+        if (!pstereo::batch_width_ok(j.w)) return bfail(b, PSTEREO_E_UNSUPPORTED, "job %d: width %d too large", i, j.w);
+        const uintptr_t al = (uintptr_t)j.frame | (uintptr_t)j.out_left | (uintptr_t)j.out_right | (uintptr_t)j.out_anaglyph;
+        if (al % 4) return bfail(b, PSTEREO_E_UNSUPPORTED, "job %d: buffers must be 4-byte aligned", i);
+        const int B = j.max_disparity < 0 ? (2 * j.w + 50) / 100 : j.max_disparity;
+        if (j.max_disparity < -1 || B > 255) return bfail(b, PSTEREO_E_INVALID, "job %d: max_disparity out of range", i);
+        const int K = p.block_size ? p.block_size : auto_block_size(j.w, j.h);
+        if (K < 0) return bfail(b, PSTEREO_E_INVALID, "job %d: frame too large for the block grid", i);
+        const int gw = (j.w + K - 1) / K, gh = (j.h + K - 1) / K;
+        if ((long long)gw * gh > PSTEREO_MAX_BLOCKS) return bfail(b, PSTEREO_E_INVALID, "job %d: too many blocks", i);
+        if (!dev_ptr_ok(j.frame, b->device)) return bfail(b, PSTEREO_E_INVALID, "job %d: frame is not device memory", i);
+        const uint8_t* outs[3] = {j.out_left, j.out_right, j.out_anaglyph};
+        for (const uint8_t* o : outs)
+            if (o && !dev_ptr_ok(o, b->device)) return bfail(b, PSTEREO_E_INVALID, "job %d: output is not device memory", i);
+        px_total += (int64_t)j.w * j.h;
+        if (px_total > b->max_pixels) return bfail(b, PSTEREO_E_INVALID, "batch exceeds %lld pixels", (long long)b->max_pixels);
+        FrameDesc f{};
+        f.frame = j.frame;
+        f.out_l = j.out_left;
+        f.out_r = j.out_right;
+        f.out_a = j.out_anaglyph;
+        f.stats = b->d_stats + (size_t)i * PSTEREO_MAX_BLOCKS;
+        f.binfo = b->d_binfo + (size_t)i * PSTEREO_MAX_BLOCKS;
+        f.labels = b->d_labels + (size_t)i * PSTEREO_MAX_BLOCKS;
+        f.df = b->d_df + df_off;
+        df_off += ((size_t)j.w * j.h + 255) / 256 * 256;
+        f.w = j.w;
+        f.h = j.h;
+        f.K = K;
+        f.gw = gw;
+        f.gh = gh;
+        f.B = B;
+        f.T = p.depth_threshold;
+        f.g = p.edge_thresh;
+        f.tau = p.link_thresh;
+        f.r = p.cbf_radius;
+        f.aligned = 1;
+        b->h_frames[i] = f;
+    }
+    // outputs must not overlap any frame or other output of the batch
+    struct Rng { const uint8_t* p; size_t n; };
+    std::vector<Rng> ins, outs;
+    for (int i = 0; i < n; ++i) {
+        const size_t img = (size_t)jobs[i].w * jobs[i].h * 3;
+        ins.push_back({jobs[i].frame, img});
+        const uint8_t* o[3] = {jobs[i].out_left, jobs[i].out_right, jobs[i].out_anaglyph};
+        for (const uint8_t* x : o) if (x) outs.push_back({x, img});
+    }
+    for (size_t a = 0; a < outs.size(); ++a) {
+        for (const Rng& r : ins)
+            if (outs[a].p < r.p + r.n && r.p < outs[a].p + outs[a].n) return bfail(b, PSTEREO_E_ALIAS, "an output overlaps a frame");
+        for (size_t c = a + 1; c < outs.size(); ++c)
+            if (outs[a].p < outs[c].p + outs[c].n && outs[c].p < outs[a].p + outs[a].n)
+                return bfail(b, PSTEREO_E_ALIAS, "two outputs overlap");
+    }
+    // tasks in claim order: (blockstats, regions) of every frame, then
+    // (depth filter, warp) of every frame
+    int task = 0, s = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i < n; ++i) {
+            for (int ph = 2 * pass; ph < 2 * pass + 2; ++ph) {
+                BatchSeg sg;
+                sg.frame = i;
+                sg.phase = ph;
+                sg.first = task;
+                sg.ntask = pstereo::batch_tasks(b->h_frames[i], ph, &sg.items, &sg.gx);
+                b->h_need[4 * i + ph] = sg.ntask;
+                b->h_segs[s++] = sg;
+                task += sg.ntask;
+            }
+        }
+    }
+    b->n = n;
+    b->ntask = task;
+    b->r = p.cbf_radius;
+    b->stream = p.stream ? (hipStream_t)p.stream : pstereo::ctx_stream(b->ctx);
+    hipStream_t st = b->stream;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(b->d_frames, b->h_frames, sizeof(FrameDesc) * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(b->d_segs, b->h_segs, sizeof(BatchSeg) * 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(b->d_need, b->h_need, sizeof(int) * 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipEventRecord(b->staged, st)) != hipSuccess)
+        return bfail(b, PSTEREO_E_DEVICE, "table upload: %s", hipGetErrorString(e));
+    b->staged_pending = true;
+    b->prepared = true;
+    return PSTEREO_OK;
+}
+
+int pstereo_batch_launch(pstereo_batch* b, void* stream) {
+    if (!b) return PSTEREO_E_INVALID;
+    b->err.clear();
+    if (!b->prepared) return bfail(b, PSTEREO_E_INVALID, "no prepared batch");
+    (void)hipSetDevice(b->device);
+    BatchDesc bd;
+    bd.frames = b->d_frames;
+    bd.segs = b->d_segs;
+    bd.need = b->d_need;
+    bd.ctr = b->d_ctr;
+    bd.nframes = b->n;
+    bd.ntask = b->ntask;
+    hipStream_t st = stream ? (hipStream_t)stream : b->stream;
+    hipError_t e = pstereo::launch_batch(bd, b->r, b->grid, st);
+    if (e != hipSuccess) return bfail(b, PSTEREO_E_DEVICE, "batch launch: %s", hipGetErrorString(e));
+    return PSTEREO_OK;
+}
+
+int pstereo_batch_run(pstereo_batch* b, const pstereo_job* jobs, int n, const pstereo_params* p) {
+    int rc = pstereo_batch_prepare(b, jobs, n, p);
+    if (rc != PSTEREO_OK) return rc;
+    rc = pstereo_batch_launch(b, nullptr);
+    if (rc != PSTEREO_OK) return rc;
+    if (p && (p->flags & PSTEREO_SYNC)) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, PSTEREO_E_DEVICE, "stream synchronize");
+    }
+    return PSTEREO_OK;
+}
+
+}  // extern "C"

@@ -34,15 +34,34 @@ struct WarpShape {
     size_t lds_bytes;   // dynamic LDS per workgroup
 };
 
-// Host-side launch helpers (pstereo_kernels.hip).  Each returns hipSuccess or
-// the launch error.
+// One kernel launch of a frame: every kernel takes a single FrameDesc.
+struct LaunchSpec {
+    const void* func;
+    dim3 grid, block;
+    size_t lds;
+};
+
+// Launch specifications (kernels_depth.hip, kernels_render.hip); func is null
+// for an unsupported combination.
 bool warp_shape(int w, WarpShape* out);
-hipError_t launch_blockstats(const FrameDesc& f, hipStream_t s);
-hipError_t launch_regions(const FrameDesc& f, hipStream_t s);
-hipError_t launch_cbf(const FrameDesc& f, hipStream_t s);
-hipError_t launch_warp(const FrameDesc& f, const WarpShape& ws, hipStream_t s);
+LaunchSpec spec_blockstats(const FrameDesc& f);
+LaunchSpec spec_regions(const FrameDesc& f);
+LaunchSpec spec_cbf(const FrameDesc& f);
+LaunchSpec spec_warp(const FrameDesc& f, const WarpShape& ws);
+
+// Launch one spec on a stream (hipSuccess or the launch error).
+inline hipError_t launch(const LaunchSpec& ls, const FrameDesc& f, hipStream_t s) {
+    if (!ls.func) return hipErrorInvalidValue;
+    FrameDesc arg = f;
+    void* args[] = {&arg};
+    return hipLaunchKernel(ls.func, ls.grid, ls.block, args, ls.lds, s);
+}
 size_t regions_lds_bytes(int nb);
 hipError_t prepare_depth_kernels();
 hipError_t prepare_render_kernels();
+
+// Accessors of the opaque context for the other C ABI files.
+int ctx_device(const pstereo_ctx* c);
+hipStream_t ctx_stream(const pstereo_ctx* c);
 
 }  // namespace pstereo

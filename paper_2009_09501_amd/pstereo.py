@@ -36,6 +36,9 @@ _CODES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_ALIAS"
 EXPORTED = [
     "pstereo_params_init", "pstereo_create", "pstereo_synthesize", "pstereo_destroy",
     "pstereo_last_error", "pstereo_debug_blocks", "pstereo_profile_collect",
+    "pstereo_video_begin", "pstereo_video_frame", "pstereo_video_end",
+    "pstereo_batch_create", "pstereo_batch_prepare", "pstereo_batch_launch", "pstereo_batch_run",
+    "pstereo_batch_destroy", "pstereo_batch_last_error",
 ]
 
 
@@ -53,6 +56,18 @@ class PstereoParams(ctypes.Structure):
         ("out_depth", ctypes.c_void_p),
         ("out_depth_raw", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
+    ]
+
+
+class PstereoJob(ctypes.Structure):
+    _fields_ = [
+        ("frame", ctypes.c_void_p),
+        ("w", ctypes.c_int32),
+        ("h", ctypes.c_int32),
+        ("out_left", ctypes.c_void_p),
+        ("out_right", ctypes.c_void_p),
+        ("out_anaglyph", ctypes.c_void_p),
+        ("max_disparity", ctypes.c_int32),
     ]
 
 
@@ -91,6 +106,25 @@ def load_library():
     lib.pstereo_profile_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ci),
                                             ctypes.POINTER(ctypes.c_double), ci]
     lib.pstereo_profile_collect.restype = ci
+    lib.pstereo_video_begin.argtypes = [vp, ci, ci, P, ctypes.POINTER(vp)]
+    lib.pstereo_video_begin.restype = ci
+    lib.pstereo_video_frame.argtypes = [vp, vp, vp, vp, vp]
+    lib.pstereo_video_frame.restype = ci
+    lib.pstereo_video_end.argtypes = [vp]
+    lib.pstereo_video_end.restype = ci
+    J = ctypes.POINTER(PstereoJob)
+    lib.pstereo_batch_create.argtypes = [vp, ci, ctypes.c_int64, ctypes.POINTER(vp)]
+    lib.pstereo_batch_create.restype = ci
+    lib.pstereo_batch_prepare.argtypes = [vp, J, ci, P]
+    lib.pstereo_batch_prepare.restype = ci
+    lib.pstereo_batch_launch.argtypes = [vp, vp]
+    lib.pstereo_batch_launch.restype = ci
+    lib.pstereo_batch_run.argtypes = [vp, J, ci, P]
+    lib.pstereo_batch_run.restype = ci
+    lib.pstereo_batch_destroy.argtypes = [vp]
+    lib.pstereo_batch_destroy.restype = ci
+    lib.pstereo_batch_last_error.argtypes = [vp]
+    lib.pstereo_batch_last_error.restype = ctypes.c_char_p
     _ = cu
     _lib = lib
     return lib
@@ -168,6 +202,71 @@ def pstereo_profile_collect(ctx: int, cap: int = 4096):
     n = ctypes.c_int()
     _check(load_library().pstereo_profile_collect(ctx, arr, ctypes.byref(n), per, cap), ctx)
     return [arr[i] for i in range(4)], n.value, [per[i] for i in range(min(n.value, cap))]
+
+
+def pstereo_video_begin(ctx: int, w: int, h: int, params: Optional[PstereoParams]) -> int:
+    v = ctypes.c_void_p()
+    _check(load_library().pstereo_video_begin(ctx, w, h, ctypes.byref(params) if params is not None else None,
+                                              ctypes.byref(v)), ctx)
+    return v.value
+
+
+def pstereo_video_frame(video: int, frame, out_left, out_right, out_anaglyph, ctx: Optional[int] = None) -> int:
+    rc = load_library().pstereo_video_frame(video, _ptr(frame), _ptr(out_left), _ptr(out_right), _ptr(out_anaglyph))
+    return _check(rc, ctx)
+
+
+def pstereo_video_end(video: int) -> int:
+    return load_library().pstereo_video_end(video)
+
+
+def _bcheck(rc: int, b: int):
+    if rc != PSTEREO_OK:
+        m = load_library().pstereo_batch_last_error(b)
+        raise PstereoError(rc, m.decode() if m else "")
+    return rc
+
+
+def make_jobs(frames, outs, max_disparity=None):
+    """ctypes array of PstereoJob from lists of frames [h, w, 3] and output
+    triples (tensors or device pointers)."""
+    arr = (PstereoJob * len(frames))()
+    for i, (f, o) in enumerate(zip(frames, outs)):
+        h, w = int(f.shape[0]), int(f.shape[1])
+        arr[i] = PstereoJob(_ptr(f), w, h, _ptr(o[0]), _ptr(o[1]), _ptr(o[2]),
+                            -1 if max_disparity is None else int(max_disparity[i]))
+    return arr
+
+
+def pstereo_batch_create(ctx: int, max_jobs: int, max_pixels: int) -> int:
+    b = ctypes.c_void_p()
+    _check(load_library().pstereo_batch_create(ctx, max_jobs, max_pixels, ctypes.byref(b)), None)
+    return b.value
+
+
+def pstereo_batch_prepare(b: int, jobs, n: int, params: Optional[PstereoParams]) -> int:
+    return _bcheck(load_library().pstereo_batch_prepare(
+        b, jobs, n, ctypes.byref(params) if params is not None else None), b)
+
+
+def pstereo_batch_launch(b: int, stream=None, check: bool = True) -> int:
+    s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    rc = load_library().pstereo_batch_launch(b, s)
+    return _bcheck(rc, b) if check else rc
+
+
+def pstereo_batch_run(b: int, jobs, n: int, params: Optional[PstereoParams], check: bool = True) -> int:
+    rc = load_library().pstereo_batch_run(b, jobs, n, ctypes.byref(params) if params is not None else None)
+    return _bcheck(rc, b) if check else rc
+
+
+def pstereo_batch_destroy(b: int) -> int:
+    return load_library().pstereo_batch_destroy(b)
+
+
+def pstereo_batch_last_error(b: int) -> str:
+    m = load_library().pstereo_batch_last_error(b)
+    return m.decode() if m else ""
 
 
 # ------------------------------------------------------- torch convenience

@@ -45,41 +45,56 @@ def default_disparity(width: int) -> int:
     return (2 * width + 50) // 100
 
 
-def _gradient(w: int, h: int, c00, c10, c01) -> np.ndarray:
-    """Linear horizontal + vertical gradient, float32 [h, w, 3]."""
+_BAND = 128  # rows generated at a time (keeps temporaries in cache)
+
+
+def _gradient_band(w: int, h: int, y0: int, y1: int, c00, c10, c01) -> np.ndarray:
+    """Rows y0..y1-1 of the linear horizontal + vertical gradient, float32."""
     c00 = np.asarray(c00, np.float32)
     c10 = np.asarray(c10, np.float32)
     c01 = np.asarray(c01, np.float32)
-    fx = (np.arange(w, dtype=np.float32) / max(w - 1, 1))[None, :, None]
-    fy = (np.arange(h, dtype=np.float32) / max(h - 1, 1))[:, None, None]
+    fx = (np.arange(w, dtype=np.float32) / np.float32(max(w - 1, 1)))[None, :, None]
+    fy = (np.arange(y0, y1, dtype=np.float32) / np.float32(max(h - 1, 1)))[:, None, None]
     return c00 + (c10 - c00) * fx + (c01 - c00) * fy
 
 
-def _paint(img: np.ndarray, kind: int, cx: float, cy: float, rx: float,
+def _paint(band: np.ndarray, y0: int, kind: int, cx: float, cy: float, rx: float,
            ry: float, colour) -> None:
-    """Paint one opaque axis-aligned ellipse (kind 0) or rectangle (kind 1)."""
-    h, w = img.shape[:2]
+    """Paint the part of one opaque axis-aligned ellipse (kind 0) or rectangle
+    (kind 1) that falls in the band of rows starting at image row y0."""
+    hb, w = band.shape[:2]
     x0 = max(int(math.floor(cx - rx)), 0)
     x1 = min(int(math.ceil(cx + rx)) + 1, w)
-    y0 = max(int(math.floor(cy - ry)), 0)
-    y1 = min(int(math.ceil(cy + ry)) + 1, h)
-    if x0 >= x1 or y0 >= y1:
+    ya = max(int(math.floor(cy - ry)), y0)
+    yb = min(int(math.ceil(cy + ry)) + 1, y0 + hb)
+    if x0 >= x1 or ya >= yb:
         return
     xs = np.arange(x0, x1, dtype=np.float32)[None, :]
-    ys = np.arange(y0, y1, dtype=np.float32)[:, None]
+    ys = np.arange(ya, yb, dtype=np.float32)[:, None]
     if kind == 0:
-        m = ((xs - cx) / rx) ** 2 + ((ys - cy) / ry) ** 2 <= 1.0
+        m = ((xs - np.float32(cx)) / np.float32(rx)) ** 2 + ((ys - np.float32(cy)) / np.float32(ry)) ** 2 <= 1.0
     else:
-        m = (np.abs(xs - cx) <= rx) & (np.abs(ys - cy) <= ry)
-    img[y0:y1, x0:x1][m] = np.asarray(colour, np.float32)
+        m = (np.abs(xs - np.float32(cx)) <= rx) & (np.abs(ys - np.float32(cy)) <= ry)
+    band[ya - y0:yb - y0, x0:x1][m] = np.asarray(colour, np.float32)
 
 
-def _finish(img: np.ndarray, rng: np.random.Generator, sigma: float) -> np.ndarray:
-    if sigma > 0:
-        img += rng.standard_normal(img.shape, dtype=np.float32) * np.float32(sigma)
-    np.rint(img, out=img)
-    np.clip(img, 0, 255, out=img)
-    return img.astype(np.uint8)
+def _render(w: int, h: int, corners, shapes, noise_rng: np.random.Generator,
+            sigma: float) -> np.ndarray:
+    """Gradient, then the shapes in draw order, then N(0, sigma^2) noise per
+    pixel and channel (drawn band by band in row order), rounded to the
+    nearest integer and clipped to [0, 255]."""
+    out = np.empty((h, w, 3), np.uint8)
+    for y0 in range(0, h, _BAND):
+        y1 = min(y0 + _BAND, h)
+        band = _gradient_band(w, h, y0, y1, *corners)
+        for sh in shapes:
+            _paint(band, y0, *sh)
+        if sigma > 0:
+            band += noise_rng.standard_normal(band.shape, dtype=np.float32) * np.float32(sigma)
+        np.rint(band, out=band)
+        np.clip(band, 0, 255, out=band)
+        out[y0:y1] = band
+    return out
 
 
 def gen_frame(seed: int, w: int, h: int, n_shapes: int = 12,
@@ -96,8 +111,8 @@ def gen_frame(seed: int, w: int, h: int, n_shapes: int = 12,
     if w < 1 or h < 1:
         raise ValueError("frame size must be positive")
     rng = np.random.default_rng(seed)
-    c00, c10, c01 = (rng.integers(0, 256, 3) for _ in range(3))
-    img = _gradient(w, h, c00, c10, c01)
+    corners = [rng.integers(0, 256, 3) for _ in range(3)]
+    shapes = []
     for _ in range(n_shapes):
         kind = 0 if rng.random() < 0.5 else 1
         cx = rng.uniform(0, w)
@@ -105,8 +120,8 @@ def gen_frame(seed: int, w: int, h: int, n_shapes: int = 12,
         rx = rng.uniform(max(w / 64, 0.5), max(w / 8, 1.0))
         ry = rng.uniform(max(h / 64, 0.5), max(h / 8, 1.0))
         colour = rng.integers(0, 256, 3)
-        _paint(img, kind, cx, cy, rx, ry, colour)
-    return _finish(img, rng, sigma)
+        shapes.append((kind, cx, cy, rx, ry, colour))
+    return _render(w, h, corners, shapes, rng, sigma)
 
 
 class VideoSpec:
@@ -134,15 +149,12 @@ class VideoSpec:
     def frame(self, t: int) -> np.ndarray:
         a = t / max(self.frames - 1, 1)
         corners = [(1 - a) * s + a * e for s, e in zip(self.c_start, self.c_end)]
-        img = _gradient(self.w, self.h, *corners)
         pos = self.p0 + t * self.v
         pos[:, 0] %= self.w
         pos[:, 1] %= self.h
-        for i in range(len(pos)):
-            _paint(img, 0, float(pos[i, 0]), float(pos[i, 1]),
-                   float(self.rx[i]), float(self.ry[i]), self.colour[i])
-        rng = np.random.default_rng([self.seed, t])
-        return _finish(img, rng, self.sigma)
+        shapes = [(0, float(pos[i, 0]), float(pos[i, 1]), float(self.rx[i]), float(self.ry[i]),
+                   self.colour[i]) for i in range(len(pos))]
+        return _render(self.w, self.h, corners, shapes, np.random.default_rng([self.seed, t]), self.sigma)
 
 
 def gen_video_frame(seed: int, w: int, h: int, t: int, frames: int = 300,

@@ -1,0 +1,162 @@
+"""GPU tests of the launch forms beyond the single call: hipGraph video replay
+(and, as they land, batched and served frames).  Every form must give exactly
+the bytes of the plain per-frame call, which the parity tests tie to the
+oracle."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2009_09501_amd import Context
+    c = Context(0, 7680, 4320)
+    yield c
+    c.close()
+
+
+def _plain(ctx, frame_t, **params):
+    L, R, A = ctx.synthesize(frame_t, **params)
+    torch.cuda.synchronize()
+    return L.cpu().numpy(), R.cpu().numpy(), A.cpu().numpy()
+
+
+@pytest.mark.parametrize("w,h", [(1920, 1080), (640, 360), (333, 190)])
+def test_video_graph_matches_plain_and_oracle(ctx, oracle_mod, w, h):
+    from paper_2009_09501_amd import pstereo_params_init
+    from paper_2009_09501_amd.pstereo import pstereo_video_begin, pstereo_video_end, pstereo_video_frame
+    dev = torch.device("cuda:0")
+    spec = synth.VideoSpec(4, w, h, frames=12, n=40, sigma=3.0)
+    frames = [torch.from_numpy(spec.frame(t)).to(dev) for t in range(10)]
+    B = synth.default_disparity(w)
+    print(f"video {w}x{h} B={B}: 10 frames through the graph", flush=True)
+    outs = [[torch.empty_like(frames[0]) for _ in range(3)] for _ in frames]
+    p = pstereo_params_init(max_disparity=B)
+    p.stream = torch.cuda.current_stream().cuda_stream
+    v = pstereo_video_begin(ctx.handle, w, h, p)
+    try:
+        for f, o in zip(frames, outs):
+            pstereo_video_frame(v, f, *o, ctx=ctx.handle)
+        torch.cuda.synchronize()
+    finally:
+        pstereo_video_end(v)
+    for i, (f, o) in enumerate(zip(frames, outs)):
+        ref = _plain(ctx, f, max_disparity=B)
+        for got, want in zip(o, ref):
+            assert np.array_equal(got.cpu().numpy(), want), f"frame {i}"
+    ora = oracle_mod.synthesize(spec.frame(9), B)
+    assert np.array_equal(outs[9][2].cpu().numpy(), ora.A)
+
+
+def test_video_rejects_external_depth(ctx):
+    from paper_2009_09501_amd import PSTEREO_DEPTH_EXTERNAL, pstereo_params_init
+    from paper_2009_09501_amd.pstereo import PstereoError, pstereo_video_begin
+    p = pstereo_params_init()
+    p.flags = PSTEREO_DEPTH_EXTERNAL
+    with pytest.raises(PstereoError):
+        pstereo_video_begin(ctx.handle, 64, 64, p)
+
+
+def _batch_frames(sizes, seed0):
+    dev = torch.device("cuda:0")
+    host = [synth.gen_frame(seed0 + i, w, h, 20, 4.0) for i, (w, h) in enumerate(sizes)]
+    return host, [torch.from_numpy(f).to(dev) for f in host]
+
+
+BATCH_SIZES = [(1920, 1080), (640, 360), (1280, 720), (3840, 2160), (648, 364), (1024, 768), (2560, 1440),
+               (7680, 4320)]
+
+
+def test_batch_matches_plain_and_oracle(ctx, oracle_mod):
+    from paper_2009_09501_amd import pstereo_params_init
+    from paper_2009_09501_amd.pstereo import (make_jobs, pstereo_batch_create, pstereo_batch_destroy,
+                                              pstereo_batch_run)
+    host, frames = _batch_frames(BATCH_SIZES, 700)
+    outs = [[torch.zeros_like(f) for _ in range(3)] for f in frames]
+    print(f"batch of {len(frames)} frames: {BATCH_SIZES}", flush=True)
+    b = pstereo_batch_create(ctx.handle, 16, sum(w * h for w, h in BATCH_SIZES) + 1024)
+    try:
+        p = pstereo_params_init()
+        p.stream = torch.cuda.current_stream().cuda_stream
+        jobs = make_jobs(frames, outs)
+        pstereo_batch_run(b, jobs, len(frames), p)
+        torch.cuda.synchronize()
+    finally:
+        pstereo_batch_destroy(b)
+    for i, (f, o) in enumerate(zip(frames, outs)):
+        ref = _plain(ctx, f, max_disparity=synth.default_disparity(f.shape[1]))
+        for k, (got, want) in enumerate(zip(o, ref)):
+            g = got.cpu().numpy()
+            assert np.array_equal(g, want), f"frame {i} {BATCH_SIZES[i]} output {k}: {(g != want).any(-1).sum()} px"
+    ora = oracle_mod.synthesize(host[1], synth.default_disparity(640))
+    assert np.array_equal(outs[1][0].cpu().numpy(), ora.L)
+
+
+def test_batch_relaunch_and_graph_replay(ctx):
+    from paper_2009_09501_amd import pstereo_params_init
+    from paper_2009_09501_amd.pstereo import (make_jobs, pstereo_batch_create, pstereo_batch_destroy,
+                                              pstereo_batch_launch, pstereo_batch_prepare)
+    sizes = [(1280, 720), (640, 360), (1920, 1080)]
+    _, frames = _batch_frames(sizes, 900)
+    outs = [[torch.zeros_like(f) for _ in range(3)] for f in frames]
+    refs = [_plain(ctx, f, max_disparity=synth.default_disparity(f.shape[1])) for f in frames]
+    b = pstereo_batch_create(ctx.handle, 4, sum(w * h for w, h in sizes))
+    s = torch.cuda.Stream()
+    try:
+        p = pstereo_params_init()
+        p.stream = s.cuda_stream
+        jobs = make_jobs(frames, outs)
+        pstereo_batch_prepare(b, jobs, len(frames), p)
+        for rep in range(3):
+            for o in outs:
+                for x in o:
+                    x.zero_()
+            torch.cuda.synchronize()
+            pstereo_batch_launch(b, s)
+            s.synchronize()
+            for o, r in zip(outs, refs):
+                for got, want in zip(o, r):
+                    assert np.array_equal(got.cpu().numpy(), want), f"relaunch {rep}"
+        # captured into a HIP graph (through torch's graph API) and replayed
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            pstereo_batch_launch(b, torch.cuda.current_stream())
+        for rep in range(3):
+            for o in outs:
+                for x in o:
+                    x.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for o, r in zip(outs, refs):
+                for got, want in zip(o, r):
+                    assert np.array_equal(got.cpu().numpy(), want), f"graph replay {rep}"
+    finally:
+        torch.cuda.synchronize()
+        pstereo_batch_destroy(b)
+
+
+def test_batch_rejects(ctx):
+    from paper_2009_09501_amd.pstereo import (PSTEREO_E_ALIAS, PSTEREO_E_INVALID, PSTEREO_E_UNSUPPORTED,
+                                              make_jobs, pstereo_batch_create, pstereo_batch_destroy,
+                                              pstereo_batch_run)
+    dev = torch.device("cuda:0")
+    b = pstereo_batch_create(ctx.handle, 2, 1 << 22)
+    try:
+        f = torch.zeros((64, 66, 3), dtype=torch.uint8, device=dev)
+        o = [torch.empty_like(f) for _ in range(3)]
+        assert pstereo_batch_run(b, make_jobs([f], [o]), 1, None, check=False) == PSTEREO_E_UNSUPPORTED
+        f = torch.zeros((64, 64, 3), dtype=torch.uint8, device=dev)
+        o = [torch.empty_like(f) for _ in range(3)]
+        assert pstereo_batch_run(b, make_jobs([f], [[o[0], o[0], o[2]]]), 1, None, check=False) == PSTEREO_E_ALIAS
+        assert pstereo_batch_run(b, make_jobs([f, f, f], [o, o, o]), 3, None, check=False) == PSTEREO_E_INVALID
+        big = torch.zeros((4096, 2048, 3), dtype=torch.uint8, device=dev)
+        ob = [torch.empty_like(big) for _ in range(3)]
+        assert pstereo_batch_run(b, make_jobs([big], [ob]), 1, None, check=False) == PSTEREO_E_INVALID
+    finally:
+        pstereo_batch_destroy(b)
