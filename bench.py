@@ -67,6 +67,190 @@ def cpu_baseline(frames, B, budget_s: float = 12.0, max_frames: int = 60):
             "sample": f"{n} 3840x2160 frames of the same workload, full pipeline, one thread, {dt:.1f} s"}
 
 
+def _pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(q * len(xs)))]
+
+
+def video_leg(torch, synth, ctx, steps: int, warmup: int, bank: int):
+    """4K moving-ellipse video through the replayed kernel graphs: a bank of
+    ``bank`` frames spread over the 300-frame clip, cycled."""
+    from paper_2009_09501_amd import pstereo_params_init
+    from paper_2009_09501_amd.pstereo import pstereo_video_begin, pstereo_video_end, pstereo_video_frame
+    W, H = 3840, 2160
+    spec = synth.VideoSpec(4, W, H, frames=300, n=40, sigma=3.0)
+    ts = [round(i * 299 / max(bank - 1, 1)) for i in range(bank)]
+    dev = torch.device("cuda:0")
+    frames = [torch.from_numpy(spec.frame(t)).to(dev) for t in ts]
+    outs = [torch.empty_like(frames[0]) for _ in range(3)]
+    stream = torch.cuda.current_stream(dev)
+    p = pstereo_params_init(max_disparity=synth.default_disparity(W))
+    p.stream = stream.cuda_stream
+    v = pstereo_video_begin(ctx.handle, W, H, p)
+    try:
+        for i in range(warmup):
+            pstereo_video_frame(v, frames[i % bank], *outs)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(steps):
+            pstereo_video_frame(v, frames[i % bank], *outs)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        pstereo_video_end(v)
+    lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return {"fps": round(steps / dt, 2), "ms_per_frame": round(dt / steps * 1e3, 4),
+            "frame_gpu_ms": {"p50": round(_pct(lat, 0.5), 4), "p99": round(_pct(lat, 0.99), 4)},
+            "pipeline_hbm_frac": round(BYTES_PER_PX * W * H * steps / dt / 1e9 / HBM_PEAK_GBS, 4),
+            "frames": f"VideoSpec(seed 4, 3840x2160, 300 frames, 40 ellipses, sigma 3) frames {ts} cycled"}
+
+
+def batch_leg(torch, synth, ctx, steps: int, warmup: int, distinct: int):
+    """64 frames of uneven size (the seeded 720p..8K mix) in one persistent
+    launch, prepared once and launched ``steps`` times."""
+    from paper_2009_09501_amd import pstereo_params_init
+    from paper_2009_09501_amd.pstereo import (make_jobs, pstereo_batch_create, pstereo_batch_destroy,
+                                              pstereo_batch_launch, pstereo_batch_prepare)
+    sizes = synth.batch_mix_sizes(5, 64)
+    dev = torch.device("cuda:0")
+    bank = {}
+    frames = []
+    for i, (w, h) in enumerate(sizes):
+        lst = bank.setdefault((w, h), [])
+        if len(lst) < distinct:
+            lst.append(torch.from_numpy(synth.gen_frame(10000 + i, w, h, 40, 4.0)).to(dev))
+            frames.append(lst[-1])
+        else:
+            frames.append(lst[i % distinct])
+    outs = [[torch.empty_like(f) for _ in range(3)] for f in frames]
+    px = sum(w * h for w, h in sizes)
+    stream = torch.cuda.current_stream(dev)
+    b = pstereo_batch_create(ctx.handle, len(frames), px)
+    try:
+        p = pstereo_params_init()
+        p.stream = stream.cuda_stream
+        pstereo_batch_prepare(b, make_jobs(frames, outs), len(frames), p)
+        for _ in range(warmup):
+            pstereo_batch_launch(b, stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(steps):
+            pstereo_batch_launch(b, stream)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        torch.cuda.synchronize()
+        pstereo_batch_destroy(b)
+    lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    mps = px * steps / dt / 1e6
+    return {"frames_per_s": round(len(frames) * steps / dt, 2),
+            "megapixels_per_s": round(mps, 1),
+            "fps_4k_equivalent": round(mps / (3840 * 2160 / 1e6), 2),
+            "ms_per_batch": round(dt / steps * 1e3, 4),
+            "batch_gpu_ms": {"p50": round(_pct(lat, 0.5), 4), "p99": round(_pct(lat, 0.99), 4)},
+            "pipeline_hbm_frac": round(BYTES_PER_PX * px * steps / dt / 1e9 / HBM_PEAK_GBS, 4),
+            "frames": f"64 frames, batch_mix_sizes(seed 5) = {px / 1e6:.1f} MP, "
+                      f"{distinct} distinct gen_frame inputs per resolution"}
+
+
+SERVE_SIZES = [(1920, 1080), (3840, 2160), (7680, 4320)]
+
+
+def _serve_run(torch, srv_mod, policy, streams, banks, arrivals, slots, lanes, closed_loop):
+    """Feed one server the arrival schedule (or, closed_loop, everything at
+    once) and return per-request latencies and the span."""
+    import numpy as np
+    m = srv_mod
+    dev = torch.device("cuda:0")
+    srv = m.pstereo_server_create(0, 32 << 30, len(streams), lanes, policy)
+    try:
+        sids, rings = [], []
+        for (w, h, fps) in streams:
+            sids.append(m.pstereo_server_open_stream(srv, w, h, -1, slots))
+            rings.append([[torch.empty((h, w, 3), dtype=torch.uint8, device=dev) for _ in range(3)]
+                          for _ in range(2 * slots)])
+        torch.cuda.synchronize()
+        # warm-up: one frame per stream
+        for i, (w, h, _) in enumerate(streams):
+            m.pstereo_server_submit(srv, sids[i], banks[(w, h)][0], *rings[i][0])
+        m.pstereo_server_drain(srv)
+        m.pstereo_server_poll(srv, 4096)
+        count = [0] * len(streams)
+        t0 = time.perf_counter()
+        base = None
+        for t, i in arrivals:
+            if not closed_loop:
+                while True:
+                    d = t - (time.perf_counter() - t0)
+                    if d <= 0:
+                        break
+                    time.sleep(min(d, 0.0005) if d > 0.0005 else 0)
+            k = count[i]
+            count[i] += 1
+            w, h, _ = streams[i]
+            rid = m.pstereo_server_submit(srv, sids[i], banks[(w, h)][k % len(banks[(w, h)])],
+                                          *rings[i][k % len(rings[i])])
+            if base is None:
+                base = rid
+        m.pstereo_server_drain(srv)
+        span = time.perf_counter() - t0
+        done = m.pstereo_server_poll(srv, 1 << 16)
+    finally:
+        m.pstereo_server_destroy(srv)
+    lat = {}
+    for c in done:
+        w, h, _ = streams[c["stream_id"]]
+        lat.setdefault(f"{w}x{h}", []).append((c["t_done"] - c["t_submit"]) * 1e3)
+    allv = np.concatenate([np.asarray(v) for v in lat.values()])
+    out = {"frames": int(allv.size), "span_s": round(span, 3), "frames_per_s": round(allv.size / span, 1),
+           "latency_ms": {"p50": round(float(np.percentile(allv, 50)), 3),
+                          "p99": round(float(np.percentile(allv, 99)), 3)},
+           "latency_ms_by_size": {k: {"p50": round(float(np.percentile(v, 50)), 3),
+                                      "p99": round(float(np.percentile(v, 99)), 3), "n": len(v)}
+                                  for k, v in sorted(lat.items())}}
+    px = sum(streams[c["stream_id"]][0] * streams[c["stream_id"]][1] for c in done)
+    out["fps_4k_equivalent"] = round(px / (3840 * 2160) / span, 1)
+    return out
+
+
+def serve_leg(torch, synth, duration_s: float, burst: int):
+    """Eight synthetic video streams (1080p / 4K / 8K, Poisson arrivals at 30
+    or 60 frames/s each) through the continuous-batching server and through the
+    plain one-frame-at-a-time policy; then a closed-loop burst of ``burst``
+    frames per stream (everything submitted at once) for capacity."""
+    import numpy as np
+
+    from paper_2009_09501_amd import pstereo as m
+    rng = np.random.default_rng(8)
+    streams = []
+    for i in range(8):
+        w, h = SERVE_SIZES[int(rng.integers(0, 3))]
+        streams.append((w, h, int(rng.choice([30, 60]))))
+    dev = torch.device("cuda:0")
+    banks = {}
+    for w, h, _ in streams:
+        if (w, h) not in banks:
+            spec = synth.VideoSpec(20 + w, w, h, frames=300, n=40, sigma=3.0)
+            banks[(w, h)] = [torch.from_numpy(spec.frame(t)).to(dev) for t in (0, 150)]
+    arrivals = []
+    for i, (_, _, fps) in enumerate(streams):
+        arrivals += [(float(t), i) for t in synth.poisson_arrivals(100 + i, fps, duration_s)]
+    arrivals.sort()
+    burst_arr = [(0.0, i) for k in range(burst) for i in range(len(streams))]
+    res = {"streams": [f"{w}x{h}@{fps}" for w, h, fps in streams], "duration_s": duration_s,
+           "hbm_budget_bytes": 32 << 30}
+    for name, pol, lanes in (("served", m.PSTEREO_SERVE_BATCH, 4), ("plain", m.PSTEREO_SERVE_PLAIN, 1)):
+        res[name] = _serve_run(torch, m, pol, streams, banks, arrivals, 4, lanes, False)
+        res[name + "_burst"] = _serve_run(torch, m, pol, streams, banks, burst_arr, 4, lanes, True)
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,7 +258,13 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--frames", type=int, default=4, help="distinct synthetic frames cycled")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--rows-per-band", type=int, default=0)
+    ap.add_argument("--forms", default="video,batch,serve",
+                    help="extra launch forms measured after the plain path (video, batch, serve; empty = none)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-burst", type=int, default=16)
+    ap.add_argument("--form-steps", type=int, default=60)
+    ap.add_argument("--video-bank", type=int, default=8)
+    ap.add_argument("--batch-distinct", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -148,6 +338,15 @@ def main() -> int:
         "latency_ms": {"p50": round(statistics.median(lat), 4),
                        "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4)},
     }
+    forms = [f for f in args.forms.split(",") if f]
+    if forms:
+        out["forms"] = {}
+    if "video" in forms:
+        out["forms"]["video_graph_4k"] = video_leg(torch, synth, ctx, args.form_steps * 5, 10, args.video_bank)
+    if "batch" in forms:
+        out["forms"]["batch_uneven_64"] = batch_leg(torch, synth, ctx, args.form_steps, 3, args.batch_distinct)
+    if "serve" in forms:
+        out["forms"]["serve_8_streams"] = serve_leg(torch, synth, args.serve_seconds, args.serve_burst)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host, B)
     ctx.close()

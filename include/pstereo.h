@@ -193,7 +193,11 @@ int pstereo_video_end(pstereo_video *v);
  *   persistent kernel; no copies and no allocation, so it can be captured
  *   into a HIP graph and replayed.  A prepared batch can be launched any
  *   number of times; launches of one batch object must not overlap.
- * pstereo_batch_run: prepare + launch (+ wait if PSTEREO_SYNC).
+ *   Each dependency wait inside the persistent kernel is bounded (1 s of
+ *   wall-clock time); should one run out, every workgroup leaves early, the
+ *   outputs are incomplete and the abort word is raised.
+ * pstereo_batch_run: prepare + launch; with PSTEREO_SYNC it also waits for
+ *   the stream and returns PSTEREO_E_DEVICE if the abort word was raised.
  * pstereo_batch_last_error: message of the last failure on the batch.
  */
 typedef struct pstereo_job {
@@ -212,6 +216,74 @@ int pstereo_batch_launch(pstereo_batch *b, void *stream);
 int pstereo_batch_run(pstereo_batch *b, const pstereo_job *jobs, int n, const pstereo_params *p);
 int pstereo_batch_destroy(pstereo_batch *b);
 const char *pstereo_batch_last_error(const pstereo_batch *b);
+
+/*
+ * Serving: frames of several concurrent video streams with continuous
+ * batching (the paper converts each frame independently, Section 5, so a
+ * stream's device state is its buffers only).
+ *
+ * pstereo_server_create(device, hbm_budget_bytes, max_streams, lanes, policy):
+ *   a server with its own context and `lanes` HIP streams (1..16, default
+ *   priority).  policy PSTEREO_SERVE_BATCH forms batches of waiting frames
+ *   (up to 64) and runs each as one persistent launch on an idle lane, so a
+ *   batch of frames that arrived meanwhile runs while earlier ones drain;
+ *   PSTEREO_SERVE_PLAIN runs the frames one at a time through the plain
+ *   per-frame kernels on a single lane (the comparison baseline).  A
+ *   scheduler thread owns all device work of the server.
+ * pstereo_server_open_stream(s, w, h, max_disparity (-1 = 2 % of w), slots,
+ *   flags, &stream_id): admits a stream if its device state fits in what is
+ *   left of the HBM budget (else PSTEREO_E_NOMEM): `slots` (1..64) slots of
+ *   per-frame scratch (block tables + filtered depth, w*h bytes), each also
+ *   holding the frame and the three output images (12*w*h bytes) with
+ *   PSTEREO_STREAM_HOST_IO.  Frames of a stream run in at most `slots`
+ *   requests at once; more wait in the stream's queue (up to 256; beyond
+ *   that submit returns PSTEREO_E_BUSY).  Under PSTEREO_SERVE_BATCH the
+ *   width must be divisible by 4 (PSTEREO_E_UNSUPPORTED otherwise).
+ * pstereo_server_submit(s, stream_id, frame, out_left, out_right,
+ *   out_anaglyph, &req_id): queues one frame of the stream's size.  Without
+ *   PSTEREO_STREAM_HOST_IO every buffer is device memory of the server's GPU,
+ *   4-byte aligned under the batch policy; with it every buffer is host
+ *   memory (pinned memory makes the copies asynchronous), staged through the
+ *   stream's slots.  The caller keeps the buffers valid and untouched until
+ *   the request's completion is reported; outputs may be NULL.
+ * pstereo_server_poll(s, out, max, &n, wait_us): takes up to `max`
+ *   completions (request id, stream, status, host times of submit, launch and
+ *   observed completion in seconds since create), waiting up to wait_us
+ *   microseconds for the first.
+ * pstereo_server_drain(s): waits until every submitted request has completed.
+ * pstereo_server_close_stream(s, id): waits for the stream's requests, frees
+ *   its slots and returns their bytes to the budget.
+ * pstereo_server_info(s, &budget, &in_use, &submitted, &completed).
+ * pstereo_server_destroy(s): completes all submitted requests, then frees.
+ * A server is thread-safe: any host thread may submit and poll.
+ */
+#define PSTEREO_SERVE_BATCH 0
+#define PSTEREO_SERVE_PLAIN 1
+#define PSTEREO_STREAM_HOST_IO 0x1u
+
+typedef struct pstereo_completion {
+    uint64_t req_id;
+    int32_t stream_id;
+    int32_t status;      /* PSTEREO_OK or the failure's code */
+    double t_submit;     /* host seconds since pstereo_server_create */
+    double t_launch;
+    double t_done;
+} pstereo_completion;
+
+typedef struct pstereo_server pstereo_server;
+int pstereo_server_create(int device, int64_t hbm_budget_bytes, int max_streams, int lanes, int policy,
+                          pstereo_server **out);
+int pstereo_server_open_stream(pstereo_server *s, int w, int h, int max_disparity, int slots, uint32_t flags,
+                               int *stream_id);
+int pstereo_server_close_stream(pstereo_server *s, int stream_id);
+int pstereo_server_submit(pstereo_server *s, int stream_id, const uint8_t *frame, uint8_t *out_left,
+                          uint8_t *out_right, uint8_t *out_anaglyph, uint64_t *req_id);
+int pstereo_server_poll(pstereo_server *s, pstereo_completion *out, int max, int *n_out, int wait_us);
+int pstereo_server_drain(pstereo_server *s);
+int pstereo_server_info(const pstereo_server *s, int64_t *budget, int64_t *in_use, uint64_t *submitted,
+                        uint64_t *completed);
+int pstereo_server_destroy(pstereo_server *s);
+const char *pstereo_server_last_error(const pstereo_server *s);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,9 @@
 // were claimed before its own, i.e. by running workgroups, so the loop cannot
 // deadlock whatever the number of resident workgroups.  Completion counters
 // use agent-scope release / acquire so results written through one XCD's L2
-// are visible to the others.
+// are visible to the others.  A dependency wait is also bounded in wall-clock
+// time: should one ever exceed it, the workgroup raises the abort word and
+// every workgroup leaves its loop at its next claim or wait.
 #include <hip/hip_runtime.h>
 
 #include "body_depth.h"
@@ -25,8 +27,16 @@ constexpr int kBatchThreads = 1024;
 constexpr size_t kBatchLdsBytes = kMaxLds;
 constexpr size_t kBatchSlotOffset = kMaxLds - 16;
 
+// Longest dependency wait, in ticks of the 100 MHz constant clock (1 s; a
+// whole 64-frame batch takes a few milliseconds).
+constexpr uint64_t kWaitLimitTicks = 100000000ull;
+
 __device__ __forceinline__ uint32_t load_acquire(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t load_relaxed(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Lanes per row group and quads per lane of the warp stage for a row width.
@@ -96,9 +106,10 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchDesc bd) {
     extern __shared__ uint32_t lds[];
     int* slot = reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(lds) + kBatchSlotOffset);
     const int tid = threadIdx.x;
+    uint32_t* abort_word = bd.ctr + 1 + 4 * bd.nframes;
     int seg = 0;
     while (true) {
-        if (tid == 0) slot[0] = (int)atomicAdd(&bd.ctr[0], 1u);
+        if (tid == 0) slot[0] = load_relaxed(abort_word) ? bd.ntask : (int)atomicAdd(&bd.ctr[0], 1u);
         __syncthreads();
         const int task = slot[0];
         __syncthreads();
@@ -112,9 +123,20 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchDesc bd) {
             if (tid == 0) {
                 const uint32_t* dep = &bd.ctr[1 + 4 * sg.frame + sg.phase - 1];
                 const uint32_t need = (uint32_t)bd.need[4 * sg.frame + sg.phase - 1];
-                while (load_acquire(dep) < need) __builtin_amdgcn_s_sleep(2);
+                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                int ok = 1;
+                while (load_acquire(dep) < need) {
+                    if (load_relaxed(abort_word) || __builtin_amdgcn_s_memrealtime() - t0 > kWaitLimitTicks) {
+                        __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                slot[1] = ok;
             }
             __syncthreads();
+            if (!slot[1]) break;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (sg.phase == 0) task_blockstats(fp, k, sg.items, sg.gx, lds);
@@ -180,7 +202,7 @@ hipError_t prepare_batch_kernels() {
 }
 
 hipError_t launch_batch(const BatchDesc& bd, int r, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, bd.ctr, 1 + 4 * bd.nframes);
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, bd.ctr, 2 + 4 * bd.nframes);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (r) {

@@ -22,14 +22,43 @@ struct BatchDesc {
     const FrameDesc* frames;  // [nframes]
     const BatchSeg* segs;     // [4 * nframes] in claim order
     const int* need;          // [4 * nframes]: tasks of (frame, phase)
-    uint32_t* ctr;            // [0]: next task; [1 + 4 f + p]: finished tasks of (frame f, phase p)
+    uint32_t* ctr;            // [0]: next task; [1 + 4 f + p]: finished tasks of (frame f, phase p);
+                              // [1 + 4 nframes]: abort word (a dependency wait timed out)
     int nframes;
     int ntask;
 };
+
+// Device scratch of one job: block tables (gw * gh entries each) and the
+// filtered-depth image (w * h bytes).
+struct JobScratch {
+    uint32_t* stats;
+    uint2* binfo;
+    int32_t* labels;
+    uint8_t* df;
+};
+
+// Scratch bytes of one job of size w x h with blocks K (tables then depth,
+// each 256-byte aligned); carve() lays such a region out.
+size_t job_scratch_bytes(int w, int h, int K);
+JobScratch job_scratch_carve(uint8_t* base, int w, int h, int K);
 
 int batch_tasks(const FrameDesc& f, int phase, int* items, int* gx);
 bool batch_width_ok(int w);
 hipError_t prepare_batch_kernels();
 hipError_t launch_batch(const BatchDesc& bd, int r, int grid, hipStream_t s);
+
+}  // namespace pstereo
+
+struct pstereo_batch;
+
+namespace pstereo {
+
+// Batch objects for a caller that brings each job's scratch (the server):
+// own_scratch = false allocates only the task tables; prepare then takes one
+// JobScratch per job and, with check_ptrs = false, trusts the caller to have
+// validated the job's device pointers.
+int batch_create_internal(pstereo_ctx* ctx, int max_jobs, int64_t max_pixels, bool own_scratch, pstereo_batch** out);
+int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, const pstereo_params* p,
+                           const JobScratch* scratch, bool check_ptrs);
 
 }  // namespace pstereo

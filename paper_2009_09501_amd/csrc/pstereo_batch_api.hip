@@ -96,9 +96,9 @@ void batch_free(pstereo_batch* b) {
 
 }  // namespace
 
-extern "C" {
+namespace pstereo {
 
-int pstereo_batch_create(pstereo_ctx* ctx, int max_jobs, int64_t max_pixels, pstereo_batch** out) {
+int batch_create_internal(pstereo_ctx* ctx, int max_jobs, int64_t max_pixels, bool own_scratch, pstereo_batch** out) {
     if (!ctx || !out || max_jobs < 1 || max_jobs > 4096 || max_pixels < 1) return PSTEREO_E_INVALID;
     *out = nullptr;
     pstereo_batch* b = new (std::nothrow) pstereo_batch;
@@ -123,11 +123,11 @@ int pstereo_batch_create(pstereo_ctx* ctx, int max_jobs, int64_t max_pixels, pst
     bool ok = hipMalloc(&b->d_frames, sizeof(FrameDesc) * max_jobs) == hipSuccess &&
               hipMalloc(&b->d_segs, sizeof(BatchSeg) * 4 * max_jobs) == hipSuccess &&
               hipMalloc(&b->d_need, sizeof(int) * 4 * max_jobs) == hipSuccess &&
-              hipMalloc(&b->d_ctr, sizeof(uint32_t) * (1 + 4 * max_jobs)) == hipSuccess &&
-              hipMalloc(&b->d_stats, sizeof(uint32_t) * nb * max_jobs) == hipSuccess &&
-              hipMalloc(&b->d_binfo, sizeof(uint2) * nb * max_jobs) == hipSuccess &&
-              hipMalloc(&b->d_labels, sizeof(int32_t) * nb * max_jobs) == hipSuccess &&
-              hipMalloc(&b->d_df, df_bytes) == hipSuccess &&
+              hipMalloc(&b->d_ctr, sizeof(uint32_t) * (2 + 4 * max_jobs)) == hipSuccess &&
+              (!own_scratch || (hipMalloc(&b->d_stats, sizeof(uint32_t) * nb * max_jobs) == hipSuccess &&
+                                hipMalloc(&b->d_binfo, sizeof(uint2) * nb * max_jobs) == hipSuccess &&
+                                hipMalloc(&b->d_labels, sizeof(int32_t) * nb * max_jobs) == hipSuccess &&
+                                hipMalloc(&b->d_df, df_bytes) == hipSuccess)) &&
               hipHostMalloc(&b->h_frames, sizeof(FrameDesc) * max_jobs, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&b->h_segs, sizeof(BatchSeg) * 4 * max_jobs, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&b->h_need, sizeof(int) * 4 * max_jobs, hipHostMallocDefault) == hipSuccess &&
@@ -141,6 +141,14 @@ int pstereo_batch_create(pstereo_ctx* ctx, int max_jobs, int64_t max_pixels, pst
     return PSTEREO_OK;
 }
 
+}  // namespace pstereo
+
+extern "C" {
+
+int pstereo_batch_create(pstereo_ctx* ctx, int max_jobs, int64_t max_pixels, pstereo_batch** out) {
+    return pstereo::batch_create_internal(ctx, max_jobs, max_pixels, true, out);
+}
+
 int pstereo_batch_destroy(pstereo_batch* b) {
     if (!b) return PSTEREO_OK;
     batch_free(b);
@@ -150,6 +158,15 @@ int pstereo_batch_destroy(pstereo_batch* b) {
 const char* pstereo_batch_last_error(const pstereo_batch* b) { return b ? b->err.c_str() : ""; }
 
 int pstereo_batch_prepare(pstereo_batch* b, const pstereo_job* jobs, int n, const pstereo_params* pin) {
+    return pstereo::batch_prepare_internal(b, jobs, n, pin, nullptr, true);
+}
+
+}  // extern "C"
+
+namespace pstereo {
+
+int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, const pstereo_params* pin,
+                           const JobScratch* scratch, bool check_ptrs) {
     if (!b) return PSTEREO_E_INVALID;
     b->err.clear();
     b->prepared = false;
@@ -190,22 +207,33 @@ int pstereo_batch_prepare(pstereo_batch* b, const pstereo_job* jobs, int n, cons
         if (K < 0) return bfail(b, PSTEREO_E_INVALID, "job %d: frame too large for the block grid", i);
         const int gw = (j.w + K - 1) / K, gh = (j.h + K - 1) / K;
         if ((long long)gw * gh > PSTEREO_MAX_BLOCKS) return bfail(b, PSTEREO_E_INVALID, "job %d: too many blocks", i);
-        if (!dev_ptr_ok(j.frame, b->device)) return bfail(b, PSTEREO_E_INVALID, "job %d: frame is not device memory", i);
-        const uint8_t* outs[3] = {j.out_left, j.out_right, j.out_anaglyph};
-        for (const uint8_t* o : outs)
-            if (o && !dev_ptr_ok(o, b->device)) return bfail(b, PSTEREO_E_INVALID, "job %d: output is not device memory", i);
+        if (check_ptrs) {
+            if (!dev_ptr_ok(j.frame, b->device)) return bfail(b, PSTEREO_E_INVALID, "job %d: frame is not device memory", i);
+            const uint8_t* outs[3] = {j.out_left, j.out_right, j.out_anaglyph};
+            for (const uint8_t* o : outs)
+                if (o && !dev_ptr_ok(o, b->device))
+                    return bfail(b, PSTEREO_E_INVALID, "job %d: output is not device memory", i);
+        }
         px_total += (int64_t)j.w * j.h;
-        if (px_total > b->max_pixels) return bfail(b, PSTEREO_E_INVALID, "batch exceeds %lld pixels", (long long)b->max_pixels);
+        if (!scratch && px_total > b->max_pixels)
+            return bfail(b, PSTEREO_E_INVALID, "batch exceeds %lld pixels", (long long)b->max_pixels);
         FrameDesc f{};
         f.frame = j.frame;
         f.out_l = j.out_left;
         f.out_r = j.out_right;
         f.out_a = j.out_anaglyph;
-        f.stats = b->d_stats + (size_t)i * PSTEREO_MAX_BLOCKS;
-        f.binfo = b->d_binfo + (size_t)i * PSTEREO_MAX_BLOCKS;
-        f.labels = b->d_labels + (size_t)i * PSTEREO_MAX_BLOCKS;
-        f.df = b->d_df + df_off;
-        df_off += ((size_t)j.w * j.h + 255) / 256 * 256;
+        if (scratch) {
+            f.stats = scratch[i].stats;
+            f.binfo = scratch[i].binfo;
+            f.labels = scratch[i].labels;
+            f.df = scratch[i].df;
+        } else {
+            f.stats = b->d_stats + (size_t)i * PSTEREO_MAX_BLOCKS;
+            f.binfo = b->d_binfo + (size_t)i * PSTEREO_MAX_BLOCKS;
+            f.labels = b->d_labels + (size_t)i * PSTEREO_MAX_BLOCKS;
+            f.df = b->d_df + df_off;
+            df_off += ((size_t)j.w * j.h + 255) / 256 * 256;
+        }
         f.w = j.w;
         f.h = j.h;
         f.K = K;
@@ -220,6 +248,7 @@ int pstereo_batch_prepare(pstereo_batch* b, const pstereo_job* jobs, int n, cons
         b->h_frames[i] = f;
     }
     // outputs must not overlap any frame or other output of the batch
+    // (a server checks each request once, when it is submitted)
     struct Rng { const uint8_t* p; size_t n; };
     std::vector<Rng> ins, outs;
     for (int i = 0; i < n; ++i) {
@@ -228,6 +257,7 @@ int pstereo_batch_prepare(pstereo_batch* b, const pstereo_job* jobs, int n, cons
         const uint8_t* o[3] = {jobs[i].out_left, jobs[i].out_right, jobs[i].out_anaglyph};
         for (const uint8_t* x : o) if (x) outs.push_back({x, img});
     }
+    if (!check_ptrs) outs.clear();
     for (size_t a = 0; a < outs.size(); ++a) {
         for (const Rng& r : ins)
             if (outs[a].p < r.p + r.n && r.p < outs[a].p + outs[a].n) return bfail(b, PSTEREO_E_ALIAS, "an output overlaps a frame");
@@ -268,6 +298,26 @@ int pstereo_batch_prepare(pstereo_batch* b, const pstereo_job* jobs, int n, cons
     return PSTEREO_OK;
 }
 
+size_t job_scratch_bytes(int w, int h, int K) {
+    const size_t nb = (size_t)((w + K - 1) / K) * ((h + K - 1) / K);
+    const size_t tab = (nb * (4 + 8 + 4) + 255) / 256 * 256;
+    return tab + ((size_t)w * h + 255) / 256 * 256;
+}
+
+JobScratch job_scratch_carve(uint8_t* base, int w, int h, int K) {
+    const size_t nb = (size_t)((w + K - 1) / K) * ((h + K - 1) / K);
+    JobScratch s;
+    s.binfo = reinterpret_cast<uint2*>(base);
+    s.stats = reinterpret_cast<uint32_t*>(base + nb * 8);
+    s.labels = reinterpret_cast<int32_t*>(base + nb * 12);
+    s.df = base + (nb * 16 + 255) / 256 * 256;
+    return s;
+}
+
+}  // namespace pstereo
+
+extern "C" {
+
 int pstereo_batch_launch(pstereo_batch* b, void* stream) {
     if (!b) return PSTEREO_E_INVALID;
     b->err.clear();
@@ -293,6 +343,10 @@ int pstereo_batch_run(pstereo_batch* b, const pstereo_job* jobs, int n, const ps
     if (rc != PSTEREO_OK) return rc;
     if (p && (p->flags & PSTEREO_SYNC)) {
         if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, PSTEREO_E_DEVICE, "stream synchronize");
+        uint32_t aborted = 0;
+        if (hipMemcpy(&aborted, b->d_ctr + 1 + 4 * b->n, sizeof(aborted), hipMemcpyDeviceToHost) != hipSuccess)
+            return bfail(b, PSTEREO_E_DEVICE, "abort word read-back");
+        if (aborted) return bfail(b, PSTEREO_E_DEVICE, "a dependency wait timed out; outputs are incomplete");
     }
     return PSTEREO_OK;
 }

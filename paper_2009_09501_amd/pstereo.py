@@ -29,6 +29,10 @@ PSTEREO_PROFILE = 0x4
 
 PSTEREO_MAX_BLOCKS = 32768
 
+PSTEREO_SERVE_BATCH = 0
+PSTEREO_SERVE_PLAIN = 1
+PSTEREO_STREAM_HOST_IO = 0x1
+
 _CODES = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_ALIAS",
           -5: "E_UNSUPPORTED", -6: "E_BUSY"}
 
@@ -39,6 +43,9 @@ EXPORTED = [
     "pstereo_video_begin", "pstereo_video_frame", "pstereo_video_end",
     "pstereo_batch_create", "pstereo_batch_prepare", "pstereo_batch_launch", "pstereo_batch_run",
     "pstereo_batch_destroy", "pstereo_batch_last_error",
+    "pstereo_server_create", "pstereo_server_open_stream", "pstereo_server_close_stream",
+    "pstereo_server_submit", "pstereo_server_poll", "pstereo_server_drain", "pstereo_server_info",
+    "pstereo_server_destroy", "pstereo_server_last_error",
 ]
 
 
@@ -68,6 +75,17 @@ class PstereoJob(ctypes.Structure):
         ("out_right", ctypes.c_void_p),
         ("out_anaglyph", ctypes.c_void_p),
         ("max_disparity", ctypes.c_int32),
+    ]
+
+
+class PstereoCompletion(ctypes.Structure):
+    _fields_ = [
+        ("req_id", ctypes.c_uint64),
+        ("stream_id", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("t_submit", ctypes.c_double),
+        ("t_launch", ctypes.c_double),
+        ("t_done", ctypes.c_double),
     ]
 
 
@@ -125,7 +143,26 @@ def load_library():
     lib.pstereo_batch_destroy.restype = ci
     lib.pstereo_batch_last_error.argtypes = [vp]
     lib.pstereo_batch_last_error.restype = ctypes.c_char_p
-    _ = cu
+    lib.pstereo_server_create.argtypes = [ci, ctypes.c_int64, ci, ci, ci, ctypes.POINTER(vp)]
+    lib.pstereo_server_create.restype = ci
+    lib.pstereo_server_open_stream.argtypes = [vp, ci, ci, ci, ci, cu, ctypes.POINTER(ci)]
+    lib.pstereo_server_open_stream.restype = ci
+    lib.pstereo_server_close_stream.argtypes = [vp, ci]
+    lib.pstereo_server_close_stream.restype = ci
+    lib.pstereo_server_submit.argtypes = [vp, ci, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+    lib.pstereo_server_submit.restype = ci
+    lib.pstereo_server_poll.argtypes = [vp, ctypes.POINTER(PstereoCompletion), ci, ctypes.POINTER(ci), ci]
+    lib.pstereo_server_poll.restype = ci
+    lib.pstereo_server_drain.argtypes = [vp]
+    lib.pstereo_server_drain.restype = ci
+    I64 = ctypes.POINTER(ctypes.c_int64)
+    U64 = ctypes.POINTER(ctypes.c_uint64)
+    lib.pstereo_server_info.argtypes = [vp, I64, I64, U64, U64]
+    lib.pstereo_server_info.restype = ci
+    lib.pstereo_server_destroy.argtypes = [vp]
+    lib.pstereo_server_destroy.restype = ci
+    lib.pstereo_server_last_error.argtypes = [vp]
+    lib.pstereo_server_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -270,6 +307,79 @@ def pstereo_batch_last_error(b: int) -> str:
 
 
 # ------------------------------------------------------- torch convenience
+def _scheck(rc: int, srv):
+    if rc != PSTEREO_OK:
+        m = load_library().pstereo_server_last_error(srv)
+        raise PstereoError(rc, m.decode() if m else "")
+    return rc
+
+
+def pstereo_server_create(device: int, hbm_budget_bytes: int, max_streams: int, lanes: int,
+                          policy: int = PSTEREO_SERVE_BATCH) -> int:
+    s = ctypes.c_void_p()
+    _check(load_library().pstereo_server_create(device, hbm_budget_bytes, max_streams, lanes, policy,
+                                                ctypes.byref(s)))
+    return s.value
+
+
+def pstereo_server_open_stream(srv: int, w: int, h: int, max_disparity: int = -1, slots: int = 4,
+                               flags: int = 0, check: bool = True):
+    sid = ctypes.c_int()
+    rc = load_library().pstereo_server_open_stream(srv, w, h, max_disparity, slots, flags, ctypes.byref(sid))
+    if not check:
+        return rc, sid.value
+    _scheck(rc, srv)
+    return sid.value
+
+
+def pstereo_server_close_stream(srv: int, stream_id: int) -> int:
+    return _scheck(load_library().pstereo_server_close_stream(srv, stream_id), srv)
+
+
+def pstereo_server_submit(srv: int, stream_id: int, frame, out_left, out_right, out_anaglyph,
+                          check: bool = True):
+    """Queue one frame; returns the request id (or (rc, id) with check=False).
+    ``frame`` and outputs are tensors or raw pointers (device, or host for a
+    host-I/O stream)."""
+    rid = ctypes.c_uint64()
+    rc = load_library().pstereo_server_submit(srv, stream_id, _ptr(frame), _ptr(out_left), _ptr(out_right),
+                                              _ptr(out_anaglyph), ctypes.byref(rid))
+    if not check:
+        return rc, rid.value
+    _scheck(rc, srv)
+    return rid.value
+
+
+def pstereo_server_poll(srv: int, max_n: int = 256, wait_us: int = 0):
+    """List of completed requests as dicts."""
+    arr = (PstereoCompletion * max(max_n, 1))()
+    n = ctypes.c_int()
+    _scheck(load_library().pstereo_server_poll(srv, arr, max_n, ctypes.byref(n), wait_us), srv)
+    return [{"req_id": c.req_id, "stream_id": c.stream_id, "status": c.status, "t_submit": c.t_submit,
+             "t_launch": c.t_launch, "t_done": c.t_done} for c in arr[:n.value]]
+
+
+def pstereo_server_drain(srv: int) -> int:
+    return _scheck(load_library().pstereo_server_drain(srv), srv)
+
+
+def pstereo_server_info(srv: int):
+    b, u = ctypes.c_int64(), ctypes.c_int64()
+    sub, com = ctypes.c_uint64(), ctypes.c_uint64()
+    _scheck(load_library().pstereo_server_info(srv, ctypes.byref(b), ctypes.byref(u), ctypes.byref(sub),
+                                               ctypes.byref(com)), srv)
+    return {"budget": b.value, "in_use": u.value, "submitted": sub.value, "completed": com.value}
+
+
+def pstereo_server_destroy(srv: int) -> int:
+    return load_library().pstereo_server_destroy(srv)
+
+
+def pstereo_server_last_error(srv: int) -> str:
+    m = load_library().pstereo_server_last_error(srv)
+    return m.decode() if m else ""
+
+
 class Context:
     """One library context on a GPU; frames and outputs are torch uint8 CUDA
     tensors [h, w, 3].  Work goes on torch's current stream unless a stream

@@ -56,3 +56,21 @@ def test_null_and_bad_args_without_gpu(lib):
     h = ctypes.c_void_p()
     assert lib.pstereo_create(ctypes.byref(h), 0, 0, 10) == -1
     assert b"out of range" in lib.pstereo_last_error(None)
+
+
+def test_completion_struct_layout():
+    """pstereo_completion: u64 id, i32 stream, i32 status, three doubles."""
+    from paper_2009_09501_amd.pstereo import PstereoCompletion
+    assert ctypes.sizeof(PstereoCompletion) == 40
+    assert [PstereoCompletion.__dict__[f].offset for f in
+            ("req_id", "stream_id", "status", "t_submit", "t_launch", "t_done")] == [0, 8, 12, 16, 24, 32]
+
+
+def test_server_bad_args_without_gpu(lib):
+    s = ctypes.c_void_p()
+    assert lib.pstereo_server_create(0, 0, 8, 2, 0, ctypes.byref(s)) == -1      # no budget
+    assert lib.pstereo_server_create(0, 1 << 30, 0, 2, 0, ctypes.byref(s)) == -1  # no streams
+    assert lib.pstereo_server_create(0, 1 << 30, 8, 0, 0, ctypes.byref(s)) == -1  # no lanes
+    assert lib.pstereo_server_create(0, 1 << 30, 8, 2, 7, ctypes.byref(s)) == -1  # unknown policy
+    assert lib.pstereo_server_submit(None, 0, None, None, None, None, None) == -1
+    assert lib.pstereo_server_destroy(None) == 0
