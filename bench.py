@@ -112,8 +112,8 @@ def batch_leg(torch, synth, ctx, steps: int, warmup: int, distinct: int):
     """64 frames of uneven size (the seeded 720p..8K mix) in one persistent
     launch, prepared once and launched ``steps`` times."""
     from paper_2009_09501_amd import pstereo_params_init
-    from paper_2009_09501_amd.pstereo import (make_jobs, pstereo_batch_create, pstereo_batch_destroy,
-                                              pstereo_batch_launch, pstereo_batch_prepare)
+    from paper_2009_09501_amd.pstereo import (make_jobs, pstereo_batch_autotune, pstereo_batch_create,
+                                              pstereo_batch_destroy, pstereo_batch_launch)
     sizes = synth.batch_mix_sizes(5, 64)
     dev = torch.device("cuda:0")
     bank = {}
@@ -132,7 +132,7 @@ def batch_leg(torch, synth, ctx, steps: int, warmup: int, distinct: int):
     try:
         p = pstereo_params_init()
         p.stream = stream.cuda_stream
-        pstereo_batch_prepare(b, make_jobs(frames, outs), len(frames), p)
+        best, best_ms, trials = pstereo_batch_autotune(b, make_jobs(frames, outs), len(frames), p, reps=2)
         for _ in range(warmup):
             pstereo_batch_launch(b, stream)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
@@ -155,6 +155,8 @@ def batch_leg(torch, synth, ctx, steps: int, warmup: int, distinct: int):
             "ms_per_batch": round(dt / steps * 1e3, 4),
             "batch_gpu_ms": {"p50": round(_pct(lat, 0.5), 4), "p99": round(_pct(lat, 0.99), 4)},
             "pipeline_hbm_frac": round(BYTES_PER_PX * px * steps / dt / 1e9 / HBM_PEAK_GBS, 4),
+            "autotune": {"best": best, "best_ms": round(best_ms, 4),
+                         "trials": [dict(t, ms=round(t["ms"], 4)) for t in trials]},
             "frames": f"64 frames, batch_mix_sizes(seed 5) = {px / 1e6:.1f} MP, "
                       f"{distinct} distinct gen_frame inputs per resolution"}
 
@@ -286,7 +288,10 @@ def main() -> int:
     frames = [torch.from_numpy(f).to(dev) for f in host]
     outs = [torch.empty_like(frames[0]) for _ in range(3)]
     ctx = Context(0, W, H)
-    stream = torch.cuda.current_stream(dev)
+    # a stream of our own (default priority): torch's current stream would
+    # otherwise be the NULL stream, which the library maps to its own stream
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
     params = dict(max_disparity=B)
 
     for i in range(args.warmup):

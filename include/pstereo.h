@@ -218,6 +218,45 @@ int pstereo_batch_destroy(pstereo_batch *b);
 const char *pstereo_batch_last_error(const pstereo_batch *b);
 
 /*
+ * Batch forms and their tuning.
+ *  PSTEREO_BATCH_STAGED (default): one launch per stage over all frames of
+ *    the batch (block statistics, region grouping with one workgroup per
+ *    frame, depth filter, then one row-warp launch per distinct row shape);
+ *    kernel boundaries order the stages.
+ *  PSTEREO_BATCH_FUSED: the single persistent kernel described above.
+ * Tuning fields: warp_lanes (64..1024, multiple of 64) caps the lanes of a
+ * row-warp workgroup before quads per lane grow (1, 2, 4); warp_rows (1..8)
+ * rows per row-warp workgroup; fused_grid = persistent workgroups (0 = one
+ * per compute unit).  A new tuning takes effect at the next prepare.
+ * pstereo_batch_autotune: runs the jobs (outputs are written) under each
+ *   candidate tuning -- staged with warp_lanes in {128, 256, 512, 1024} x
+ *   warp_rows in {1, 2, 4}, and fused -- timing `reps` launches of each with
+ *   HIP events on the prepare stream, and leaves the batch prepared with the
+ *   fastest; every timed candidate is reported in trials (up to cap).  The
+ *   call synchronises with the stream.
+ */
+#define PSTEREO_BATCH_STAGED 0
+#define PSTEREO_BATCH_FUSED 1
+
+typedef struct pstereo_batch_tuning {
+    int32_t mode;
+    int32_t warp_lanes;
+    int32_t warp_rows;
+    int32_t fused_grid;
+} pstereo_batch_tuning;
+
+typedef struct pstereo_batch_trial {
+    pstereo_batch_tuning tuning;
+    double ms;  /* mean launch time */
+} pstereo_batch_trial;
+
+int pstereo_batch_set_tuning(pstereo_batch *b, const pstereo_batch_tuning *t);
+int pstereo_batch_get_tuning(const pstereo_batch *b, pstereo_batch_tuning *t);
+int pstereo_batch_autotune(pstereo_batch *b, const pstereo_job *jobs, int n, const pstereo_params *p, int reps,
+                           pstereo_batch_tuning *best, double *best_ms, pstereo_batch_trial *trials, int cap,
+                           int *n_trials);
+
+/*
  * Serving: frames of several concurrent video streams with continuous
  * batching (the paper converts each frame independently, Section 5, so a
  * stream's device state is its buffers only).

@@ -1,5 +1,6 @@
-// Persistent, fused batch kernel: many frames of uneven size in one launch.
+// Batched forms: many frames of uneven size per launch.
 //
+// Fused form: one persistent kernel.
 // Every workgroup (1024 lanes, one per CU) loops: claim the next task from a
 // global counter, wait until the task's inputs are complete, run it, signal
 // completion.  Tasks are numbered in a topological order:
@@ -14,6 +15,9 @@
 // are visible to the others.  A dependency wait is also bounded in wall-clock
 // time: should one ever exceed it, the workgroup raises the abort word and
 // every workgroup leaves its loop at its next claim or wait.
+//
+// Staged form (below the fused kernel): one launch per stage, each over all
+// frames of the batch.
 #include <hip/hip_runtime.h>
 
 #include "body_depth.h"
@@ -157,7 +161,102 @@ __global__ void k_batch_reset(uint32_t* ctr, int n) {
 }
 
 // ---------------------------------------------------------------------------
+// Staged form: one launch per stage over the tiles (rows) of every frame of
+// the batch.  first[] holds, per frame, the index of its first workgroup in
+// the launch (non-decreasing, n + 1 entries); a workgroup finds its frame by
+// binary search over that table (uniform, so scalar loads), then its tile.
+// Kernel boundaries order the stages, so no workgroup ever waits on another.
+
+__device__ __forceinline__ int frame_of(const int* first, int n, int idx) {
+    int lo = 0, hi = n - 1;  // last f with first[f] <= idx
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= idx) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+constexpr int kBsLdsMax = BsTile<64>::kLdsWords > BsTile<8>::kLdsWords ? BsTile<64>::kLdsWords : BsTile<8>::kLdsWords;
+
+__global__ void __launch_bounds__(256) k_mf_blockstats(const FrameDesc* frames, const int* first, int n) {
+    static_assert(BsTile<4>::kLdsWords <= kBsLdsMax && BsTile<16>::kLdsWords <= kBsLdsMax &&
+                  BsTile<32>::kLdsWords <= kBsLdsMax, "blockstats LDS");
+    __shared__ uint32_t lds[kBsLdsMax];
+    const int idx = blockIdx.x;
+    const int fi = frame_of(first, n, idx);
+    const FrameDesc f = frames[fi];
+    const int local = idx - first[fi];
+    const int gx = (f.w + 63) / 64;
+    const int tx = local % gx, ty = local / gx;
+    switch (f.K) {
+        case 4: bs_tile<4, true>(f, tx, ty, threadIdx.x, lds, true); break;
+        case 8: bs_tile<8, true>(f, tx, ty, threadIdx.x, lds, true); break;
+        case 16: bs_tile<16, true>(f, tx, ty, threadIdx.x, lds, true); break;
+        case 32: bs_tile<32, true>(f, tx, ty, threadIdx.x, lds, true); break;
+        default: bs_tile<64, true>(f, tx, ty, threadIdx.x, lds, true); break;
+    }
+}
+
+__global__ void __launch_bounds__(kRegionThreads) k_mf_regions(const FrameDesc* frames) {
+    extern __shared__ uint32_t lds[];
+    const FrameDesc f = frames[blockIdx.x];
+    regions_body(f, lds);
+}
+
+template <int R>
+__global__ void __launch_bounds__(256) k_mf_cbf(const FrameDesc* frames, const int* first, int n) {
+    __shared__ uint32_t lds[CbfTile<R>::kLdsWords];
+    const int idx = blockIdx.x;
+    const int fi = frame_of(first, n, idx);
+    const FrameDesc f = frames[fi];
+    const int local = idx - first[fi];
+    const int gx = (f.w + kTileW - 1) / kTileW;
+    cbf_tile<R, true>(f, local % gx, local / gx, threadIdx.x, lds, true);
+}
+
+// `rows` consecutive image rows per workgroup, one after another.
+template <int Q>
+__global__ void __launch_bounds__(1024) k_mf_warp(const FrameDesc* frames, const int* first, int n, int rows) {
+    extern __shared__ uint32_t lds[];
+    const int idx = blockIdx.x;
+    const int fi = frame_of(first, n, idx);
+    const FrameDesc f = frames[fi];
+    const int y0 = (idx - first[fi]) * rows;
+    for (int k = 0; k < rows; ++k) {
+        const int y = y0 + k;
+        if (y >= f.h) break;
+        if (k) __syncthreads();  // the previous row's last LDS reads are done
+        warp_row<true, Q>(f, y, threadIdx.x, blockDim.x, lds, true);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
+
+hipError_t launch_staged(const FrameDesc* d_frames, const int* d_first, const StagedPlan& pl, hipStream_t s) {
+    const int n = pl.n;
+    const int* first_bs = d_first;
+    const int* first_cbf = d_first + (n + 1);
+    hipLaunchKernelGGL(k_mf_blockstats, dim3(pl.tiles_bs), dim3(256), 0, s, d_frames, first_bs, n);
+    hipLaunchKernelGGL(k_mf_regions, dim3(n), dim3(kRegionThreads), pl.regions_lds, s, d_frames);
+    switch (pl.r) {
+        case 0: hipLaunchKernelGGL(k_mf_cbf<0>, dim3(pl.tiles_cbf), dim3(256), 0, s, d_frames, first_cbf, n); break;
+        case 1: hipLaunchKernelGGL(k_mf_cbf<1>, dim3(pl.tiles_cbf), dim3(256), 0, s, d_frames, first_cbf, n); break;
+        case 2: hipLaunchKernelGGL(k_mf_cbf<2>, dim3(pl.tiles_cbf), dim3(256), 0, s, d_frames, first_cbf, n); break;
+        default: hipLaunchKernelGGL(k_mf_cbf<3>, dim3(pl.tiles_cbf), dim3(256), 0, s, d_frames, first_cbf, n); break;
+    }
+    for (int c = 0; c < pl.nclass; ++c) {
+        const int* fw = d_first + (size_t)(2 + c) * (n + 1);
+        const dim3 g(pl.cls_rows[c]), b(pl.cls_threads[c]);
+        switch (pl.cls_q[c]) {
+            case 1: hipLaunchKernelGGL(k_mf_warp<1>, g, b, pl.cls_lds[c], s, d_frames, fw, n, pl.warp_rows); break;
+            case 2: hipLaunchKernelGGL(k_mf_warp<2>, g, b, pl.cls_lds[c], s, d_frames, fw, n, pl.warp_rows); break;
+            default: hipLaunchKernelGGL(k_mf_warp<4>, g, b, pl.cls_lds[c], s, d_frames, fw, n, pl.warp_rows); break;
+        }
+    }
+    return hipGetLastError();
+}
 
 int batch_tasks(const FrameDesc& f, int phase, int* items, int* gx) {
     switch (phase) {
@@ -195,6 +294,10 @@ bool batch_width_ok(int w) {
 
 hipError_t prepare_batch_kernels() {
     hipError_t e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_regions), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_warp<1>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_warp<2>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mf_warp<4>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<0>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBatchLdsBytes)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<1>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBatchLdsBytes)) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<2>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBatchLdsBytes)) != hipSuccess) return e;

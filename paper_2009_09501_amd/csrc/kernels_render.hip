@@ -22,10 +22,12 @@ __global__ void __launch_bounds__(1024) k_warp(FrameDesc f) {
 // ---------------------------------------------------------------------------
 // host-side launch helpers
 
-bool warp_shape(int w, WarpShape* out) {
+bool warp_shape(int w, WarpShape* out) { return warp_shape_cap(w, 256, out); }
+
+bool warp_shape_cap(int w, int cap, WarpShape* out) {
     const int quads = (w + 3) / 4;
     int q = 1;
-    while (q < 4 && (quads + q - 1) / q > 256) q *= 2;
+    while (q < 4 && (quads + q - 1) / q > cap) q *= 2;
     int threads = ((quads + q - 1) / q + 63) / 64 * 64;
     if (threads > 1024) return false;
     const size_t lds = warp_lds_bytes(w, threads, q);

@@ -28,6 +28,26 @@ struct BatchDesc {
     int ntask;
 };
 
+// Launch plan of the staged form: per-stage workgroup counts and the warp
+// launches, one per distinct (lanes, quads per lane) shape among the frames.
+constexpr int kMaxWarpClasses = 24;
+struct StagedPlan {
+    int n = 0;
+    int tiles_bs = 0, tiles_cbf = 0;
+    size_t regions_lds = 0;
+    int r = 2;
+    int warp_rows = 1;  // image rows per warp workgroup
+    int nclass = 0;
+    int cls_threads[kMaxWarpClasses];
+    int cls_q[kMaxWarpClasses];
+    size_t cls_lds[kMaxWarpClasses];
+    int cls_rows[kMaxWarpClasses];  // workgroups of each warp launch
+};
+
+// d_first: (2 + nclass) tables of n + 1 ints: first workgroup of each frame in
+// the block-statistics launch, the depth-filter launch, then each warp launch.
+hipError_t launch_staged(const FrameDesc* d_frames, const int* d_first, const StagedPlan& plan, hipStream_t s);
+
 // Device scratch of one job: block tables (gw * gh entries each) and the
 // filtered-depth image (w * h bytes).
 struct JobScratch {

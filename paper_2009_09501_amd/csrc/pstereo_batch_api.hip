@@ -2,6 +2,7 @@
 // persistent kernel launch (kernels_batch.hip).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -41,6 +42,12 @@ struct pstereo_batch {
     // the prepared batch
     int n = 0, ntask = 0, r = 2;
     bool prepared = false;
+    // tuning and the staged form's tables
+    pstereo_batch_tuning tune{PSTEREO_BATCH_STAGED, 256, 1, 0};
+    int cus = 0;
+    int* d_first = nullptr;
+    int* h_first = nullptr;
+    pstereo::StagedPlan plan;
     hipStream_t stream = nullptr;
     std::string err;
 };
@@ -83,6 +90,8 @@ void batch_free(pstereo_batch* b) {
     (void)hipFree(b->d_segs);
     (void)hipFree(b->d_need);
     (void)hipFree(b->d_ctr);
+    (void)hipFree(b->d_first);
+    (void)hipHostFree(b->h_first);
     (void)hipFree(b->d_stats);
     (void)hipFree(b->d_binfo);
     (void)hipFree(b->d_labels);
@@ -117,13 +126,17 @@ int batch_create_internal(pstereo_ctx* ctx, int max_jobs, int64_t max_pixels, bo
         delete b;
         return PSTEREO_E_DEVICE;
     }
-    b->grid = prop.multiProcessorCount;  // one 1024-lane workgroup per CU
+    b->cus = prop.multiProcessorCount;
+    b->grid = b->cus;  // fused form: one 1024-lane workgroup per CU
+    const size_t first_ints = (size_t)(2 + pstereo::kMaxWarpClasses) * (max_jobs + 1);
     const size_t nb = PSTEREO_MAX_BLOCKS;
     const size_t df_bytes = (size_t)max_pixels + 256 * (size_t)max_jobs;
     bool ok = hipMalloc(&b->d_frames, sizeof(FrameDesc) * max_jobs) == hipSuccess &&
               hipMalloc(&b->d_segs, sizeof(BatchSeg) * 4 * max_jobs) == hipSuccess &&
               hipMalloc(&b->d_need, sizeof(int) * 4 * max_jobs) == hipSuccess &&
               hipMalloc(&b->d_ctr, sizeof(uint32_t) * (2 + 4 * max_jobs)) == hipSuccess &&
+              hipMalloc(&b->d_first, sizeof(int) * first_ints) == hipSuccess &&
+              hipHostMalloc(&b->h_first, sizeof(int) * first_ints, hipHostMallocDefault) == hipSuccess &&
               (!own_scratch || (hipMalloc(&b->d_stats, sizeof(uint32_t) * nb * max_jobs) == hipSuccess &&
                                 hipMalloc(&b->d_binfo, sizeof(uint2) * nb * max_jobs) == hipSuccess &&
                                 hipMalloc(&b->d_labels, sizeof(int32_t) * nb * max_jobs) == hipSuccess &&
@@ -198,7 +211,8 @@ int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, con
         const pstereo_job& j = jobs[i];
         if (!j.frame || j.w < 1 || j.h < 1) return bfail(b, PSTEREO_E_INVALID, "job %d: bad frame or size", i);
         if (j.w % 4 != 0) return bfail(b, PSTEREO_E_UNSUPPORTED, "job %d: width %d not a multiple of 4", i, j.w);
-        if (!pstereo::batch_width_ok(j.w)) return bfail(b, PSTEREO_E_UNSUPPORTED, "job %d: width %d too large", i, j.w);
+        if (b->tune.mode == PSTEREO_BATCH_FUSED && !pstereo::batch_width_ok(j.w))
+            return bfail(b, PSTEREO_E_UNSUPPORTED, "job %d: width %d too large for the fused form", i, j.w);
         const uintptr_t al = (uintptr_t)j.frame | (uintptr_t)j.out_left | (uintptr_t)j.out_right | (uintptr_t)j.out_anaglyph;
         if (al % 4) return bfail(b, PSTEREO_E_UNSUPPORTED, "job %d: buffers must be 4-byte aligned", i);
         const int B = j.max_disparity < 0 ? (2 * j.w + 50) / 100 : j.max_disparity;
@@ -265,34 +279,92 @@ int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, con
             if (outs[a].p < outs[c].p + outs[c].n && outs[c].p < outs[a].p + outs[a].n)
                 return bfail(b, PSTEREO_E_ALIAS, "two outputs overlap");
     }
-    // tasks in claim order: (blockstats, regions) of every frame, then
-    // (depth filter, warp) of every frame
-    int task = 0, s = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int i = 0; i < n; ++i) {
-            for (int ph = 2 * pass; ph < 2 * pass + 2; ++ph) {
-                BatchSeg sg;
-                sg.frame = i;
-                sg.phase = ph;
-                sg.first = task;
-                sg.ntask = pstereo::batch_tasks(b->h_frames[i], ph, &sg.items, &sg.gx);
-                b->h_need[4 * i + ph] = sg.ntask;
-                b->h_segs[s++] = sg;
-                task += sg.ntask;
-            }
-        }
-    }
     b->n = n;
-    b->ntask = task;
     b->r = p.cbf_radius;
     b->stream = p.stream ? (hipStream_t)p.stream : pstereo::ctx_stream(b->ctx);
     hipStream_t st = b->stream;
     hipError_t e;
-    if ((e = hipMemcpyAsync(b->d_frames, b->h_frames, sizeof(FrameDesc) * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(b->d_segs, b->h_segs, sizeof(BatchSeg) * 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(b->d_need, b->h_need, sizeof(int) * 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipEventRecord(b->staged, st)) != hipSuccess)
-        return bfail(b, PSTEREO_E_DEVICE, "table upload: %s", hipGetErrorString(e));
+    if (b->tune.mode == PSTEREO_BATCH_FUSED) {
+        // tasks in claim order: (blockstats, regions) of every frame, then
+        // (depth filter, warp) of every frame
+        int task = 0, s = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i = 0; i < n; ++i) {
+                for (int ph = 2 * pass; ph < 2 * pass + 2; ++ph) {
+                    BatchSeg sg;
+                    sg.frame = i;
+                    sg.phase = ph;
+                    sg.first = task;
+                    sg.ntask = pstereo::batch_tasks(b->h_frames[i], ph, &sg.items, &sg.gx);
+                    b->h_need[4 * i + ph] = sg.ntask;
+                    b->h_segs[s++] = sg;
+                    task += sg.ntask;
+                }
+            }
+        }
+        b->ntask = task;
+        b->grid = b->tune.fused_grid > 0 ? b->tune.fused_grid : b->cus;
+        if ((e = hipMemcpyAsync(b->d_frames, b->h_frames, sizeof(FrameDesc) * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(b->d_segs, b->h_segs, sizeof(BatchSeg) * 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(b->d_need, b->h_need, sizeof(int) * 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipEventRecord(b->staged, st)) != hipSuccess)
+            return bfail(b, PSTEREO_E_DEVICE, "table upload: %s", hipGetErrorString(e));
+    } else {
+        // staged form: per-stage first-workgroup tables and the warp shapes
+        pstereo::StagedPlan& pl = b->plan;
+        pl = pstereo::StagedPlan();
+        pl.n = n;
+        pl.r = p.cbf_radius;
+        pl.warp_rows = b->tune.warp_rows;
+        int* fb = b->h_first;
+        int* fc = b->h_first + (n + 1);
+        int nb_max = 1;
+        std::vector<int> cls(n);
+        for (int i = 0; i < n; ++i) {
+            const FrameDesc& f = b->h_frames[i];
+            int items, gx;
+            fb[i] = pl.tiles_bs;
+            (void)pstereo::batch_tasks(f, 0, &items, &gx);  // block-statistics tiles
+            pl.tiles_bs += items;
+            fc[i] = pl.tiles_cbf;
+            (void)pstereo::batch_tasks(f, 2, &items, &gx);  // depth-filter tiles
+            pl.tiles_cbf += items;
+            nb_max = std::max(nb_max, f.gw * f.gh);
+            pstereo::WarpShape ws;
+            if (!pstereo::warp_shape_cap(f.w, b->tune.warp_lanes, &ws))
+                return bfail(b, PSTEREO_E_UNSUPPORTED, "job %d: width %d too large for the row warp", i, f.w);
+            int c = 0;
+            while (c < pl.nclass && !(pl.cls_threads[c] == ws.threads && pl.cls_q[c] == ws.quads)) ++c;
+            if (c == pl.nclass) {
+                if (pl.nclass == pstereo::kMaxWarpClasses) return bfail(b, PSTEREO_E_UNSUPPORTED, "too many row shapes");
+                pl.cls_threads[c] = ws.threads;
+                pl.cls_q[c] = ws.quads;
+                pl.cls_lds[c] = 0;
+                ++pl.nclass;
+            }
+            pl.cls_lds[c] = std::max(pl.cls_lds[c], ws.lds_bytes);
+            cls[i] = c;
+        }
+        fb[n] = pl.tiles_bs;
+        fc[n] = pl.tiles_cbf;
+        pl.regions_lds = pstereo::regions_lds_bytes(nb_max);
+        for (int c = 0; c < pl.nclass; ++c) {
+            int* fw = b->h_first + (size_t)(2 + c) * (n + 1);
+            int acc = 0;
+            for (int i = 0; i < n; ++i) {
+                fw[i] = acc;
+                if (cls[i] == c) acc += (b->h_frames[i].h + pl.warp_rows - 1) / pl.warp_rows;
+            }
+            fw[n] = acc;
+            pl.cls_rows[c] = acc;
+        }
+        b->ntask = pl.tiles_bs + n + pl.tiles_cbf;
+        if ((e = hipMemcpyAsync(b->d_frames, b->h_frames, sizeof(FrameDesc) * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(b->d_first, b->h_first, sizeof(int) * (2 + pl.nclass) * (n + 1), hipMemcpyHostToDevice,
+                                st)) != hipSuccess ||
+            (e = hipEventRecord(b->staged, st)) != hipSuccess)
+            return bfail(b, PSTEREO_E_DEVICE, "table upload: %s", hipGetErrorString(e));
+    }
     b->staged_pending = true;
     b->prepared = true;
     return PSTEREO_OK;
@@ -331,7 +403,8 @@ int pstereo_batch_launch(pstereo_batch* b, void* stream) {
     bd.nframes = b->n;
     bd.ntask = b->ntask;
     hipStream_t st = stream ? (hipStream_t)stream : b->stream;
-    hipError_t e = pstereo::launch_batch(bd, b->r, b->grid, st);
+    hipError_t e = b->tune.mode == PSTEREO_BATCH_FUSED ? pstereo::launch_batch(bd, b->r, b->grid, st)
+                                                        : pstereo::launch_staged(b->d_frames, b->d_first, b->plan, st);
     if (e != hipSuccess) return bfail(b, PSTEREO_E_DEVICE, "batch launch: %s", hipGetErrorString(e));
     return PSTEREO_OK;
 }
@@ -344,11 +417,97 @@ int pstereo_batch_run(pstereo_batch* b, const pstereo_job* jobs, int n, const ps
     if (p && (p->flags & PSTEREO_SYNC)) {
         if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, PSTEREO_E_DEVICE, "stream synchronize");
         uint32_t aborted = 0;
-        if (hipMemcpy(&aborted, b->d_ctr + 1 + 4 * b->n, sizeof(aborted), hipMemcpyDeviceToHost) != hipSuccess)
+        if (b->tune.mode == PSTEREO_BATCH_FUSED && hipMemcpy(&aborted, b->d_ctr + 1 + 4 * b->n, sizeof(aborted), hipMemcpyDeviceToHost) != hipSuccess)
             return bfail(b, PSTEREO_E_DEVICE, "abort word read-back");
         if (aborted) return bfail(b, PSTEREO_E_DEVICE, "a dependency wait timed out; outputs are incomplete");
     }
     return PSTEREO_OK;
+}
+
+int pstereo_batch_set_tuning(pstereo_batch* b, const pstereo_batch_tuning* t) {
+    if (!b || !t) return PSTEREO_E_INVALID;
+    b->err.clear();
+    if (t->mode != PSTEREO_BATCH_STAGED && t->mode != PSTEREO_BATCH_FUSED)
+        return bfail(b, PSTEREO_E_INVALID, "unknown batch mode %d", t->mode);
+    if (t->warp_lanes < 64 || t->warp_lanes > 1024 || t->warp_lanes % 64)
+        return bfail(b, PSTEREO_E_INVALID, "warp_lanes %d not a multiple of 64 in 64..1024", t->warp_lanes);
+    if (t->warp_rows < 1 || t->warp_rows > 8) return bfail(b, PSTEREO_E_INVALID, "warp_rows %d outside 1..8", t->warp_rows);
+    if (t->fused_grid < 0 || t->fused_grid > 65536) return bfail(b, PSTEREO_E_INVALID, "fused_grid out of range");
+    b->tune = *t;
+    b->prepared = false;  // the tables depend on the tuning
+    return PSTEREO_OK;
+}
+
+int pstereo_batch_get_tuning(const pstereo_batch* b, pstereo_batch_tuning* t) {
+    if (!b || !t) return PSTEREO_E_INVALID;
+    *t = b->tune;
+    return PSTEREO_OK;
+}
+
+int pstereo_batch_autotune(pstereo_batch* b, const pstereo_job* jobs, int n, const pstereo_params* p, int reps,
+                           pstereo_batch_tuning* best, double* best_ms, pstereo_batch_trial* trials, int cap,
+                           int* n_trials) {
+    if (!b || reps < 1 || reps > 1000 || cap < 0 || (cap > 0 && !trials)) return PSTEREO_E_INVALID;
+    // candidates: the staged form over row-workgroup lane caps and rows per
+    // workgroup, and the fused form with one workgroup per compute unit
+    std::vector<pstereo_batch_tuning> cand;
+    static const int lanes[4] = {128, 256, 512, 1024};
+    static const int rows[3] = {1, 2, 4};
+    for (int l : lanes)
+        for (int r : rows) cand.push_back({PSTEREO_BATCH_STAGED, l, r, 0});
+    cand.push_back({PSTEREO_BATCH_FUSED, 256, 1, 0});
+    const pstereo_batch_tuning saved = b->tune;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipSetDevice(b->device);
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipGetLastError();
+        if (e0) (void)hipEventDestroy(e0);
+        return bfail(b, PSTEREO_E_DEVICE, "event create");
+    }
+    double best_t = -1;
+    pstereo_batch_tuning best_c = saved;
+    int nt = 0, rc = PSTEREO_OK;
+    for (const pstereo_batch_tuning& c : cand) {
+        b->tune = c;
+        int r = pstereo_batch_prepare(b, jobs, n, p);
+        if (r == PSTEREO_E_UNSUPPORTED) continue;  // e.g. a width the fused form cannot take
+        if (r != PSTEREO_OK) { rc = r; break; }
+        hipStream_t st = b->stream;
+        if ((r = pstereo_batch_launch(b, nullptr)) != PSTEREO_OK) { rc = r; break; }  // warm-up
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = bfail(b, PSTEREO_E_DEVICE, "event record"); break; }
+        for (int k = 0; k < reps && r == PSTEREO_OK; ++k) r = pstereo_batch_launch(b, nullptr);
+        if (r != PSTEREO_OK) { rc = r; break; }
+        float ms = 0;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = bfail(b, PSTEREO_E_DEVICE, "event timing");
+            break;
+        }
+        const double t = ms / reps;
+        if (nt < cap) {
+            trials[nt].tuning = c;
+            trials[nt].ms = t;
+        }
+        ++nt;
+        if (best_t < 0 || t < best_t) {
+            best_t = t;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (n_trials) *n_trials = nt;
+    if (rc != PSTEREO_OK || best_t < 0) {
+        b->tune = saved;
+        b->prepared = false;
+        return rc != PSTEREO_OK ? rc : bfail(b, PSTEREO_E_UNSUPPORTED, "no candidate could run this batch");
+    }
+    // leave the batch prepared with the winner
+    b->tune = best_c;
+    rc = pstereo_batch_prepare(b, jobs, n, p);
+    if (best) *best = best_c;
+    if (best_ms) *best_ms = best_t;
+    return rc;
 }
 
 }  // extern "C"

@@ -44,6 +44,9 @@ struct LaunchSpec {
 // Launch specifications (kernels_depth.hip, kernels_render.hip); func is null
 // for an unsupported combination.
 bool warp_shape(int w, WarpShape* out);
+// The fewest quads per lane (1, 2, 4) that keep the lanes of a row within
+// cap (else four quads per lane, up to 1024 lanes).
+bool warp_shape_cap(int w, int cap, WarpShape* out);
 LaunchSpec spec_blockstats(const FrameDesc& f);
 LaunchSpec spec_regions(const FrameDesc& f);
 LaunchSpec spec_cbf(const FrameDesc& f);

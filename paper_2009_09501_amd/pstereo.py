@@ -29,6 +29,9 @@ PSTEREO_PROFILE = 0x4
 
 PSTEREO_MAX_BLOCKS = 32768
 
+PSTEREO_BATCH_STAGED = 0
+PSTEREO_BATCH_FUSED = 1
+
 PSTEREO_SERVE_BATCH = 0
 PSTEREO_SERVE_PLAIN = 1
 PSTEREO_STREAM_HOST_IO = 0x1
@@ -43,6 +46,7 @@ EXPORTED = [
     "pstereo_video_begin", "pstereo_video_frame", "pstereo_video_end",
     "pstereo_batch_create", "pstereo_batch_prepare", "pstereo_batch_launch", "pstereo_batch_run",
     "pstereo_batch_destroy", "pstereo_batch_last_error",
+    "pstereo_batch_set_tuning", "pstereo_batch_get_tuning", "pstereo_batch_autotune",
     "pstereo_server_create", "pstereo_server_open_stream", "pstereo_server_close_stream",
     "pstereo_server_submit", "pstereo_server_poll", "pstereo_server_drain", "pstereo_server_info",
     "pstereo_server_destroy", "pstereo_server_last_error",
@@ -76,6 +80,22 @@ class PstereoJob(ctypes.Structure):
         ("out_anaglyph", ctypes.c_void_p),
         ("max_disparity", ctypes.c_int32),
     ]
+
+
+class PstereoBatchTuning(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int32),
+        ("warp_lanes", ctypes.c_int32),
+        ("warp_rows", ctypes.c_int32),
+        ("fused_grid", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class PstereoBatchTrial(ctypes.Structure):
+    _fields_ = [("tuning", PstereoBatchTuning), ("ms", ctypes.c_double)]
 
 
 class PstereoCompletion(ctypes.Structure):
@@ -143,6 +163,14 @@ def load_library():
     lib.pstereo_batch_destroy.restype = ci
     lib.pstereo_batch_last_error.argtypes = [vp]
     lib.pstereo_batch_last_error.restype = ctypes.c_char_p
+    T = ctypes.POINTER(PstereoBatchTuning)
+    lib.pstereo_batch_set_tuning.argtypes = [vp, T]
+    lib.pstereo_batch_set_tuning.restype = ci
+    lib.pstereo_batch_get_tuning.argtypes = [vp, T]
+    lib.pstereo_batch_get_tuning.restype = ci
+    lib.pstereo_batch_autotune.argtypes = [vp, J, ci, P, ci, T, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(PstereoBatchTrial), ci, ctypes.POINTER(ci)]
+    lib.pstereo_batch_autotune.restype = ci
     lib.pstereo_server_create.argtypes = [ci, ctypes.c_int64, ci, ci, ci, ctypes.POINTER(vp)]
     lib.pstereo_server_create.restype = ci
     lib.pstereo_server_open_stream.argtypes = [vp, ci, ci, ci, ci, cu, ctypes.POINTER(ci)]
@@ -307,6 +335,33 @@ def pstereo_batch_last_error(b: int) -> str:
 
 
 # ------------------------------------------------------- torch convenience
+def pstereo_batch_set_tuning(b: int, mode: int = PSTEREO_BATCH_STAGED, warp_lanes: int = 256,
+                             warp_rows: int = 1, fused_grid: int = 0, check: bool = True) -> int:
+    t = PstereoBatchTuning(mode, warp_lanes, warp_rows, fused_grid)
+    rc = load_library().pstereo_batch_set_tuning(b, ctypes.byref(t))
+    return _bcheck(rc, b) if check else rc
+
+
+def pstereo_batch_get_tuning(b: int) -> dict:
+    t = PstereoBatchTuning()
+    _bcheck(load_library().pstereo_batch_get_tuning(b, ctypes.byref(t)), b)
+    return t.as_dict()
+
+
+def pstereo_batch_autotune(b: int, jobs, n: int, params: Optional[PstereoParams], reps: int = 3):
+    """Time every candidate tuning on these jobs; the batch is left prepared
+    with the fastest.  Returns (best tuning dict, best ms, [trial dicts])."""
+    best = PstereoBatchTuning()
+    best_ms = ctypes.c_double()
+    trials = (PstereoBatchTrial * 64)()
+    nt = ctypes.c_int()
+    _bcheck(load_library().pstereo_batch_autotune(b, jobs, n, ctypes.byref(params) if params is not None else None,
+                                                  reps, ctypes.byref(best), ctypes.byref(best_ms), trials, 64,
+                                                  ctypes.byref(nt)), b)
+    tried = [dict(trials[i].tuning.as_dict(), ms=trials[i].ms) for i in range(min(nt.value, 64))]
+    return best.as_dict(), best_ms.value, tried
+
+
 def _scheck(rc: int, srv):
     if rc != PSTEREO_OK:
         m = load_library().pstereo_server_last_error(srv)

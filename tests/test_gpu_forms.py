@@ -72,15 +72,25 @@ BATCH_SIZES = [(1920, 1080), (640, 360), (1280, 720), (3840, 2160), (648, 364), 
                (7680, 4320)]
 
 
-def test_batch_matches_plain_and_oracle(ctx, oracle_mod):
+TUNINGS = {
+    "staged": dict(mode=0, warp_lanes=256, warp_rows=1),
+    "staged_wide_rows3": dict(mode=0, warp_lanes=1024, warp_rows=3),
+    "staged_narrow_rows8": dict(mode=0, warp_lanes=64, warp_rows=8),
+    "fused": dict(mode=1),
+}
+
+
+@pytest.mark.parametrize("tuning", list(TUNINGS))
+def test_batch_matches_plain_and_oracle(ctx, oracle_mod, tuning):
     from paper_2009_09501_amd import pstereo_params_init
     from paper_2009_09501_amd.pstereo import (make_jobs, pstereo_batch_create, pstereo_batch_destroy,
-                                              pstereo_batch_run)
+                                              pstereo_batch_run, pstereo_batch_set_tuning)
     host, frames = _batch_frames(BATCH_SIZES, 700)
     outs = [[torch.zeros_like(f) for _ in range(3)] for f in frames]
-    print(f"batch of {len(frames)} frames: {BATCH_SIZES}", flush=True)
+    print(f"batch ({tuning}) of {len(frames)} frames: {BATCH_SIZES}", flush=True)
     b = pstereo_batch_create(ctx.handle, 16, sum(w * h for w, h in BATCH_SIZES) + 1024)
     try:
+        pstereo_batch_set_tuning(b, **TUNINGS[tuning])
         p = pstereo_params_init()
         p.stream = torch.cuda.current_stream().cuda_stream
         jobs = make_jobs(frames, outs)
@@ -97,10 +107,11 @@ def test_batch_matches_plain_and_oracle(ctx, oracle_mod):
     assert np.array_equal(outs[1][0].cpu().numpy(), ora.L)
 
 
-def test_batch_relaunch_and_graph_replay(ctx):
+@pytest.mark.parametrize("tuning", ["staged", "fused"])
+def test_batch_relaunch_and_graph_replay(ctx, tuning):
     from paper_2009_09501_amd import pstereo_params_init
     from paper_2009_09501_amd.pstereo import (make_jobs, pstereo_batch_create, pstereo_batch_destroy,
-                                              pstereo_batch_launch, pstereo_batch_prepare)
+                                              pstereo_batch_launch, pstereo_batch_prepare, pstereo_batch_set_tuning)
     sizes = [(1280, 720), (640, 360), (1920, 1080)]
     _, frames = _batch_frames(sizes, 900)
     outs = [[torch.zeros_like(f) for _ in range(3)] for f in frames]
@@ -108,6 +119,7 @@ def test_batch_relaunch_and_graph_replay(ctx):
     b = pstereo_batch_create(ctx.handle, 4, sum(w * h for w, h in sizes))
     s = torch.cuda.Stream()
     try:
+        pstereo_batch_set_tuning(b, **TUNINGS[tuning])
         p = pstereo_params_init()
         p.stream = s.cuda_stream
         jobs = make_jobs(frames, outs)
@@ -136,6 +148,40 @@ def test_batch_relaunch_and_graph_replay(ctx):
             for o, r in zip(outs, refs):
                 for got, want in zip(o, r):
                     assert np.array_equal(got.cpu().numpy(), want), f"graph replay {rep}"
+    finally:
+        torch.cuda.synchronize()
+        pstereo_batch_destroy(b)
+
+
+def test_batch_autotune_picks_a_candidate_and_stays_exact(ctx):
+    from paper_2009_09501_amd import pstereo_params_init
+    from paper_2009_09501_amd.pstereo import (make_jobs, pstereo_batch_autotune, pstereo_batch_create,
+                                              pstereo_batch_destroy, pstereo_batch_get_tuning,
+                                              pstereo_batch_launch)
+    sizes = [(1280, 720), (640, 360), (1920, 1080), (2560, 1440)]
+    _, frames = _batch_frames(sizes, 950)
+    refs = [_plain(ctx, f, max_disparity=synth.default_disparity(f.shape[1])) for f in frames]
+    outs = [[torch.zeros_like(f) for _ in range(3)] for f in frames]
+    s = torch.cuda.Stream()
+    b = pstereo_batch_create(ctx.handle, 4, sum(w * h for w, h in sizes))
+    try:
+        p = pstereo_params_init()
+        p.stream = s.cuda_stream
+        jobs = make_jobs(frames, outs)
+        best, best_ms, trials = pstereo_batch_autotune(b, jobs, len(frames), p, reps=2)
+        print(f"autotune: best {best} {best_ms:.3f} ms over {len(trials)} candidates", flush=True)
+        assert len(trials) == 13
+        assert best_ms == min(t["ms"] for t in trials)
+        assert pstereo_batch_get_tuning(b) == best
+        for o in outs:
+            for x in o:
+                x.zero_()
+        torch.cuda.synchronize()
+        pstereo_batch_launch(b, s)
+        s.synchronize()
+        for o, r in zip(outs, refs):
+            for got, want in zip(o, r):
+                assert np.array_equal(got.cpu().numpy(), want)
     finally:
         torch.cuda.synchronize()
         pstereo_batch_destroy(b)
