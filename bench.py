@@ -262,6 +262,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="video,batch,serve",
                     help="extra launch forms measured after the plain path (video, batch, serve; empty = none)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of a known size (to scale HBM byte counters)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-burst", type=int, default=16)
     ap.add_argument("--form-steps", type=int, default=60)
@@ -276,6 +278,18 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        # 512 MiB device-to-device copies: a kernel whose HBM traffic is known
+        # (read 512 MiB + write 512 MiB per launch)
+        n = 512 << 20
+        src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": n, "bytes_written": n, "launches": 10}), flush=True)
+        return 0
 
     import synth
     from paper_2009_09501_amd import PSTEREO_PROFILE, Context, pstereo_profile_collect

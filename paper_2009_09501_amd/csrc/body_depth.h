@@ -223,8 +223,32 @@ __device__ __forceinline__ void uf_unite_s(uint32_t* parent, uint32_t a, uint32_
     }
 }
 
+// The value of v, opaque to the optimiser: per-block indices derived from it
+// are recomputed where they are used instead of being held in registers
+// across the whole kernel.
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Exact floor(n / d) for n, d < 2^16 from m = ceil(2^32 / d) (d >= 2): the
+// product overshoots n / d by less than n / 2^32 < 1 / d, which never carries
+// past the next integer.
+__device__ __forceinline__ uint32_t div_u16(uint32_t n, uint32_t m, uint32_t d) {
+    return d == 1 ? n : __umulhi(n, m);
+}
+
 // Region grouping of one frame on a whole 1024-lane workgroup; lds: the
 // regions_lds_bytes(gw * gh) bytes of dynamic LDS.
+//
+// Lane t owns the 32 contiguous blocks [32t, 32t + 32).  Row segments (runs
+// of right-linked blocks) are formed by a prefix-max scan, rows are joined by
+// union-find in LDS only where the pair of segments changes along a row, and
+// the label of a component (its smallest block index, always a segment start)
+// is found at the root.  The label's own word then collects the lowest block
+// row + 1 (low half, atomicMax) and the block count (high half, atomicAdd,
+// after the rows); the lane owning the label block turns that into the
+// region's depth.  Edge blocks are components of their own.
 __device__ __forceinline__ void regions_body(const FrameDesc& f, uint32_t* lds) {
     const int gw = f.gw, gh = f.gh, nb = gw * gh;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -235,55 +259,100 @@ __device__ __forceinline__ void regions_body(const FrameDesc& f, uint32_t* lds) 
     uint32_t* eb = ldb + kRegionThreads;              // edge bits
     uint32_t* scan = eb + kRegionThreads;             // NW words
     uint32_t* misc = scan + NW;                       // [0]: background key
+    uint32_t* binfo_w = reinterpret_cast<uint32_t*>(f.binfo);
 
-    // 1. link / edge bits, strided over the blocks so the loads coalesce; a
-    // wave's 64 bits go to two bitmap words through ballots.  The block column
-    // advances by 1024 mod gw per step (no division in the loop).
-    const int step_x = kRegionThreads % gw;
-    int bx = t % gw;
-#pragma unroll 8
-    for (int i = 0; i < kRegionPer; ++i) {
-        const int b = i * kRegionThreads + t;
-        bool e = true, lr = false, ld = false;
-        if (b < nb) {
-            const uint32_t s = f.stats[b];
-            parent[pidx(b)] = b;
-            e = (s >> 24) != 0;
-            if (!e && bx + 1 < gw) {
-                const uint32_t n = f.stats[b + 1];
-                lr = !(n >> 24) && mean_l1(s, n) <= f.tau;
-            }
-            if (!e && b + gw < nb) {
-                const uint32_t n = f.stats[b + gw];
-                ld = !(n >> 24) && mean_l1(s, n) <= f.tau;
-            }
+    // 1. block statistics into LDS (strided, coalesced loads, all in flight),
+    // and the statistics half of the block table
+    {
+        uint32_t sv[kRegionPer];
+#pragma unroll
+        for (int i = 0; i < kRegionPer; ++i) {
+            const int b = i * kRegionThreads + t;
+            sv[i] = b < nb ? f.stats[b] : 0u;
         }
-        bx += step_x;
-        if (bx >= gw) bx -= gw;
-        const unsigned long long mr = __ballot(lr), md = __ballot(ld), me = __ballot(e);
-        if (lane == 0) {
-            const int w0 = (i * kRegionThreads + wave * 64) >> 5;
-            lrb[w0] = (uint32_t)mr; lrb[w0 + 1] = (uint32_t)(mr >> 32);
-            ldb[w0] = (uint32_t)md; ldb[w0 + 1] = (uint32_t)(md >> 32);
-            eb[w0] = (uint32_t)me; eb[w0 + 1] = (uint32_t)(me >> 32);
+#pragma unroll
+        for (int i = 0; i < kRegionPer; ++i) {
+            const int b = i * kRegionThreads + t;
+            if (b < nb) {
+                parent[pidx(b)] = sv[i];
+                binfo_w[2 * b] = sv[i];
+            }
         }
     }
     if (t == 0) misc[0] = 0;
     __syncthreads();
 
-    // from here on lane t owns the 32 contiguous blocks [32t, 32t+32)
+    // 2. edge / right-link / down-link bits of the owned blocks, branch-free
+    // from LDS (lane t's words sit 33 apart: distinct banks across a wave).
+    // Blocks past the grid read as edges.
     const int b0 = t * kRegionPer;
     const int nown = max(0, min(kRegionPer, nb - b0));
-    const int bx0 = b0 % gw, by0 = b0 / gw;
-    const uint32_t lr = lrb[t], ld = ldb[t], emask = eb[t];
+    const uint32_t own_mask = nown >= 32 ? 0xFFFFFFFFu : ((1u << nown) - 1u);
+    uint32_t* own = parent + 33 * t;  // own[i] = parent[pidx(b0 + i)] for i < 32
+    int B0 = b0;
+    const uint32_t gwm = gw > 1 ? (uint32_t)((0x100000000ull + (uint32_t)gw - 1) / (uint32_t)gw) : 0u;
+    const uint32_t row0 = div_u16((uint32_t)min(b0, nb - 1 > 0 ? nb - 1 : 0), gwm, (uint32_t)gw);
+    uint32_t emask = 0, lr = 0, ld = 0;
+    {
+        constexpr uint32_t kPast = 0xFF000000u;
+        // bit i: block b0 + i ends its row (then it has no right neighbour);
+        // a run of 32 blocks crosses at most one row end when gw >= 32
+        uint32_t rowend = 0;
+        if (gw >= kRegionPer) {
+            const int wrap = (int)((row0 + 1) * (uint32_t)gw) - b0;  // next row's first block, from b0
+            if (wrap >= 1 && wrap <= kRegionPer) rowend = 1u << (wrap - 1);
+        } else {
+            for (int i = 0; i < kRegionPer; ++i)
+                if ((b0 + i + 1) % gw == 0) rowend |= 1u << i;
+        }
+        // two halves of 16 blocks: 33 loads in flight per half
+#pragma unroll
+        for (int h = 0; h < kRegionPer; h += 16) {
+            // unconditional loads from clamped (in-range) indices, then a
+            // select: no branch per load
+            uint32_t sv[17], dv[16];
+            const int last = nb - 1;
+#pragma unroll
+            for (int i = 0; i <= 16; ++i) {
+                const int b = b0 + h + i;
+                const uint32_t v = parent[pidx((uint32_t)min(b, last))];
+                sv[i] = b <= last ? v : kPast;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int b = b0 + h + i + gw;
+                const uint32_t v = parent[pidx((uint32_t)min(b, last))];
+                dv[i] = b <= last ? v : kPast;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint32_t sb = sv[i];
+                const bool e = (sb >> 24) != 0;
+                const bool row_end = (rowend >> (h + i)) & 1u;
+                const bool rok = !row_end && !(sv[i + 1] >> 24) &&
+                                 (int)__builtin_amdgcn_sad_u8(sb, sv[i + 1], 0u) <= f.tau;
+                const bool dok = !(dv[i] >> 24) && (int)__builtin_amdgcn_sad_u8(sb, dv[i], 0u) <= f.tau;
+                emask |= (uint32_t)e << (h + i);
+                lr |= (uint32_t)(!e && rok) << (h + i);
+                ld |= (uint32_t)(!e && dok) << (h + i);
+            }
+        }
+    }
+    emask = (uint32_t)opaque((int)(emask | ~own_mask));  // kept as one mask, not 32 flags
+    lr &= own_mask;
+    ld &= own_mask;
+    lrb[t] = lr;
+    ldb[t] = ld;
+    eb[t] = emask;
+    __syncthreads();
 
-    // 2. segments: start(b) = b is not right-linked from b - 1 (a row's first
+    B0 = opaque(b0);
+    // 3. segments: start(b) = b is not right-linked from b - 1 (a row's first
     // block never is: the last block of a row has no right link)
     const uint32_t prev_lr = t > 0 ? lrb[t - 1] : 0u;
     const uint32_t linked_from_left = (lr << 1) | (prev_lr >> 31);
-    const uint32_t own_mask = nown >= 32 ? 0xFFFFFFFFu : ((1u << nown) - 1u);
     const uint32_t starts = ~linked_from_left & own_mask;
-    const int last_start = starts ? b0 + 31 - __clz(starts) : -1;
+    const int last_start = starts ? B0 + 31 - __clz(starts) : -1;
     int incl = last_start;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -295,22 +364,22 @@ __device__ __forceinline__ void regions_body(const FrameDesc& f, uint32_t* lds) 
     int carry = __shfl_up(incl, 1);
     if (lane == 0) carry = -1;
     for (int v = 0; v < wave; ++v) carry = max(carry, (int)scan[v] - 1);
-    uint32_t node[kRegionPer];  // segment, then root, then label of each owned block
+    const int seg_in = carry;   // segment start of block b0 when b0 is not a start
 #pragma unroll
     for (int i = 0; i < kRegionPer; ++i) {
-        if ((starts >> i) & 1u) carry = b0 + i;
-        node[i] = (uint32_t)carry;
+        if ((starts >> i) & 1u) carry = B0 + i;
+        if (i < nown) own[i] = (uint32_t)carry;
     }
-#pragma unroll
-    for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown) parent[pidx(b0 + i)] = node[i];
     __syncthreads();
 
-    // 3. unions across rows, only where the segment pair changes along the row:
-    // skip b when b - 1 is in the same segment, also links down, and the
-    // blocks below b - 1 and b are right-linked too
+    B0 = opaque(b0);
+    // 4. unions across rows, only where the pair of segments changes along
+    // the row: skip b when b - 1 is in the same segment, also links down, and
+    // the blocks below b - 1 and b are right-linked too (then b and the block
+    // below it are already joined through b - 1).  Block b0 - 1 belongs to
+    // the previous lane; its bits are read from the shared bitmaps.
     {
-        const int c0 = b0 + gw;  // first block below the owned run
+        const int c0 = B0 + gw;  // first block below the owned run
         uint32_t below_lr = 0;
         if (ld) {
             const int w = c0 >> 5, sh = c0 & 31;
@@ -318,127 +387,147 @@ __device__ __forceinline__ void regions_body(const FrameDesc& f, uint32_t* lds) 
             const uint32_t hi = (w + 1 < kRegionThreads) ? lrb[w + 1] : 0u;
             below_lr = sh ? (lo >> sh) | (hi << (32 - sh)) : lo;  // bit i = right link of block c0 + i
         }
-        // skip bit i (i >= 1): ld(i-1) & lr(i-1) & below_lr(i-1)
         uint32_t todo = ld & ~((ld & lr & below_lr) << 1);
+        if ((todo & 1u) && t > 0 && ((ldb[t - 1] & prev_lr) >> 31)) {
+            const int c = B0 - 1 + gw;  // below block b0 - 1 (exists: b0 - 1 links down)
+            if ((lrb[c >> 5] >> (c & 31)) & 1u) todo &= ~1u;
+        }
         while (todo) {
             const int i = __ffs(todo) - 1;
             todo &= todo - 1;
-            uf_unite_s(parent, (uint32_t)(b0 + i), (uint32_t)(b0 + i + gw));
+            uf_unite_s(parent, (uint32_t)(B0 + i), (uint32_t)(B0 + i + gw));
         }
     }
     __syncthreads();
 
-    // roots: only segment starts search their tree; after a barrier each start
-    // records its root in its own entry and every other block reads the root
-    // off its segment start
+    B0 = opaque(b0);
+    // 5. labels of the segment starts: root, then the smallest start index of
+    // the tree collected at the root as 0x10000 | min, then published in the
+    // start's own word for the blocks of later lanes in the same segment
+    uint32_t lab[kRegionPer];  // root, then label of each segment start; then label of each owned block
 #pragma unroll
-    for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown && ((starts >> i) & 1u)) node[i] = uf_find_s(parent, b0 + i);
+    for (int i = 0; i < kRegionPer; ++i) lab[i] = ((starts >> i) & 1u) ? uf_find_s(parent, opaque(b0) + i) : 0u;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown && ((starts >> i) & 1u)) parent[pidx(b0 + i)] = node[i];
+        if (((starts >> i) & 1u) && lab[i] == (uint32_t)(B0 + i)) own[i] = 0xFFFFFFFFu;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown && !((starts >> i) & 1u)) node[i] = parent[pidx(node[i])];
-    __syncthreads();
-
-    // 4. label = smallest block index of the tree, kept at the root as 0x10000 | min
-#pragma unroll
-    for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown && node[i] == (uint32_t)(b0 + i)) parent[pidx(b0 + i)] = 0xFFFFFFFFu;
+        if ((starts >> i) & 1u) atomicMin(&parent[pidx(lab[i])], 0x10000u | (uint32_t)(B0 + i));
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown && (i == 0 || node[i] != node[i - 1]))
-            atomicMin(&parent[pidx(node[i])], 0x10000u | (uint32_t)(b0 + i));
+        if ((starts >> i) & 1u) lab[i] = parent[pidx(lab[i])] & 0xFFFFu;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown) node[i] = parent[pidx(node[i])] & 0xFFFFu;
-    __syncthreads();
-
-    // background key per label: (non-edge block count << 16) | (0xFFFF - label);
-    // the largest key is the largest region, ties to the smaller label
-#pragma unroll
-    for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown) parent[pidx(b0 + i)] = 0;
+        if ((starts >> i) & 1u) own[i] = lab[i];
     __syncthreads();
     {
-        uint32_t run = 0;
+        uint32_t cur = (nown && !(starts & 1u)) ? parent[pidx(seg_in)] : 0u;
 #pragma unroll
         for (int i = 0; i < kRegionPer; ++i) {
-            if (i >= nown) break;
-            if (!((emask >> i) & 1u)) ++run;
-            const bool flush = i + 1 == nown || i + 1 == kRegionPer || node[i + 1 < kRegionPer ? i + 1 : i] != node[i];
-            if (flush && run) {
-                atomicAdd(&parent[pidx(node[i])], run << 16);
-                atomicOr(&parent[pidx(node[i])], 0xFFFFu - node[i]);
+            if ((starts >> i) & 1u) cur = lab[i];
+            lab[i] = cur;
+        }
+    }
+    // piece ends: last owned block of a run of equal labels
+    uint32_t pend = 0;
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (i + 1 < kRegionPer && lab[i + 1] != lab[i]) pend |= 1u << i;
+    pend = (pend | (1u << (nown > 0 ? nown - 1 : 0))) & own_mask;
+    // label blocks owned here (the component's smallest block)
+    uint32_t lown = 0;
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if (lab[i] == (uint32_t)(B0 + i)) lown |= 1u << i;
+    lown &= own_mask;
+    __syncthreads();
+
+    B0 = opaque(b0);
+    // 6. per non-edge label: lowest row + 1, then the block count
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if ((lown >> i) & 1u) own[i] = 0;
+    __syncthreads();
+    const uint32_t nonedge_end = pend & ~emask;
+#pragma unroll
+    for (int i = 0; i < kRegionPer; ++i)
+        if ((nonedge_end >> i) & 1u)
+            atomicMax(&parent[pidx(lab[i])], div_u16((uint32_t)(B0 + i), gwm, (uint32_t)gw) + 1u);
+    __syncthreads();
+    {
+        // a piece is one edge block or all non-edge; its length is the
+        // distance to the previous piece end
+        int prev = -1;
+#pragma unroll
+        for (int i = 0; i < kRegionPer; ++i) {
+            if ((pend >> i) & 1u) {
+                if (!((emask >> i) & 1u)) atomicAdd(&parent[pidx(lab[i])], (uint32_t)(i - prev) << 16);
+                prev = i;
             }
-            if (flush) run = 0;
         }
     }
     __syncthreads();
-    uint32_t best = 0;
+
+    B0 = opaque(b0);
+    // 7. background = the largest non-edge region, ties to the smaller label
+    // (largest key (count << 16) | (0xFFFF - label)); each non-edge label's
+    // word becomes its region depth: the ramp at its lowest row
+    {
+        uint32_t best = 0;
+        const uint32_t lne = lown & ~emask;
 #pragma unroll
-    for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown) best = max(best, parent[pidx(b0 + i)]);
+        for (int i = 0; i < kRegionPer; ++i) {
+            if ((lne >> i) & 1u) {
+                const uint32_t w = own[i];
+                best = max(best, (w & 0xFFFF0000u) | (0xFFFFu - (uint32_t)(B0 + i)));
+                own[i] = (uint32_t)ramp((int)(w & 0xFFFFu) - 1, gh);
+            }
+        }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) best = max(best, (uint32_t)__shfl_xor((int)best, o));
-    if (lane == 0 && best) atomicMax(&misc[0], best);
+        for (int o = 32; o >= 1; o >>= 1) best = max(best, (uint32_t)__shfl_xor((int)best, o));
+        if (lane == 0 && best) atomicMax(&misc[0], best);
+    }
     __syncthreads();
     const uint32_t bgkey = misc[0];
-    const int bg = bgkey ? (int)(0xFFFFu - (bgkey & 0xFFFFu)) : -1;
+    const uint32_t bg = bgkey ? 0xFFFFu - (bgkey & 0xFFFFu) : 0xFFFFFFFFu;
 
-    // lowest block row (+1) per label, one atomic per run of equal labels
-    // (rows never decrease along the owned blocks)
-#pragma unroll
-    for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown) parent[pidx(b0 + i)] = 0;
-    __syncthreads();
+    B0 = opaque(b0);
+    // 8. block depth: edge and background blocks follow the row ramp, any
+    // other block takes its region's depth; packed (label << 8 | depth)
     {
-        int by = by0, bx = bx0;
-        uint32_t run_row = 0;
+        auto pack = [&](int i, int rr) {
+            const bool own_ramp = ((emask >> i) & 1u) || lab[i] == bg;
+            const int d = own_ramp ? rr : (int)parent[pidx(lab[i])];
+            lab[i] = (lab[i] << 8) | (uint32_t)d;
+        };
+        if (gw >= kRegionPer) {
+            // at most two rows: the ramps of both, picked per block
+            const int r0 = ramp((int)row0, gh), r1 = ramp((int)row0 + 1, gh);
+            const int wrap = (int)((row0 + 1) * (uint32_t)gw) - b0;
 #pragma unroll
-        for (int i = 0; i < kRegionPer; ++i) {
-            if (i >= nown) break;
-            if (!((emask >> i) & 1u)) run_row = (uint32_t)(by + 1);
-            const bool flush = i + 1 == nown || i + 1 == kRegionPer || node[i + 1 < kRegionPer ? i + 1 : i] != node[i];
-            if (flush && run_row) atomicMax(&parent[pidx(node[i])], run_row);
-            if (flush) run_row = 0;
-            if (++bx == gw) { bx = 0; ++by; }
-        }
-    }
-    __syncthreads();
-
-    // region depth: background and edge blocks follow the row ramp, any other
-    // region sits at the ramp of its lowest block row (ground contact).
-    // Packed (label << 8 | depth) per block, then written out in a strided
-    // pass so the global stores coalesce.
-    {
-        int by = by0, bx = bx0;
+            for (int i = 0; i < kRegionPer; ++i)
+                if (i < nown) pack(i, i < wrap ? r0 : r1);
+        } else {
 #pragma unroll
-        for (int i = 0; i < kRegionPer; ++i) {
-            if (i >= nown) break;
-            int d;
-            if (((emask >> i) & 1u) || (int)node[i] == bg) d = ramp(by, gh);
-            else d = ramp((int)parent[pidx(node[i])] - 1, gh);
-            node[i] = (node[i] << 8) | (uint32_t)d;
-            if (++bx == gw) { bx = 0; ++by; }
+            for (int i = 0; i < kRegionPer; ++i)
+                if (i < nown) pack(i, ramp((int)div_u16((uint32_t)(B0 + i), gwm, (uint32_t)gw), gh));
         }
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kRegionPer; ++i)
-        if (i < nown) parent[pidx(b0 + i)] = node[i];
+        if (i < nown) own[i] = lab[i];
     __syncthreads();
 #pragma unroll 8
     for (int i = 0; i < kRegionPer; ++i) {
         const int b = i * kRegionThreads + t;
         if (b < nb) {
             const uint32_t v = parent[pidx(b)];
-            f.binfo[b] = make_uint2(f.stats[b], v & 255u);
+            binfo_w[2 * b + 1] = v & 255u;
             f.labels[b] = (int32_t)(v >> 8);
         }
     }
