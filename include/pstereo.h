@@ -86,6 +86,14 @@ typedef struct pstereo_params {
     uint8_t *out_depth;       /* optional device uint8 [h][w]: filtered depth */
     uint8_t *out_depth_raw;   /* optional device uint8 [h][w]: depth before filtering */
     void *stream;             /* hipStream_t to enqueue on; NULL = context stream */
+    uint8_t *out_hsbs;        /* optional device RGB24 [h][w][3]: half side-by-side
+                                 frame (Section 5 names it beside the anaglyph):
+                                 left half = left view squeezed to floor(w/2)
+                                 columns, right half = right view squeezed to the
+                                 remaining ceil(w/2); column p of a half is the mean
+                                 of view columns 2p, 2p+1 rounded half up (column
+                                 w-1 alone for the last one of odd w).  Plain calls
+                                 only: the video, batch and server forms reject it */
 } pstereo_params;
 
 typedef struct pstereo_ctx pstereo_ctx;

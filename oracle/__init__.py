@@ -21,7 +21,7 @@ import numpy as np
 from .build import LIB_PATH, build_oracle
 
 __all__ = ["OracleResult", "synthesize", "auto_block", "disparity_lut",
-           "weight_tables", "luma", "load", "build_oracle"]
+           "weight_tables", "luma", "hsbs", "gather", "synthesize_gather", "load", "build_oracle"]
 
 _lib = None
 
@@ -53,6 +53,11 @@ def load():
     lib.oracle_weight_tables.argtypes = [_i32p, _i32p]
     lib.oracle_luma.restype = None
     lib.oracle_luma.argtypes = [_u8p, ctypes.c_int64, _u8p]
+    lib.oracle_gather.restype = ctypes.c_int
+    lib.oracle_gather.argtypes = [_u8p, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  _u8p, _u8p, _u8p]
+    lib.oracle_hsbs.restype = ctypes.c_int
+    lib.oracle_hsbs.argtypes = [_u8p, _u8p, ctypes.c_int, ctypes.c_int, _u8p]
     _lib = lib
     return lib
 
@@ -166,3 +171,35 @@ def luma(rgb: np.ndarray) -> np.ndarray:
     out = np.empty(rgb.shape[:-1], np.uint8)
     load().oracle_luma(_p(rgb, _u8p), n, _p(out, _u8p))
     return out
+
+
+def hsbs(L: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """Half side-by-side frame of a stereo pair (oracle_hsbs)."""
+    L = np.ascontiguousarray(L, dtype=np.uint8)
+    R = np.ascontiguousarray(R, dtype=np.uint8)
+    h, w, _ = L.shape
+    out = np.empty_like(L)
+    rc = load().oracle_hsbs(_p(L, _u8p), _p(R, _u8p), w, h, _p(out, _u8p))
+    if rc != 0:
+        raise ValueError(f"oracle_hsbs failed with code {rc}")
+    return out
+
+
+def gather(frame: np.ndarray, Df: np.ndarray, B: int, T: int = 150):
+    """(L, R, A) by the Fig. 3 gather at the destination's filtered depth."""
+    frame = np.ascontiguousarray(frame, dtype=np.uint8)
+    Df = np.ascontiguousarray(Df, dtype=np.uint8)
+    h, w, _ = frame.shape
+    L, R, A = (np.empty((h, w, 3), np.uint8) for _ in range(3))
+    rc = load().oracle_gather(_p(frame, _u8p), _p(Df, _u8p), w, h, B, T, _p(L, _u8p), _p(R, _u8p), _p(A, _u8p))
+    if rc != 0:
+        raise ValueError(f"oracle_gather failed with code {rc}")
+    return L, R, A
+
+
+def synthesize_gather(frame: np.ndarray, B: int, T: int = 150, K: int = 0, g: int = 24, tau: int = 24,
+                      r: int = 2, depth: Optional[np.ndarray] = None):
+    """The pipeline with the Fig. 3 gather in place of the z-buffered warp and
+    the fill: depth stages as in synthesize, then gather(frame, Df)."""
+    res = synthesize(frame, B, T, K, g, tau, r, depth=depth)
+    return gather(frame, res.Df, B, T)

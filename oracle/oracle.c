@@ -377,3 +377,79 @@ done:
     free(Lv); free(Rv);
     return rc;
 }
+
+/* ---------------------------------------------------------- HSBS output */
+/* Half side-by-side stereo frame, the second output format the paper's
+ * timing compares against the anaglyph (Section 5).  The format is only named;
+ * the reading: an image of the input's size whose left half holds the left
+ * view squeezed to half width and whose right half holds the right view
+ * squeezed likewise.  Column p of a half is the mean of columns 2p and 2p+1 of
+ * its view, per channel, rounded half up.  The left half has floor(w/2)
+ * columns and the right half the remaining ceil(w/2); for odd w the right
+ * half's last column has only column w-1 of the right view and copies it. */
+int oracle_hsbs(const uint8_t *L, const uint8_t *R, int w, int h, uint8_t *out) {
+    if (!L || !R || !out || w < 1 || h < 1) return ORC_E_INVALID;
+    const int hw = w / 2;
+    for (int y = 0; y < h; ++y) {
+        const uint8_t *lrow = L + (size_t)y * w * 3;
+        const uint8_t *rrow = R + (size_t)y * w * 3;
+        uint8_t *orow = out + (size_t)y * w * 3;
+        for (int p = 0; p < hw; ++p) {
+            for (int c = 0; c < 3; ++c) {
+                const int a = lrow[(2 * p) * 3 + c], b = lrow[(2 * p + 1) * 3 + c];
+                orow[p * 3 + c] = (uint8_t)((a + b + 1) / 2);
+            }
+        }
+        for (int p = 0; hw + p < w; ++p) {
+            for (int c = 0; c < 3; ++c) {
+                int v;
+                if (2 * p + 1 < w) {
+                    const int a = rrow[(2 * p) * 3 + c], b = rrow[(2 * p + 1) * 3 + c];
+                    v = (a + b + 1) / 2;
+                } else {
+                    v = rrow[(2 * p) * 3 + c];
+                }
+                orow[(hw + p) * 3 + c] = (uint8_t)v;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------- Fig. 3 gather warp */
+/* The reconstruction exactly as the Fig. 3 code organises it: every
+ * destination pixel reads the filtered depth at its own position, takes the
+ * per-view offset of that depth (the O10 table, the reading of the code's
+ * shift expressions) and copies the source pixel it points back to; a source
+ * position outside the row copies the destination's own source pixel, as the
+ * code's else branches do.  There is no occlusion test and nothing is left to
+ * fill.  The anaglyph takes red from the gathered left view and green and
+ * blue from the gathered right view, as the code writes res.  Df is the
+ * filtered depth map of the frame (u8 [h][w]). */
+int oracle_gather(const uint8_t *frame, const uint8_t *Df, int w, int h, int B, int T,
+                  uint8_t *out_L, uint8_t *out_R, uint8_t *out_A) {
+    if (!frame || !Df || w < 1 || h < 1 || B < 0 || B > 255 || T < -1 || T > 255) return ORC_E_INVALID;
+    int32_t lutP[256], lutL[256], lutR[256];
+    oracle_disparity_lut(B, T, lutP, lutL, lutR);
+    for (int y = 0; y < h; y++) {
+        for (int x = 0; x < w; x++) {
+            const int d = Df[(size_t)y * w + x];
+            int xl = x - lutL[d], xr = x - lutR[d];
+            if (xl < 0 || xl >= w) xl = x;
+            if (xr < 0 || xr >= w) xr = x;
+            const uint8_t *sl = frame + ((size_t)y * w + xl) * 3;
+            const uint8_t *sr = frame + ((size_t)y * w + xr) * 3;
+            const size_t o = ((size_t)y * w + x) * 3;
+            for (int c = 0; c < 3; c++) {
+                if (out_L) out_L[o + c] = sl[c];
+                if (out_R) out_R[o + c] = sr[c];
+            }
+            if (out_A) {
+                out_A[o + 0] = sl[0];
+                out_A[o + 1] = sr[1];
+                out_A[o + 2] = sr[2];
+            }
+        }
+    }
+    return ORC_OK;
+}

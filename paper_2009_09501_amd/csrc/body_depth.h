@@ -537,4 +537,262 @@ __host__ __device__ constexpr size_t regions_lds_bytes_c(int nb) {
     return (size_t)(nb + nb / 32 + 1 + 3 * kRegionThreads + kRegionThreads / 64 + 4) * 4;
 }
 
+// ---------------------------------------------------------------------------
+// Strip-parallel region grouping.  The same components and labels as
+// regions_body, computed in three launches:
+//   strips: one workgroup per strip of rstrip block rows (at most
+//     kStripBlocks blocks, two per lane) finds the strip-local components by
+//     union-find in LDS (a root is hooked under the smaller root, so every
+//     root is its component's smallest block), writes each block's
+//     strip-local label, and enters every non-edge component into a slot
+//     table: {label, block count} and its lowest block row + 1;
+//   merge: one workgroup joins slots across strip boundaries (union-find over
+//     slots, again rooted at the smallest label), sums counts and takes the
+//     lowest row per merged component, picks the background and writes each
+//     slot's final label and depth.  With more than kRegionSlots slots it runs
+//     regions_body instead, for the whole frame;
+//   final: one lane per block turns its strip-local label into the final
+//     label and depth.
+
+constexpr int kStripLanes = 1024;
+constexpr int kStripBlocks = 2048;
+
+__device__ __forceinline__ uint32_t ufl_find(uint32_t* par, uint32_t x) {
+    while (true) {
+        const uint32_t p = lds_load(&par[x]);
+        if (p == x) return x;
+        const uint32_t gp = lds_load(&par[p]);
+        if (gp != p) lds_store(&par[x], gp);
+        x = gp;
+    }
+}
+
+// Join the sets of a and b, hooking the root with the larger key under the
+// other (key: the index itself, or key[] when given).
+__device__ __forceinline__ void ufl_unite(uint32_t* par, uint32_t a, uint32_t b, const uint32_t* key) {
+    while (true) {
+        a = ufl_find(par, a);
+        b = ufl_find(par, b);
+        if (a == b) return;
+        const uint32_t ka = key ? key[a] : a, kb = key ? key[b] : b;
+        if (ka < kb) { const uint32_t t = a; a = b; b = t; }
+        if (atomicCAS(&par[a], a, b) == a) return;
+    }
+}
+
+__device__ __forceinline__ bool linked(uint32_t s, uint32_t n, int tau) {
+    return !((s | n) >> 24) && (int)__builtin_amdgcn_sad_u8(s, n, 0u) <= tau;
+}
+
+__host__ __device__ constexpr size_t rg_strip_lds_words() { return 2 * kStripBlocks + 3 * kStripBlocks + 4; }
+
+__device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uint32_t* lds) {
+    const int gw = f.gw, gh = f.gh, SR = f.rstrip;
+    const int t = threadIdx.x;
+    const int r0 = strip * SR;
+    const int rows = min(SR, gh - r0);
+    const int n = rows * gw, base = r0 * gw;
+    const int nload = (r0 + rows < gh ? rows + 1 : rows) * gw;
+    uint32_t* st = lds;                      // statistics of the strip and the row below
+    uint32_t* par = st + 2 * kStripBlocks;   // union-find
+    uint32_t* cnt = par + kStripBlocks;      // per root: non-edge blocks
+    uint32_t* row = cnt + kStripBlocks;      // per root: lowest local row + 1
+    uint32_t* misc = row + kStripBlocks;     // [0]: slots of this strip, [1]: first slot
+    uint32_t* binfo_w = reinterpret_cast<uint32_t*>(f.binfo);
+    const uint32_t gwm = gw > 1 ? (uint32_t)((0x100000000ull + (uint32_t)gw - 1) / (uint32_t)gw) : 0u;
+
+    for (int j = t; j < nload; j += kStripLanes) {
+        const uint32_t s = f.stats[base + j];
+        st[j] = s;
+        if (j < n) binfo_w[2 * (base + j)] = s;
+    }
+    for (int j = t; j < n; j += kStripLanes) {
+        par[j] = j;
+        cnt[j] = 0;
+        row[j] = 0;
+    }
+    if (t == 0) misc[0] = 0;
+    __syncthreads();
+
+    // unions along the right and down links inside the strip
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int j = t + k * kStripLanes;
+        if (j < n) {
+            const uint32_t s = st[j];
+            const int x = j - (int)div_u16((uint32_t)j, gwm, (uint32_t)gw) * gw;
+            if (x + 1 < gw && linked(s, st[j + 1], f.tau)) ufl_unite(par, j, j + 1, nullptr);
+            if (j + gw < n && linked(s, st[j + gw], f.tau)) ufl_unite(par, j, j + gw, nullptr);
+        }
+    }
+    __syncthreads();
+
+    // roots (= smallest block of each component); per root the non-edge
+    // count and lowest row, one atomic per wave when the wave's non-edge
+    // blocks share a root
+    uint32_t root[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int j = t + k * kStripLanes;
+        root[k] = j < n ? ufl_find(par, j) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int j = t + k * kStripLanes;
+        const bool ne = j < n && !(st[j] >> 24);
+        const uint32_t lrow = j < n ? div_u16((uint32_t)j, gwm, (uint32_t)gw) + 1u : 0u;
+        const unsigned long long mne = __ballot(ne);
+        if (mne) {
+            const int lead = __ffsll((long long)mne) - 1;
+            const uint32_t r_lead = __shfl(root[k], lead);
+            const unsigned long long msame = __ballot(ne && root[k] == r_lead);
+            if (msame == mne) {
+                uint32_t mr = ne ? lrow : 0u;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) mr = max(mr, (uint32_t)__shfl_xor((int)mr, o));
+                if ((t & 63) == lead) {
+                    atomicAdd(&cnt[r_lead], (uint32_t)__popcll(mne));
+                    atomicMax(&row[r_lead], mr);
+                }
+            } else if (ne) {
+                atomicAdd(&cnt[root[k]], 1u);
+                atomicMax(&row[root[k]], lrow);
+            }
+        }
+    }
+    __syncthreads();
+
+    // slots for the strip's non-edge roots
+    uint32_t slot[2] = {0u, 0u};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int j = t + k * kStripLanes;
+        if (j < n && root[k] == (uint32_t)j && !(st[j] >> 24)) slot[k] = atomicAdd(&misc[0], 1u) + 1u;
+    }
+    __syncthreads();
+    if (t == 0) misc[1] = atomicAdd(&f.rctl[0], misc[0]);
+    __syncthreads();
+    const uint32_t first = misc[1];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int j = t + k * kStripLanes;
+        if (j >= n) continue;
+        const uint32_t lab = (uint32_t)base + root[k];
+        f.labels[base + j] = (int32_t)lab;
+        if (slot[k]) {
+            const uint32_t sidx = first + slot[k] - 1u;
+            if (sidx < (uint32_t)kRegionSlots) {
+                f.rent[sidx] = make_uint2(lab, cnt[j]);
+                f.rrow[sidx] = (uint32_t)r0 + row[j];
+                f.rcid[lab] = (int32_t)sidx;
+            }
+        }
+    }
+}
+
+__host__ __device__ constexpr size_t rg_merge_lds_words() { return 4 * (size_t)kRegionSlots + 4; }
+
+__device__ __forceinline__ void rg_merge_body(const FrameDesc& f, uint32_t* lds) {
+    const int t = threadIdx.x, lane = t & 63;
+    const uint32_t nslot = f.rctl[0];
+    if (nslot > (uint32_t)kRegionSlots) {
+        // too many strip-local components: group the whole frame here
+        regions_body(f, lds);
+        __syncthreads();
+        if (t == 0) {
+            f.rctl[0] = 0;
+            f.rctl[1] = 1;
+        }
+        return;
+    }
+    const int ns = (int)nslot;
+    const int gw = f.gw, gh = f.gh, SR = f.rstrip;
+    uint32_t* par = lds;
+    uint32_t* lab = par + kRegionSlots;
+    uint32_t* cnt = lab + kRegionSlots;
+    uint32_t* row = cnt + kRegionSlots;
+    uint32_t* misc = row + kRegionSlots;  // [0]: background key
+    for (int s = t; s < ns; s += kStripLanes) {
+        const uint2 e = f.rent[s];
+        par[s] = s;
+        lab[s] = e.x;
+        cnt[s] = e.y;
+        row[s] = f.rrow[s];
+    }
+    if (t == 0) misc[0] = 0;
+    __syncthreads();
+
+    // joins across strip boundaries: the down link from the last row of a
+    // strip to the first row of the next, skipped where the left neighbour
+    // links the same pair of strip-local components
+    const int nbnd = (gh + SR - 1) / SR - 1;
+    const int total = nbnd * gw;
+    const uint32_t gwm = gw > 1 ? (uint32_t)((0x100000000ull + (uint32_t)gw - 1) / (uint32_t)gw) : 0u;
+    for (int q = t; q < total; q += kStripLanes) {
+        const int kb = (int)div_u16((uint32_t)q, gwm, (uint32_t)gw);
+        const int x = q - kb * gw;
+        const int b = ((kb + 1) * SR - 1) * gw + x, c = b + gw;
+        const uint32_t sb = f.stats[b], sc = f.stats[c];
+        const int la = f.labels[b], lc = f.labels[c];
+        bool join = linked(sb, sc, f.tau);
+        if (join && x > 0) {
+            const uint32_t sb1 = f.stats[b - 1], sc1 = f.stats[c - 1];
+            if (linked(sb1, sc1, f.tau) && f.labels[b - 1] == la && f.labels[c - 1] == lc) join = false;
+        }
+        if (join) ufl_unite(par, (uint32_t)f.rcid[la], (uint32_t)f.rcid[lc], lab);
+    }
+    __syncthreads();
+
+    // merged component totals at the roots (the root holds the smallest label)
+    for (int s = t; s < ns; s += kStripLanes) {
+        const uint32_t r = ufl_find(par, s);
+        if (r != (uint32_t)s) {
+            atomicAdd(&cnt[r], cnt[s]);
+            atomicMax(&row[r], row[s]);
+        }
+    }
+    __syncthreads();
+    uint32_t best = 0;
+    for (int s = t; s < ns; s += kStripLanes)
+        if (par[s] == (uint32_t)s) best = max(best, (cnt[s] << 16) | (0xFFFFu - lab[s]));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) best = max(best, (uint32_t)__shfl_xor((int)best, o));
+    if (lane == 0 && best) atomicMax(&misc[0], best);
+    __syncthreads();
+    const uint32_t bgkey = misc[0];
+    const uint32_t bg = bgkey ? 0xFFFFu - (bgkey & 0xFFFFu) : 0xFFFFFFFFu;
+    for (int s = t; s < ns; s += kStripLanes) {
+        const uint32_t r = ufl_find(par, s);
+        const uint32_t L = lab[r];
+        const uint32_t d = (uint32_t)ramp((int)row[r] - 1, gh);
+        f.rfin[s] = (L << 9) | ((L == bg ? 1u : 0u) << 8) | d;
+    }
+    __syncthreads();
+    if (t == 0) {
+        f.rctl[0] = 0;
+        f.rctl[1] = 0;
+    }
+}
+
+// One block per lane: final label and depth from the strip-local label.
+__device__ __forceinline__ void rg_final_block(const FrameDesc& f, int b) {
+    const int gw = f.gw, gh = f.gh;
+    if (b >= gw * gh || f.rctl[1]) return;
+    uint32_t* binfo_w = reinterpret_cast<uint32_t*>(f.binfo);
+    const uint32_t s = binfo_w[2 * b];
+    const int by = b / gw;
+    uint32_t label = (uint32_t)b;
+    int d;
+    if (s >> 24) {
+        d = ramp(by, gh);
+    } else {
+        const int L = f.labels[b];
+        const uint32_t v = f.rfin[f.rcid[L]];
+        label = v >> 9;
+        d = ((v >> 8) & 1u) ? ramp(by, gh) : (int)(v & 255u);
+    }
+    binfo_w[2 * b + 1] = (uint32_t)d;
+    f.labels[b] = (int32_t)label;
+}
+
 }  // namespace pstereo

@@ -354,6 +354,26 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
 // over all LDS banks.
 __device__ __forceinline__ int kidx(int x) { return x + (x >> 5); }
 
+// Per-byte mean of two packed colours, rounded half up, with no carries
+// between bytes: (a | b) - ((a ^ b) >> 1) per byte.
+__device__ __forceinline__ uint32_t avg_bytes(uint32_t a, uint32_t b) {
+    return (a | b) - (((a ^ b) >> 1) & 0x7F7F7F7Fu);
+}
+
+// Two packed R | G << 8 | B << 16 pixels to 6 bytes at an even address.
+__device__ __forceinline__ void store_px2_u16(uint8_t* p, uint32_t c0, uint32_t c1) {
+    uint16_t* q = reinterpret_cast<uint16_t*>(p);
+    q[0] = (uint16_t)c0;
+    q[1] = (uint16_t)(((c0 >> 16) & 0xFFu) | ((c1 & 0xFFu) << 8));
+    q[2] = (uint16_t)(c1 >> 8);
+}
+
+__device__ __forceinline__ void store_px_bytes(uint8_t* p, uint32_t c) {
+    p[0] = (uint8_t)c;
+    p[1] = (uint8_t)(c >> 8);
+    p[2] = (uint8_t)(c >> 16);
+}
+
 __host__ __device__ constexpr size_t warp_lds_bytes(int w, int threads, int q) {
     return (size_t)(2 * (((w + 3) & ~3) + ((w + 3) & ~3) / 32 + 1) * 4 + 256 * 4 + ((w + 3) & ~3) +
                     4 * q * (threads / 64) * 4);
@@ -602,6 +622,34 @@ __device__ __forceinline__ void warp_row(const FrameDesc& f, int y, int t, int N
                (cl[4 * qi + 1] & 0xFFu) | (cr[4 * qi + 1] & 0xFFFF00u),
                (cl[4 * qi + 2] & 0xFFu) | (cr[4 * qi + 2] & 0xFFFF00u),
                (cl[4 * qi + 3] & 0xFFu) | (cr[4 * qi + 3] & 0xFFFF00u));
+        // half side-by-side: half column p = mean of view columns 2p, 2p + 1
+        // (rounded up per byte); left view in the first floor(W/2) columns,
+        // right view after them
+        if (f.out_h) {
+            const int hw = W >> 1;
+            const uint32_t l0 = avg_bytes(cl[4 * qi], cl[4 * qi + 1]), l1 = avg_bytes(cl[4 * qi + 2], cl[4 * qi + 3]);
+            const uint32_t r0 = avg_bytes(cr[4 * qi], cr[4 * qi + 1]), r1 = avg_bytes(cr[4 * qi + 2], cr[4 * qi + 3]);
+            const int p0 = x0 >> 1;
+            uint8_t* row = f.out_h + (size_t)y * W * 3;
+            if (ALIGNED) {
+                // W % 4 == 0: both pairs exist, and both halves start at even
+                // byte offsets
+                store_px2_u16(row + (size_t)p0 * 3, l0, l1);
+                store_px2_u16(row + (size_t)(hw + p0) * 3, r0, r1);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int xa = x0 + 2 * k;
+                    if (xa >= W) break;
+                    const int pc = p0 + k;
+                    const bool pair = xa + 1 < W;
+                    const uint32_t lm = pair ? (k ? l1 : l0) : cl[4 * qi + 2 * k];
+                    const uint32_t rm = pair ? (k ? r1 : r0) : cr[4 * qi + 2 * k];
+                    if (pc < hw) store_px_bytes(row + (size_t)pc * 3, lm);
+                    store_px_bytes(row + (size_t)(hw + pc) * 3, rm);
+                }
+            }
+        }
     }
 }
 

@@ -2,6 +2,8 @@
 // frame per launch); the stage bodies live in body_depth.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "body_depth.h"
 
 namespace pstereo {
@@ -16,6 +18,18 @@ __global__ void __launch_bounds__(kRegionThreads) k_regions(FrameDesc f) {
     extern __shared__ uint32_t lds[];
     regions_body(f, lds);
 }
+
+__global__ void __launch_bounds__(kStripLanes) k_rg_strip(FrameDesc f) {
+    __shared__ uint32_t lds[rg_strip_lds_words()];
+    rg_strip_body(f, blockIdx.x, lds);
+}
+
+__global__ void __launch_bounds__(kStripLanes) k_rg_merge(FrameDesc f) {
+    extern __shared__ uint32_t lds[];
+    rg_merge_body(f, lds);
+}
+
+__global__ void __launch_bounds__(256) k_rg_final(FrameDesc f) { rg_final_block(f, blockIdx.x * 256 + threadIdx.x); }
 
 // ---------------------------------------------------------------------------
 // host-side launch helpers
@@ -47,9 +61,27 @@ LaunchSpec spec_regions(const FrameDesc& f) {
     return {reinterpret_cast<const void*>(&k_regions), dim3(1), dim3(kRegionThreads), regions_lds_bytes(f.gw * f.gh)};
 }
 
+int strip_rows(int gw) { return gw >= 1 && gw <= kStripBlocks ? kStripBlocks / gw : 0; }
+
+LaunchSpec spec_rg_strip(const FrameDesc& f) {
+    return {reinterpret_cast<const void*>(&k_rg_strip), dim3((f.gh + f.rstrip - 1) / f.rstrip), dim3(kStripLanes), 0};
+}
+
+LaunchSpec spec_rg_merge(const FrameDesc& f) {
+    const size_t lds = std::max(rg_merge_lds_words() * 4, regions_lds_bytes(f.gw * f.gh));
+    return {reinterpret_cast<const void*>(&k_rg_merge), dim3(1), dim3(kStripLanes), lds};
+}
+
+LaunchSpec spec_rg_final(const FrameDesc& f) {
+    return {reinterpret_cast<const void*>(&k_rg_final), dim3((f.gw * f.gh + 255) / 256), dim3(256), 0};
+}
+
 hipError_t prepare_depth_kernels() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_regions),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_regions),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rg_merge), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kMaxLds);
 }
 
 }  // namespace pstereo

@@ -31,6 +31,11 @@ struct pstereo_ctx {
     uint2* d_binfo = nullptr;
     int32_t* d_labels = nullptr;
     uint8_t* d_df = nullptr;  // filtered depth, max_w * max_h bytes
+    int32_t* d_rcid = nullptr;  // strip-parallel region grouping scratch
+    uint2* d_rent = nullptr;
+    uint32_t* d_rrow = nullptr;
+    uint32_t* d_rfin = nullptr;
+    uint32_t* d_rctl = nullptr;
     std::string err;
     // last generated-depth call, for pstereo_debug_blocks
     bool have_blocks = false;
@@ -142,7 +147,13 @@ int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
     if (hipMalloc(&c->d_stats, nb * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_binfo, nb * sizeof(uint2)) != hipSuccess ||
         hipMalloc(&c->d_labels, nb * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&c->d_df, (size_t)max_w * max_h) != hipSuccess) {
+        hipMalloc(&c->d_df, (size_t)max_w * max_h) != hipSuccess ||
+        hipMalloc(&c->d_rcid, nb * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->d_rent, pstereo::kRegionSlots * sizeof(uint2)) != hipSuccess ||
+        hipMalloc(&c->d_rrow, pstereo::kRegionSlots * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_rfin, pstereo::kRegionSlots * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_rctl, 4 * sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->d_rctl, 0, 4 * sizeof(uint32_t)) != hipSuccess) {
         (void)hipGetLastError();
         pstereo_destroy(c);
         return fail(nullptr, PSTEREO_E_NOMEM, "scratch allocation failed");
@@ -160,6 +171,11 @@ int pstereo_destroy(pstereo_ctx* c) {
     (void)hipFree(c->d_binfo);
     (void)hipFree(c->d_labels);
     (void)hipFree(c->d_df);
+    (void)hipFree(c->d_rcid);
+    (void)hipFree(c->d_rent);
+    (void)hipFree(c->d_rrow);
+    (void)hipFree(c->d_rfin);
+    (void)hipFree(c->d_rctl);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     (void)hipGetLastError();
     delete c;
@@ -214,16 +230,18 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
         if (ext && (rc = check_device_ptr(c, p.depth_in, "depth_in")) != PSTEREO_OK) return rc;
         if (p.out_depth && (rc = check_device_ptr(c, p.out_depth, "out_depth")) != PSTEREO_OK) return rc;
         if (p.out_depth_raw && (rc = check_device_ptr(c, p.out_depth_raw, "out_depth_raw")) != PSTEREO_OK) return rc;
+        if (p.out_hsbs && (rc = check_device_ptr(c, p.out_hsbs, "out_hsbs")) != PSTEREO_OK) return rc;
     }
 
     const size_t img = (size_t)w * h * 3, pl = (size_t)w * h;
     const Range rin[2] = {{frame, img, "frame"}, {ext ? p.depth_in : nullptr, pl, "depth_in"}};
-    const Range rout[5] = {{out_l, img, "out_left"}, {out_r, img, "out_right"}, {out_a, img, "out_anaglyph"},
-                           {p.out_depth, pl, "out_depth"}, {p.out_depth_raw, pl, "out_depth_raw"}};
-    for (int i = 0; check_ptrs && i < 5; ++i) {
+    const Range rout[6] = {{out_l, img, "out_left"}, {out_r, img, "out_right"}, {out_a, img, "out_anaglyph"},
+                           {p.out_depth, pl, "out_depth"}, {p.out_depth_raw, pl, "out_depth_raw"},
+                           {p.out_hsbs, img, "out_hsbs"}};
+    for (int i = 0; check_ptrs && i < 6; ++i) {
         for (int j = 0; j < 2; ++j)
             if (overlap(rout[i], rin[j])) return fail(c, PSTEREO_E_ALIAS, "%s overlaps %s", rout[i].name, rin[j].name);
-        for (int j = i + 1; j < 5; ++j)
+        for (int j = i + 1; j < 6; ++j)
             if (overlap(rout[i], rout[j])) return fail(c, PSTEREO_E_ALIAS, "%s overlaps %s", rout[i].name, rout[j].name);
     }
     if (!pstereo::warp_shape(w, ws))
@@ -237,10 +255,17 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
     f.depth_in = ext ? p.depth_in : nullptr;
     f.out_df = p.out_depth;
     f.out_d0 = p.out_depth_raw;
+    f.out_h = p.out_hsbs;
     f.stats = c->d_stats;
     f.binfo = c->d_binfo;
     f.labels = c->d_labels;
     f.df = c->d_df;
+    f.rcid = c->d_rcid;
+    f.rent = c->d_rent;
+    f.rrow = c->d_rrow;
+    f.rfin = c->d_rfin;
+    f.rctl = c->d_rctl;
+    f.rstrip = pstereo::strip_rows(gw);
     f.w = w;
     f.h = h;
     f.K = K;
@@ -261,14 +286,35 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
 
 // The launch sequence of one frame (block statistics and region grouping
 // only with a generated depth map).
-void frame_specs(const FrameDesc& f, const WarpShape& ws, pstereo::LaunchSpec (&ls)[4], int& n) {
+constexpr int kMaxSpecs = 6;
+
+// stage[i]: which of the four profiled stages kernel i belongs to (block
+// statistics, region grouping, depth filter, warp)
+void frame_specs(const FrameDesc& f, const WarpShape& ws, pstereo::LaunchSpec (&ls)[kMaxSpecs], int& n,
+                 int (*stage)[kMaxSpecs] = nullptr) {
     n = 0;
+    int st[kMaxSpecs];
     if (!f.depth_in) {
+        st[n] = 0;
         ls[n++] = pstereo::spec_blockstats(f);
-        ls[n++] = pstereo::spec_regions(f);
+        if (f.rstrip > 0) {
+            st[n] = 1;
+            ls[n++] = pstereo::spec_rg_strip(f);
+            st[n] = 1;
+            ls[n++] = pstereo::spec_rg_merge(f);
+            st[n] = 1;
+            ls[n++] = pstereo::spec_rg_final(f);
+        } else {
+            st[n] = 1;
+            ls[n++] = pstereo::spec_regions(f);
+        }
     }
+    st[n] = 2;
     ls[n++] = pstereo::spec_cbf(f);
+    st[n] = 3;
     ls[n++] = pstereo::spec_warp(f, ws);
+    if (stage)
+        for (int i = 0; i < n; ++i) (*stage)[i] = st[i];
 }
 
 }  // namespace
@@ -305,10 +351,11 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
         c->prof_head++;
     }
 
-    pstereo::LaunchSpec ls[4];
+    pstereo::LaunchSpec ls[kMaxSpecs];
+    int stage[kMaxSpecs];
     int n;
-    frame_specs(f, ws, ls, n);
-    // event k is recorded after kernel k-1; frames without the depth kernels
+    frame_specs(f, ws, ls, n, &stage);
+    // event k is recorded at the end of stage k-1; frames without the depth kernels
     // repeat the first event so the depth slots read zero
     if (prof) (void)hipEventRecord(ev[0], s);
     if (ext && prof) {
@@ -318,8 +365,9 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
     static const char* names[4] = {"block statistics", "region grouping", "depth filter", "warp"};
     for (int i = 0; i < n; ++i) {
         if ((e = pstereo::launch(ls[i], f, s)) != hipSuccess)
-            return fail(c, PSTEREO_E_DEVICE, "%s launch: %s", names[i + (ext ? 2 : 0)], hipGetErrorString(e));
-        if (prof) (void)hipEventRecord(ev[i + 1 + (ext ? 2 : 0)], s);
+            return fail(c, PSTEREO_E_DEVICE, "%s launch: %s", names[stage[i]], hipGetErrorString(e));
+        // one event at the end of each stage
+        if (prof && (i + 1 == n || stage[i + 1] != stage[i])) (void)hipEventRecord(ev[stage[i] + 1], s);
     }
     if (!ext) {
         c->have_blocks = true;
@@ -407,11 +455,11 @@ struct pstereo_video {
     hipStream_t stream = nullptr;
     FrameDesc tmpl{};
     WarpShape ws{};
-    pstereo::LaunchSpec ls[4];
+    pstereo::LaunchSpec ls[kMaxSpecs];
     int nk = 0;
     hipGraph_t graph[kRing] = {};
     hipGraphExec_t exec[kRing] = {};
-    hipGraphNode_t node[kRing][4] = {};
+    hipGraphNode_t node[kRing][kMaxSpecs] = {};
     hipEvent_t done[kRing] = {};
     bool pending[kRing] = {};
     long long count = 0;
@@ -451,7 +499,7 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
     }
     if (pp.flags & PSTEREO_DEPTH_EXTERNAL)
         return fail(c, PSTEREO_E_UNSUPPORTED, "video replay generates the depth map (no PSTEREO_DEPTH_EXTERNAL)");
-    if (pp.out_depth || pp.out_depth_raw)
+    if (pp.out_depth || pp.out_depth_raw || pp.out_hsbs)
         return fail(c, PSTEREO_E_UNSUPPORTED, "video replay takes no depth dumps");
     pstereo_video* v = new (std::nothrow) pstereo_video;
     if (!v) return fail(c, PSTEREO_E_NOMEM, "host allocation failed");
@@ -505,7 +553,7 @@ int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, 
     if (e != hipSuccess) return fail(c, PSTEREO_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
     if (f.aligned != v->tmpl.aligned) {
         // the captured kernels assume the first frame's alignment; launch directly
-        pstereo::LaunchSpec ls[4];
+        pstereo::LaunchSpec ls[kMaxSpecs];
         int n;
         frame_specs(f, ws, ls, n);
         for (int i = 0; i < n; ++i)

@@ -191,7 +191,8 @@ int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, con
         p = *pin;
     }
     if (p.flags & PSTEREO_DEPTH_EXTERNAL) return bfail(b, PSTEREO_E_UNSUPPORTED, "batches generate their depth maps");
-    if (p.out_depth || p.out_depth_raw) return bfail(b, PSTEREO_E_UNSUPPORTED, "batches take no depth dumps");
+    if (p.out_depth || p.out_depth_raw || p.out_hsbs)
+        return bfail(b, PSTEREO_E_UNSUPPORTED, "batches take no depth dumps or half side-by-side output");
     if (p.depth_threshold < -1 || p.depth_threshold > 255) return bfail(b, PSTEREO_E_INVALID, "depth_threshold out of range");
     if (p.cbf_radius < 0 || p.cbf_radius > 3) return bfail(b, PSTEREO_E_INVALID, "cbf_radius out of range");
     if (p.edge_thresh < 0 || p.edge_thresh > 255) return bfail(b, PSTEREO_E_INVALID, "edge_thresh out of range");

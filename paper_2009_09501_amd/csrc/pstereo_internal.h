@@ -17,10 +17,19 @@ struct FrameDesc {
     const uint8_t* depth_in; // external depth map (u8 [h][w]) or null
     uint8_t* out_df;         // optional filtered-depth dump
     uint8_t* out_d0;         // optional raw-depth dump
+    uint8_t* out_h;          // optional half side-by-side frame, RGB24 [h][w][3]
     uint32_t* stats;         // per block: mean R | G << 8 | B << 16 | edge << 24
     uint2* binfo;            // per block: {stats, region depth}
     int32_t* labels;         // per block: region label
     uint8_t* df;             // filtered depth scratch, u8 [h][w] (4-byte aligned)
+    // strip-parallel region grouping (rstrip > 0): strip-local components are
+    // merged across strip boundaries through a table of slots
+    int32_t* rcid;           // per block: slot of the strip-local component it labels
+    uint2* rent;             // per slot: {strip-local label, non-edge count}
+    uint32_t* rrow;          // per slot: lowest block row + 1
+    uint32_t* rfin;          // per slot: final label << 9 | background << 8 | depth
+    uint32_t* rctl;          // [0]: slots taken, [1]: 1 if the merge fell back to one workgroup
+    int rstrip;              // block rows per strip, 0 = single-workgroup grouping
     int w, h;
     int K, gw, gh;           // depth block size and grid
     int B, T, g, tau, r;     // method parameters
@@ -49,6 +58,12 @@ bool warp_shape(int w, WarpShape* out);
 bool warp_shape_cap(int w, int cap, WarpShape* out);
 LaunchSpec spec_blockstats(const FrameDesc& f);
 LaunchSpec spec_regions(const FrameDesc& f);
+// Strip-parallel grouping: strips, merge, per-block resolution.
+int strip_rows(int gw);
+constexpr int kRegionSlots = 4096;
+LaunchSpec spec_rg_strip(const FrameDesc& f);
+LaunchSpec spec_rg_merge(const FrameDesc& f);
+LaunchSpec spec_rg_final(const FrameDesc& f);
 LaunchSpec spec_cbf(const FrameDesc& f);
 LaunchSpec spec_warp(const FrameDesc& f, const WarpShape& ws);
 

@@ -67,6 +67,7 @@ class PstereoParams(ctypes.Structure):
         ("out_depth", ctypes.c_void_p),
         ("out_depth_raw", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
+        ("out_hsbs", ctypes.c_void_p),
     ]
 
 
@@ -216,7 +217,7 @@ def pstereo_params_init(**overrides) -> PstereoParams:
     p = PstereoParams()
     _check(load_library().pstereo_params_init(ctypes.byref(p)))
     for k, v in overrides.items():
-        if k in ("depth_in", "out_depth", "out_depth_raw", "stream"):
+        if k in ("depth_in", "out_depth", "out_depth_raw", "stream", "out_hsbs"):
             v = _ptr(v) if k != "stream" else v
         setattr(p, k, v)
     return p
@@ -456,7 +457,7 @@ class Context:
             pass
 
     def synthesize(self, frame, out=None, stream=None, depth=None, out_depth=None,
-                   out_depth_raw=None, flags: int = 0, **params):
+                   out_depth_raw=None, out_hsbs=None, flags: int = 0, **params):
         import torch
         h, w, c = frame.shape
         assert c == 3 and frame.dtype == torch.uint8 and frame.is_contiguous()
@@ -469,6 +470,7 @@ class Context:
         p.depth_in = _ptr(depth)
         p.out_depth = _ptr(out_depth)
         p.out_depth_raw = _ptr(out_depth_raw)
+        p.out_hsbs = _ptr(out_hsbs)
         p.stream = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         pstereo_synthesize(self.handle, frame, w, h, p, *out)
         return out

@@ -174,3 +174,39 @@ def pipeline(frame, B, T=150, K=8, g=24, tau=24, r=2, depth=None):
             "L": L, "R": R, "A": A,
             "warpL": views["L"][1], "warpR": views["R"][1],
             "srcL": views["L"][2], "srcR": views["R"][2]}
+
+
+def hsbs(L, R):
+    """Half side-by-side frame, pixel by pixel: half p of a view = mean of its
+    columns 2p and 2p+1 rounded half up (only column 2p if 2p+1 is past the
+    edge); left half = left view, floor(w/2) columns; right half = right view,
+    the remaining columns."""
+    h, w = len(L), len(L[0])
+    hw = w // 2
+    out = [[None] * w for _ in range(h)]
+    for y in range(h):
+        for x in range(w):
+            view, p = (L, x) if x < hw else (R, x - hw)
+            a = view[y][2 * p]
+            b = view[y][2 * p + 1] if 2 * p + 1 < w else a
+            out[y][x] = tuple(round_half_up(Fraction(a[c] + b[c], 2)) for c in range(3))
+    return out
+
+
+def gather(frame, Df, B, T=150):
+    """Fig. 3 gather, pixel by pixel: L(x) = I(x - oL(Df(x))), R(x) =
+    I(x - oR(Df(x))), falling back to I(x) outside the row; A = (L.R, R.G, R.B)."""
+    h, w = len(frame), len(frame[0])
+    L = [[None] * w for _ in range(h)]
+    R = [[None] * w for _ in range(h)]
+    A = [[None] * w for _ in range(h)]
+    for y in range(h):
+        for x in range(w):
+            _, oL, oR = parallax(B, T, Df[y][x])
+            xl, xr = x - oL, x - oR
+            xl = xl if 0 <= xl < w else x
+            xr = xr if 0 <= xr < w else x
+            L[y][x] = tuple(frame[y][xl])
+            R[y][x] = tuple(frame[y][xr])
+            A[y][x] = (L[y][x][0], R[y][x][1], R[y][x][2])
+    return L, R, A

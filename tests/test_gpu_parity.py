@@ -202,3 +202,69 @@ def test_error_codes(ctx):
     pstereo_synthesize(ctx.handle, f, w, h, p, *o)
     torch.cuda.synchronize()
     _ = PSTEREO_E_UNSUPPORTED
+
+
+def _block_frame(gw, gh, K, kind):
+    """A frame of K x K blocks: kind[by, bx] = 0 uniform grey (100, 100, 100),
+    1 uniform (150, 75, 100) -- the same luma, colour distance 75 -- and
+    2 an edge block: a black/white pixel checker inside, its top row and left
+    column grey, so the blocks above and to the left see no luma step into it."""
+    f = np.empty((gh * K, gw * K, 3), np.uint8)
+    cols = {0: (100, 100, 100), 1: (150, 75, 100)}
+    yy, xx = np.mgrid[0:K, 0:K]
+    checker = np.where(((yy + xx) & 1)[..., None] == 1, 255, 0).astype(np.uint8)
+    for by in range(gh):
+        for bx in range(gw):
+            k = kind[by, bx]
+            blk = f[by * K:(by + 1) * K, bx * K:(bx + 1) * K]
+            if k == 2:
+                blk[:] = checker
+                blk[0, :] = 100
+                blk[:, 0] = 100
+            else:
+                blk[:] = cols[k]
+    return f
+
+
+@pytest.mark.parametrize("w,h", [(640, 360), (1280, 720), (3840, 2160)])
+def test_isoluminant_checker_many_components(ctx, oracle_mod, w, h):
+    """Every block its own non-edge component (neighbours share luma, so no
+    edges, but differ by 75 in colour, so no links): 3600 components at
+    640x360 (strip merge), 14400 and 32400 (the merge's whole-frame grouping)."""
+    K = 8 if w * h <= 1280 * 720 else 16
+    gw, gh = w // K, h // K
+    kind = (np.add.outer(np.arange(gh), np.arange(gw)) & 1).astype(np.int64)
+    _check(ctx, oracle_mod, _block_frame(gw, gh, K, kind), synth.default_disparity(w), K=K,
+           case=f"isoluminant checker {w}x{h}")
+
+
+@pytest.mark.parametrize("gw,gh", [(40, 300), (240, 135), (960, 20)])
+def test_serpentine_region_across_strips(ctx, oracle_mod, gw, gh):
+    """One grey path winding through every block row (walls of edge blocks,
+    openings alternately at the right and left end): a single component that
+    crosses every strip boundary, plus enclosed grey blocks below it."""
+    K = 8
+    kind = np.full((gh, gw), 2, np.int64)
+    for by in range(0, gh, 2):
+        kind[by, :] = 0
+        if by + 1 < gh:
+            kind[by + 1, gw - 1 if (by // 2) % 2 == 0 else 0] = 0
+    _check(ctx, oracle_mod, _block_frame(gw, gh, K, kind), 20, K=K, case=f"serpentine {gw}x{gh} blocks")
+
+
+@pytest.mark.parametrize("w,h", [(640, 360), (1920, 1080), (644, 200), (333, 191), (7, 5), (1, 1)])
+def test_hsbs_output(ctx, oracle_mod, w, h):
+    """The fused half side-by-side epilogue equals the oracle's HSBS of the
+    oracle's views (aligned widths through the u16-store path, others bytewise)."""
+    dev = torch.device("cuda:0")
+    frame = synth.gen_frame(31 + w, w, h, 12, 4.0)
+    B = synth.default_disparity(w)
+    print(f"hsbs {w}x{h} B={B}", flush=True)
+    f = torch.from_numpy(frame).to(dev)
+    hs = torch.zeros_like(f)
+    L, R, A = ctx.synthesize(f, out_hsbs=hs, max_disparity=B)
+    torch.cuda.synchronize()
+    ref = oracle_mod.synthesize(frame, B)
+    assert np.array_equal(L.cpu().numpy(), ref.L)
+    assert np.array_equal(R.cpu().numpy(), ref.R)
+    assert np.array_equal(hs.cpu().numpy(), oracle_mod.hsbs(ref.L, ref.R))

@@ -417,3 +417,86 @@ def test_oracle_rejects_bad_args(oracle_mod):
         args.update(kw)
         with pytest.raises(ValueError):
             oracle_mod.synthesize(f, **args)
+
+
+# ------------------------------------------------------------ HSBS output
+@pytest.mark.parametrize("w,h,seed", [(1, 1, 0), (2, 3, 1), (7, 2, 2), (8, 5, 3), (33, 4, 4), (64, 2, 5)])
+def test_hsbs_brute_force(oracle_mod, w, h, seed):
+    rng = np.random.default_rng(seed)
+    L = rng.integers(0, 256, (h, w, 3), dtype=np.uint8)
+    R = rng.integers(0, 256, (h, w, 3), dtype=np.uint8)
+    got = oracle_mod.hsbs(L, R)
+    want = np.array(brute.hsbs(L.tolist(), R.tolist()), dtype=np.uint8).reshape(h, w, 3)
+    assert np.array_equal(got, want)
+
+
+def test_hsbs_closed_forms(oracle_mod):
+    # a constant pair stays constant; equal views give equal halves; odd
+    # widths copy the right view's last column; 255/0 neighbours round up
+    c = np.full((3, 10, 3), 77, np.uint8)
+    assert np.array_equal(oracle_mod.hsbs(c, c), c)
+    rng = np.random.default_rng(9)
+    v = rng.integers(0, 256, (4, 12, 3), dtype=np.uint8)
+    hs = oracle_mod.hsbs(v, v)
+    assert np.array_equal(hs[:, :6], hs[:, 6:])
+    odd = rng.integers(0, 256, (2, 9, 3), dtype=np.uint8)
+    assert np.array_equal(oracle_mod.hsbs(odd, odd)[:, 8], odd[:, 8])
+    pair = np.zeros((1, 2, 3), np.uint8)
+    pair[0, 1] = 255
+    assert oracle_mod.hsbs(pair, pair)[0, 0].tolist() == [128, 128, 128]
+    assert oracle_mod.hsbs(pair, pair)[0, 1].tolist() == [128, 128, 128]
+
+
+# ------------------------------------------------ Fig. 3 gather warp
+def _gather_rows():
+    out = []
+    for line in open(os.path.join(GOLDEN, "gather_rows.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, dep, L, R = [s.strip() for s in line.split("|")]
+        out.append((name, [int(v) for v in dep.split()], [int(v) for v in L.split()],
+                    [int(v) for v in R.split()]))
+    return out
+
+
+@pytest.mark.parametrize("case", _gather_rows(), ids=lambda c: c[0])
+def test_gather_worked_rows(oracle_mod, case):
+    name, dep, Ls, Rs = case
+    w = len(dep)
+    f = np.zeros((1, w, 3), np.uint8)
+    f[0, :, 0] = np.arange(w) * 10
+    f[0, :, 1] = 255 - np.arange(w) * 10
+    f[0, :, 2] = 7
+    L, R, A = oracle_mod.synthesize_gather(f, 12, T=150, depth=np.array([dep], np.uint8), r=0)
+    assert np.array_equal(L[0], f[0, Ls]) and np.array_equal(R[0], f[0, Rs])
+    assert np.array_equal(A[0, :, 0], L[0, :, 0]) and np.array_equal(A[0, :, 1:], R[0, :, 1:])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_gather_brute_force(oracle_mod, seed):
+    rng = np.random.default_rng(300 + seed)
+    h, w = int(rng.integers(1, 6)), int(rng.integers(1, 40))
+    f = rng.integers(0, 256, (h, w, 3), dtype=np.uint8)
+    Df = rng.choice(np.array([0, 90, 150, 151, 200, 255], np.uint8), (h, w))
+    B, T = int(rng.integers(0, 60)), int(rng.choice([-1, 150, 100]))
+    got = oracle_mod.gather(f, Df, B, T)
+    want = brute.gather(f.tolist(), Df.tolist(), B, T)
+    for g_, w_ in zip(got, want):
+        assert np.array_equal(g_, np.array(w_, np.uint8).reshape(h, w, 3))
+
+
+def test_gather_invariants(oracle_mod):
+    rng = np.random.default_rng(77)
+    f = rng.integers(0, 256, (6, 50, 3), dtype=np.uint8)
+    # B = 0: every view is the input
+    L, R, A = oracle_mod.synthesize_gather(f, 0)
+    assert np.array_equal(L, f) and np.array_equal(R, f) and np.array_equal(A, f)
+    # constant depth: same interior as the z-buffered forward warp (a pure
+    # translation), while the border strip keeps the destination's own pixel
+    dep = np.full((6, 50), 200, np.uint8)
+    gL, gR, _ = oracle_mod.synthesize_gather(f, 12, depth=dep, r=0)
+    fw = oracle_mod.synthesize(f, 12, depth=dep, r=0)
+    _, oL, oR = oracle_mod.disparity_lut(12)
+    a, b = int(oL[200]), int(-oR[200])  # 5 and 4
+    assert np.array_equal(gL[:, a:], fw.L[:, a:]) and np.array_equal(gL[:, :a], f[:, :a])
+    assert np.array_equal(gR[:, :50 - b], fw.R[:, :50 - b]) and np.array_equal(gR[:, 50 - b:], f[:, 50 - b:])
