@@ -253,6 +253,61 @@ def serve_leg(torch, synth, duration_s: float, burst: int):
     return res
 
 
+def host_leg(torch, synth, frames_n: int, lanes: int):
+    """End to end from pinned host memory: 4K frames uploaded, converted and
+    the three views downloaded, (i) through the server's host-I/O streams, whose
+    lanes overlap one frame's copies with another's compute, and (ii) one frame
+    at a time (copy in, convert, copy out, wait) for comparison."""
+    from paper_2009_09501_amd import Context
+    from paper_2009_09501_amd import pstereo as m
+    W, H = 3840, 2160
+    spec = synth.VideoSpec(4, W, H, frames=300, n=40, sigma=3.0)
+    bank = [torch.from_numpy(spec.frame(t)).pin_memory() for t in (0, 150)]
+    ring = 8
+    outs = [[torch.empty((H, W, 3), dtype=torch.uint8).pin_memory() for _ in range(3)] for _ in range(ring)]
+    res = {"frames": frames_n, "lanes": lanes, "bytes_per_frame": {"h2d": W * H * 3, "d2h": 3 * W * H * 3}}
+    srv = m.pstereo_server_create(0, 8 << 30, 1, lanes, m.PSTEREO_SERVE_BATCH)
+    try:
+        sid = m.pstereo_server_open_stream(srv, W, H, -1, ring // 2, m.PSTEREO_STREAM_HOST_IO)
+        m.pstereo_server_submit(srv, sid, bank[0], *outs[0])
+        m.pstereo_server_drain(srv)
+        m.pstereo_server_poll(srv, 64)
+        t0 = time.perf_counter()
+        inflight, finished = [], set()
+        for k in range(frames_n):
+            if len(inflight) == ring:
+                # the buffers of request k - ring are reused: wait for it
+                while inflight[0] not in finished:
+                    finished |= {c["req_id"] for c in m.pstereo_server_poll(srv, 64, wait_us=200)}
+                finished.discard(inflight.pop(0))
+            inflight.append(m.pstereo_server_submit(srv, sid, bank[k % 2], *outs[k % ring]))
+        m.pstereo_server_drain(srv)
+        dt = time.perf_counter() - t0
+    finally:
+        m.pstereo_server_destroy(srv)
+    res["overlapped_fps"] = round(frames_n / dt, 1)
+    # one frame at a time on one stream
+    dev = torch.device("cuda:0")
+    ctx = Context(0, W, H)
+    dfr = torch.empty((H, W, 3), dtype=torch.uint8, device=dev)
+    dout = [torch.empty_like(dfr) for _ in range(3)]
+    st = torch.cuda.current_stream(dev)
+    B = synth.default_disparity(W)
+    n2 = max(frames_n // 2, 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n2):
+        dfr.copy_(bank[k % 2], non_blocking=True)
+        ctx.synthesize(dfr, out=dout, stream=st, max_disparity=B)
+        for o, hbuf in zip(dout, outs[k % ring]):
+            hbuf.copy_(o, non_blocking=True)
+        st.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    res["serial_fps"] = round(n2 / dt, 1)
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,8 +315,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--frames", type=int, default=4, help="distinct synthetic frames cycled")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="video,batch,serve",
-                    help="extra launch forms measured after the plain path (video, batch, serve; empty = none)")
+    ap.add_argument("--forms", default="video,batch,serve,host",
+                    help="extra launch forms measured after the plain path (video, batch, serve, host; "
+                         "empty = none)")
+    ap.add_argument("--host-frames", type=int, default=120)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of a known size (to scale HBM byte counters)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -366,6 +423,8 @@ def main() -> int:
         out["forms"]["batch_uneven_64"] = batch_leg(torch, synth, ctx, args.form_steps, 3, args.batch_distinct)
     if "serve" in forms:
         out["forms"]["serve_8_streams"] = serve_leg(torch, synth, args.serve_seconds, args.serve_burst)
+    if "host" in forms:
+        out["forms"]["host_pinned_4k"] = host_leg(torch, synth, args.host_frames, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host, B)
     ctx.close()

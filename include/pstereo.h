@@ -52,6 +52,23 @@ extern "C" {
 #define PSTEREO_DEPTH_EXTERNAL 0x1u /* depth_in replaces the generated depth map */
 #define PSTEREO_SYNC 0x2u           /* block until the outputs are complete */
 #define PSTEREO_PROFILE 0x4u        /* record per-kernel HIP events (pstereo_profile_collect) */
+#define PSTEREO_WARP_GATHER 0x8u    /* reconstruct the views as the Fig. 3 code does (Section 4):
+                                       each destination pixel gathers the source pixel its
+                                       own filtered depth points back to, its own source
+                                       pixel when that lies outside the row; no z-buffer, no
+                                       hole filling; the anaglyph takes red from the gathered
+                                       left view, green and blue from the gathered right.
+                                       Plain calls only */
+#define PSTEREO_INPAINT_BLOCKS 0x10u /* fill holes by the block-iterative inpainting of Fig. 3
+                                       (Section 4) instead of the row fill: Jacobi sweeps over
+                                       the whole frame, a hole with >= 2 undamaged 8-neighbours
+                                       taking their mean (rounded half up), until a sweep fills
+                                       nothing (at most 4096 sweeps); pixels never filled keep
+                                       their own source pixel.  Plain calls only.  The first
+                                       such call allocates 12 * max_w * max_h bytes of scratch,
+                                       and every such call waits for its sweeps (the host checks
+                                       convergence), so it is neither asynchronous nor
+                                       graph-capturable */
 
 /* Largest number of depth blocks per frame (region grouping runs in one
  * workgroup's LDS). */

@@ -21,7 +21,8 @@ import numpy as np
 from .build import LIB_PATH, build_oracle
 
 __all__ = ["OracleResult", "synthesize", "auto_block", "disparity_lut",
-           "weight_tables", "luma", "hsbs", "gather", "synthesize_gather", "load", "build_oracle"]
+           "weight_tables", "luma", "hsbs", "gather", "synthesize_gather", "inpaint_blocks",
+           "synthesize_inpaint", "load", "build_oracle"]
 
 _lib = None
 
@@ -56,6 +57,8 @@ def load():
     lib.oracle_gather.restype = ctypes.c_int
     lib.oracle_gather.argtypes = [_u8p, _u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   _u8p, _u8p, _u8p]
+    lib.oracle_inpaint_blocks.restype = ctypes.c_int
+    lib.oracle_inpaint_blocks.argtypes = [_u8p, _i32p, ctypes.c_int, ctypes.c_int, _u8p]
     lib.oracle_hsbs.restype = ctypes.c_int
     lib.oracle_hsbs.argtypes = [_u8p, _u8p, ctypes.c_int, ctypes.c_int, _u8p]
     _lib = lib
@@ -203,3 +206,29 @@ def synthesize_gather(frame: np.ndarray, B: int, T: int = 150, K: int = 0, g: in
     the fill: depth stages as in synthesize, then gather(frame, Df)."""
     res = synthesize(frame, B, T, K, g, tau, r, depth=depth)
     return gather(frame, res.Df, B, T)
+
+
+def inpaint_blocks(frame: np.ndarray, warp: np.ndarray):
+    """(view, sweeps): block-iterative inpainting of one warped view (warp:
+    winning source x per destination, -1 = hole)."""
+    frame = np.ascontiguousarray(frame, dtype=np.uint8)
+    warp = np.ascontiguousarray(warp, dtype=np.int32)
+    h, w, _ = frame.shape
+    out = np.empty_like(frame)
+    rc = load().oracle_inpaint_blocks(_p(frame, _u8p), _p(warp, _i32p), w, h, _p(out, _u8p))
+    if rc < 0:
+        raise ValueError(f"oracle_inpaint_blocks failed with code {rc}")
+    return out, rc
+
+
+def synthesize_inpaint(frame: np.ndarray, B: int, T: int = 150, K: int = 0, g: int = 24, tau: int = 24,
+                       r: int = 2, depth: Optional[np.ndarray] = None):
+    """(L, R, A) with the block-iterative inpainting in place of the row fill:
+    the same depth stages and forward warp as synthesize, then
+    inpaint_blocks per view; the anaglyph from the inpainted views."""
+    res = synthesize(frame, B, T, K, g, tau, r, depth=depth)
+    L, _ = inpaint_blocks(frame, res.warpL)
+    R, _ = inpaint_blocks(frame, res.warpR)
+    A = R.copy()
+    A[..., 0] = L[..., 0]
+    return L, R, A

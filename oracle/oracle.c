@@ -453,3 +453,76 @@ int oracle_gather(const uint8_t *frame, const uint8_t *Df, int w, int h, int B, 
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------ block-iterative inpainting */
+/* The inpainting algorithm of Fig. 3 (Section 4), as an alternative to the
+ * row fill.  Its pseudocode leaves the neighbourhood, the colour rule, the
+ * block size, the update order and the stopping rule open; the reading:
+ *   - damaged pixels are the holes of the forward warp (warp[y][x] < 0);
+ *   - one block is the whole frame;
+ *   - sweeps are simultaneous (Jacobi): in each sweep every pixel that is
+ *     damaged at its start and has at least two undamaged pixels among its
+ *     8 neighbours (at the sweep's start) becomes undamaged, with the mean of
+ *     those neighbours' colours per channel, rounded half up;
+ *   - the sweeps stop when one fills nothing; a pixel still damaged then keeps
+ *     its own source pixel (as the Fig. 3 code does for a destination whose
+ *     source is out of range).
+ * frame: source RGB24; warp: winning source x per destination (-1 = hole);
+ * out: the inpainted view.  Returns the number of sweeps that filled pixels,
+ * or a negative code. */
+int oracle_inpaint_blocks(const uint8_t *frame, const int32_t *warp, int w, int h, uint8_t *out) {
+    if (!frame || !warp || !out || w < 1 || h < 1) return ORC_E_INVALID;
+    const size_t n = (size_t)w * h;
+    uint8_t *dmg = (uint8_t *)malloc(n), *dmg2 = (uint8_t *)malloc(n);
+    uint8_t *col2 = (uint8_t *)malloc(n * 3);
+    if (!dmg || !dmg2 || !col2) {
+        free(dmg); free(dmg2); free(col2);
+        return ORC_E_NOMEM;
+    }
+    for (int y = 0; y < h; y++) {
+        for (int x = 0; x < w; x++) {
+            const size_t i = (size_t)y * w + x;
+            const int s = warp[i];
+            dmg[i] = s < 0;
+            for (int c = 0; c < 3; c++) out[i * 3 + c] = s < 0 ? 0 : frame[((size_t)y * w + s) * 3 + c];
+        }
+    }
+    int sweeps = 0;
+    for (;;) {
+        int filled = 0;
+        memcpy(dmg2, dmg, n);
+        memcpy(col2, out, n * 3);
+        for (int y = 0; y < h; y++) {
+            for (int x = 0; x < w; x++) {
+                const size_t i = (size_t)y * w + x;
+                if (!dmg[i]) continue;
+                int cnt = 0, sum[3] = {0, 0, 0};
+                for (int dy = -1; dy <= 1; dy++) {
+                    for (int dx = -1; dx <= 1; dx++) {
+                        if (!dx && !dy) continue;
+                        const int yy = y + dy, xx = x + dx;
+                        if (yy < 0 || yy >= h || xx < 0 || xx >= w) continue;
+                        const size_t j = (size_t)yy * w + xx;
+                        if (dmg[j]) continue;
+                        cnt++;
+                        for (int c = 0; c < 3; c++) sum[c] += out[j * 3 + c];
+                    }
+                }
+                if (cnt >= 2) {
+                    for (int c = 0; c < 3; c++) col2[i * 3 + c] = (uint8_t)((sum[c] + cnt / 2) / cnt);
+                    dmg2[i] = 0;
+                    filled++;
+                }
+            }
+        }
+        if (!filled) break;
+        memcpy(dmg, dmg2, n);
+        memcpy(out, col2, n * 3);
+        sweeps++;
+    }
+    for (size_t i = 0; i < n; i++)
+        if (dmg[i])
+            for (int c = 0; c < 3; c++) out[i * 3 + c] = frame[i * 3 + c];
+    free(dmg); free(dmg2); free(col2);
+    return sweeps;
+}

@@ -16,25 +16,27 @@ namespace pstereo {
 // ---------------------------------------------------------------------------
 // block statistics: per K x K block, rounded mean colour and edge flag.
 //
-// Tiles of 64 px x TH rows (TH = max(16, K)), 256 lanes: lane = one quad
-// (4 px) of one row, so K | 64 and K | TH keep every block inside one tile.
+// Tiles of 64 x 64 px, 256 lanes: lane = one quad (4 px) in each of four
+// rows 16 apart, so K | 64 keeps every block inside one tile.
 // Horizontal luma steps use the next pixel's bytes; vertical steps go through
 // an LDS tile of packed luma that also holds the first row below the tile.
 // The lanes of one block reduce by cross-lane xor within the wave, then one
 // LDS atomic per wave and block.
 template <int K>
 struct BsTile {
-    static constexpr int TH = K > 16 ? K : 16;  // tile rows
-    static constexpr int RPT = TH / 16;         // rows per lane
+    static constexpr int TH = 64;               // tile rows
+    static constexpr int RPT = TH / 16;         // rows per lane (16 rows apart)
     static constexpr int BC = 64 / K;           // block columns per tile
     static constexpr int BR = TH / K;           // block rows per tile
     static constexpr int QB = K / 4;            // quads per block row
     static constexpr int kLdsWords = (TH + 1) * 16 + BC * BR * 4;
 };
 
-// One 64 x TH tile (tile_x, tile_y) on 256 lanes t = 0..255 (a multiple of
-// four whole waves).  lds: BsTile<K>::kLdsWords words.  Inactive lanes groups
-// (active == false) do no memory work but pass the same two barriers.
+// One 64 x 64 tile (tile_x, tile_y) on 256 lanes t = 0..255 (a multiple of
+// four whole waves): lane t takes quad t % 16 of rows t / 16 + 16 k, k < 4,
+// with all four rows' loads in flight together.  lds: BsTile<K>::kLdsWords
+// words.  Inactive lane groups (active == false) do no memory work but pass
+// the same two barriers.
 template <int K, bool ALIGNED>
 __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile_y, int t, uint32_t* lds,
                                         bool active) {
@@ -50,43 +52,59 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
     const int n = min(4, W - x0);
     for (int i = t; i < BC * BR * 4; i += 256) acc[i] = 0;
 
-    uint32_t sr = 0, sg = 0, sb = 0;
-    int edge = 0;
+    uint32_t sr[RPT], sg[RPT], sb[RPT];
+    int edge[RPT];
     uint32_t yq[RPT];  // packed luma bytes of the lane's quad, one word per row
     const uint32_t g = (uint32_t)f.g;
+    if (ALIGNED) {
+        uint3 v[RPT];
+        uint32_t nx[RPT];
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int y = ty0 + tr + 16 * k;
-        yq[k] = 0;
-        if (y < H && x0 < W) {
-            const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
-            if (ALIGNED) {
-                // four pixels = three dwords; sums and luma by byte dot products
-                const uint3 v = *reinterpret_cast<const uint3*>(p);
-                sr = __builtin_amdgcn_udot4(v.x, 0x01000001u, sr, false);
-                sr = __builtin_amdgcn_udot4(v.y, 0x00010000u, sr, false);
-                sr = __builtin_amdgcn_udot4(v.z, 0x00000100u, sr, false);
-                sg = __builtin_amdgcn_udot4(v.x, 0x00000100u, sg, false);
-                sg = __builtin_amdgcn_udot4(v.y, 0x01000001u, sg, false);
-                sg = __builtin_amdgcn_udot4(v.z, 0x00010000u, sg, false);
-                sb = __builtin_amdgcn_udot4(v.x, 0x00010000u, sb, false);
-                sb = __builtin_amdgcn_udot4(v.y, 0x00000100u, sb, false);
-                sb = __builtin_amdgcn_udot4(v.z, 0x01000001u, sb, false);
-                constexpr uint32_t wlo = 77u | (150u << 8) | (29u << 16);
-                const uint32_t Y0 = __builtin_amdgcn_udot4(v.x, wlo, 128u, false) >> 8;
-                const uint32_t Y1 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(v.y, v.x, 3), wlo, 128u, false) >> 8;
-                const uint32_t Y2 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(v.z, v.y, 2), wlo, 128u, false) >> 8;
-                const uint32_t Y3 = __builtin_amdgcn_udot4(v.z, wlo << 8, 128u, false) >> 8;
-                uint32_t Yn = Y3;  // no step past the last column
-                if (x0 + 4 < W) {
-                    const uint32_t nx = *reinterpret_cast<const uint32_t*>(p + 12);
-                    Yn = __builtin_amdgcn_udot4(nx, wlo, 128u, false) >> 8;
-                }
-                const uint32_t hmax = max(max(__builtin_amdgcn_sad_u16(Y1, Y0, 0u), __builtin_amdgcn_sad_u16(Y2, Y1, 0u)),
-                                          max(__builtin_amdgcn_sad_u16(Y3, Y2, 0u), __builtin_amdgcn_sad_u16(Yn, Y3, 0u)));
-                if (hmax > g) edge = 1;
-                yq[k] = Y0 | (Y1 << 8) | (Y2 << 16) | (Y3 << 24);
-            } else {
+        for (int k = 0; k < RPT; ++k) {
+            const int y = ty0 + tr + 16 * k;
+            v[k] = make_uint3(0, 0, 0);
+            nx[k] = 0;
+            if (y < H && x0 < W) {
+                const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
+                v[k] = *reinterpret_cast<const uint3*>(p);
+                if (x0 + 4 < W) nx[k] = *reinterpret_cast<const uint32_t*>(p + 12);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            // four pixels = three dwords; sums and luma by byte dot products
+            sr[k] = __builtin_amdgcn_udot4(v[k].x, 0x01000001u, 0u, false);
+            sr[k] = __builtin_amdgcn_udot4(v[k].y, 0x00010000u, sr[k], false);
+            sr[k] = __builtin_amdgcn_udot4(v[k].z, 0x00000100u, sr[k], false);
+            sg[k] = __builtin_amdgcn_udot4(v[k].x, 0x00000100u, 0u, false);
+            sg[k] = __builtin_amdgcn_udot4(v[k].y, 0x01000001u, sg[k], false);
+            sg[k] = __builtin_amdgcn_udot4(v[k].z, 0x00010000u, sg[k], false);
+            sb[k] = __builtin_amdgcn_udot4(v[k].x, 0x00010000u, 0u, false);
+            sb[k] = __builtin_amdgcn_udot4(v[k].y, 0x00000100u, sb[k], false);
+            sb[k] = __builtin_amdgcn_udot4(v[k].z, 0x01000001u, sb[k], false);
+            constexpr uint32_t wlo = 77u | (150u << 8) | (29u << 16);
+            const uint32_t Y0 = __builtin_amdgcn_udot4(v[k].x, wlo, 128u, false) >> 8;
+            const uint32_t Y1 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(v[k].y, v[k].x, 3), wlo, 128u, false) >> 8;
+            const uint32_t Y2 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(v[k].z, v[k].y, 2), wlo, 128u, false) >> 8;
+            const uint32_t Y3 = __builtin_amdgcn_udot4(v[k].z, wlo << 8, 128u, false) >> 8;
+            const int y = ty0 + tr + 16 * k;
+            const uint32_t Yn = x0 + 4 < W ? __builtin_amdgcn_udot4(nx[k], wlo, 128u, false) >> 8 : Y3;  // no step past the last column
+            const uint32_t hmax = max(max(__builtin_amdgcn_sad_u16(Y1, Y0, 0u), __builtin_amdgcn_sad_u16(Y2, Y1, 0u)),
+                                      max(__builtin_amdgcn_sad_u16(Y3, Y2, 0u), __builtin_amdgcn_sad_u16(Yn, Y3, 0u)));
+            const bool in = y < H && x0 < W;
+            edge[k] = in && hmax > g;
+            yq[k] = in ? (Y0 | (Y1 << 8) | (Y2 << 16) | (Y3 << 24)) : 0u;
+            ytile[(tr + 16 * k) * 16 + qx] = yq[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int y = ty0 + tr + 16 * k;
+            sr[k] = sg[k] = sb[k] = 0;
+            edge[k] = 0;
+            yq[k] = 0;
+            if (y < H && x0 < W) {
+                const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
                 int r[4], gg[4], b[4], Y[4];
                 load_quad<false>(p, n, r, gg, b);
                 int ynext = 0;
@@ -96,14 +114,14 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if (j < n) {
-                        sr += r[j]; sg += gg[j]; sb += b[j];
+                        sr[k] += r[j]; sg[k] += gg[j]; sb[k] += b[j];
                         yq[k] |= (uint32_t)Y[j] << (8 * j);
-                        if (x0 + j + 1 < W && iabs((j < 3 ? Y[j + 1] : ynext) - Y[j]) > f.g) edge = 1;
+                        if (x0 + j + 1 < W && iabs((j < 3 ? Y[j + 1] : ynext) - Y[j]) > f.g) edge[k] = 1;
                     }
                 }
             }
+            ytile[(tr + 16 * k) * 16 + qx] = yq[k];
         }
-        ytile[(tr + 16 * k) * 16 + qx] = yq[k];
     }
     if (tr == 0) {
         // the first row below the tile, for the vertical steps of its last row
@@ -127,25 +145,31 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 if (j < n) vmax = max(vmax, __builtin_amdgcn_sad_u16((below >> (8 * j)) & 255u, (yq[k] >> (8 * j)) & 255u, 0u));
-            if (vmax > g) edge = 1;
+            if (vmax > g) edge[k] = 1;
         }
     }
-    // combine the lanes of one block: quads of a block row, and the four rows
-    // a wave covers (all inside one block row since K >= 4)
+    // per row group k: combine the lanes of one block -- quads of a block
+    // row, and the four rows a wave covers (inside one block row: they start
+    // at a multiple of 4 and K >= 4)
 #pragma unroll
-    for (int o = 1; o < QB && o < 16; o <<= 1) {
-        sr += __shfl_xor(sr, o); sg += __shfl_xor(sg, o); sb += __shfl_xor(sb, o); edge |= __shfl_xor(edge, o);
-    }
+    for (int k = 0; k < RPT; ++k) {
+        uint32_t a = sr[k], b = sg[k], c = sb[k];
+        int e = edge[k];
 #pragma unroll
-    for (int o = 16; o < 64; o <<= 1) {
-        sr += __shfl_xor(sr, o); sg += __shfl_xor(sg, o); sb += __shfl_xor(sb, o); edge |= __shfl_xor(edge, o);
-    }
-    if (lane < 16 && (qx % QB) == 0) {
-        const int blk = (qx / QB) + BC * ((4 * wave) / K % BR);
-        atomicAdd(&acc[4 * blk + 0], sr);
-        atomicAdd(&acc[4 * blk + 1], sg);
-        atomicAdd(&acc[4 * blk + 2], sb);
-        if (edge) atomicOr(&acc[4 * blk + 3], 1u);
+        for (int o = 1; o < QB && o < 16; o <<= 1) {
+            a += __shfl_xor(a, o); b += __shfl_xor(b, o); c += __shfl_xor(c, o); e |= __shfl_xor(e, o);
+        }
+#pragma unroll
+        for (int o = 16; o < 64; o <<= 1) {
+            a += __shfl_xor(a, o); b += __shfl_xor(b, o); c += __shfl_xor(c, o); e |= __shfl_xor(e, o);
+        }
+        if (lane < 16 && (qx % QB) == 0) {
+            const int blk = (qx / QB) + BC * ((16 * k + 4 * wave) / K);
+            atomicAdd(&acc[4 * blk + 0], a);
+            atomicAdd(&acc[4 * blk + 1], b);
+            atomicAdd(&acc[4 * blk + 2], c);
+            if (e) atomicOr(&acc[4 * blk + 3], 1u);
+        }
     }
     __syncthreads();
     for (int i = t; i < BC * BR; i += 256) {
@@ -728,18 +752,42 @@ __device__ __forceinline__ void rg_merge_body(const FrameDesc& f, uint32_t* lds)
     const int nbnd = (gh + SR - 1) / SR - 1;
     const int total = nbnd * gw;
     const uint32_t gwm = gw > 1 ? (uint32_t)((0x100000000ull + (uint32_t)gw - 1) / (uint32_t)gw) : 0u;
-    for (int q = t; q < total; q += kStripLanes) {
-        const int kb = (int)div_u16((uint32_t)q, gwm, (uint32_t)gw);
-        const int x = q - kb * gw;
-        const int b = ((kb + 1) * SR - 1) * gw + x, c = b + gw;
-        const uint32_t sb = f.stats[b], sc = f.stats[c];
-        const int la = f.labels[b], lc = f.labels[c];
-        bool join = linked(sb, sc, f.tau);
-        if (join && x > 0) {
-            const uint32_t sb1 = f.stats[b - 1], sc1 = f.stats[c - 1];
-            if (linked(sb1, sc1, f.tau) && f.labels[b - 1] == la && f.labels[c - 1] == lc) join = false;
+    // four boundary positions per lane at a time, every global load of the
+    // four issued before any is used
+    for (int q0 = t; q0 < total; q0 += 4 * kStripLanes) {
+        uint32_t sb[4], sc[4], sb1[4], sc1[4];
+        int la[4], lc[4], la1[4], lc1[4], xs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u * kStripLanes;
+            const int qq = q < total ? q : 0;
+            const int kb = (int)div_u16((uint32_t)qq, gwm, (uint32_t)gw);
+            const int x = qq - kb * gw;
+            const int b = ((kb + 1) * SR - 1) * gw + x, c = b + gw;
+            const int bl = x > 0 ? b - 1 : b, cl = x > 0 ? c - 1 : c;
+            xs[u] = q < total ? x : -1;
+            sb[u] = f.stats[b];
+            sc[u] = f.stats[c];
+            la[u] = f.labels[b];
+            lc[u] = f.labels[c];
+            sb1[u] = f.stats[bl];
+            sc1[u] = f.stats[cl];
+            la1[u] = f.labels[bl];
+            lc1[u] = f.labels[cl];
         }
-        if (join) ufl_unite(par, (uint32_t)f.rcid[la], (uint32_t)f.rcid[lc], lab);
+        uint32_t ua[4], uc[4];
+        bool join[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            join[u] = xs[u] >= 0 && linked(sb[u], sc[u], f.tau);
+            if (join[u] && xs[u] > 0 && linked(sb1[u], sc1[u], f.tau) && la1[u] == la[u] && lc1[u] == lc[u])
+                join[u] = false;
+            ua[u] = join[u] ? (uint32_t)f.rcid[la[u]] : 0u;
+            uc[u] = join[u] ? (uint32_t)f.rcid[lc[u]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (join[u]) ufl_unite(par, ua[u], uc[u], lab);
     }
     __syncthreads();
 

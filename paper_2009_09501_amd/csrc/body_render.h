@@ -92,6 +92,37 @@ __device__ __forceinline__ void quad_luma2(uint3 v, uint32_t& y01, uint32_t& y23
 // L1 distance to a block mean (stats word, edge byte zero for candidates) is
 // one v_sad_u8.  The nine neighbour loads are unconditional (clamped) so they
 // are all in flight together.
+// Raw depth of four pixels from a block table staged in LDS: tab holds the
+// blocks [bx_lo, bx_lo + bw) x [by_lo, ...) and covers every in-grid block the
+// lookup can touch; K = 1 << ks.
+__device__ __forceinline__ void quad_depth_tab(const FrameDesc& f, int x0, int yy, int ks, const uint2* tab,
+                                               int bx_lo, int by_lo, int bw, const uint32_t (&col)[4],
+                                               uint32_t (&D)[4]) {
+    const int bx = x0 >> ks, by = yy >> ks;
+    const uint2 own = tab[(by - by_lo) * bw + (bx - bx_lo)];
+    if (!(own.x >> 24)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) D[j] = own.y;
+        return;
+    }
+    uint32_t best[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    const uint32_t fallback = (uint32_t)ramp(by, f.gh);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) D[j] = fallback;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = bx + k % 3 - 1, cy = by + k / 3 - 1;
+        if (cx < 0 || cx >= f.gw || cy < 0 || cy >= f.gh) continue;
+        const uint2 c = tab[(cy - by_lo) * bw + (cx - bx_lo)];
+        if (c.x >> 24) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t dd = __builtin_amdgcn_sad_u8(col[j], c.x, 0u);
+            if (dd < best[j]) { best[j] = dd; D[j] = c.y; }
+        }
+    }
+}
+
 __device__ __forceinline__ void quad_depth(const FrameDesc& f, int x0, int yy, const uint32_t (&col)[4],
                                            uint32_t (&D)[4]) {
     const int bx = x0 / f.K, by = yy / f.K;
@@ -184,7 +215,11 @@ struct CbfTile {
     static constexpr int TR = kTileH + 2 * R;  // LDS rows incl. halo
     static constexpr int NK = k_count(R);
     // tY, tD: TR * kRowWords words each; wtab: NK * 256 u16; work: 512 u16; nwork
-    static constexpr int kLdsWords = 2 * TR * kRowWords + NK * 128 + 256 + 1;
+    // block table of the tile, its halo and one ring of neighbours: at most
+    // 21 x 13 blocks (K = 4, R = 3), uint2 each
+    static constexpr int kBlkEntries = 288;
+    static constexpr int kBlkOff = (2 * TR * kRowWords + NK * 128 + 256 + 1 + 1) & ~1;  // 8-byte aligned
+    static constexpr int kLdsWords = kBlkOff + 2 * kBlkEntries;
 };
 
 // One 64 x 32 tile (tile_x, tile_y) on 256 lanes t = 0..255 (four whole
@@ -202,9 +237,25 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
     uint16_t* work = wtab + NK * 256;
     int* nwork_p = reinterpret_cast<int*>(work + 512);
     int& nwork = *nwork_p;
+    uint2* btab = reinterpret_cast<uint2*>(lds + CbfTile<R>::kBlkOff);
 
     const int W = f.w, H = active ? f.h : 0;
     const int tx0 = tile_x * kTileW, ty0 = tile_y * kTileH;
+
+    // the tile's block table (halo and one ring of neighbours, clipped to the
+    // grid) into LDS, so the raw depth needs no global lookups
+    const int ks = __builtin_ctz((unsigned)f.K);
+    const int bx_lo = max(0, ((tx0 - 4) >> ks) - 1), bx_hi = min(f.gw - 1, ((tx0 + 4 * kTileQuads - 5) >> ks) + 1);
+    const int by_lo = max(0, ((ty0 - R) >> ks) - 1), by_hi = min(f.gh - 1, ((ty0 + kTileH - 1 + R) >> ks) + 1);
+    const int bw = bx_hi - bx_lo + 1;
+    if (!f.depth_in && H > 0) {
+        const int nbt = bw * (by_hi - by_lo + 1);
+        for (int i = t; i < nbt; i += 256) {
+            const int r = i / bw;
+            btab[i] = f.binfo[(by_lo + r) * f.gw + bx_lo + (i - r * bw)];
+        }
+    }
+    __syncthreads();
 
     // product weights ws[k] * wr[d] per distinct squared distance k
     for (int i = t; i < NK * 256; i += 256) wtab[i] = (uint16_t)(spatial_w(k_value(i >> 8)) * range_w(i & 255));
@@ -244,7 +295,7 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
 #pragma unroll
                 for (int j = 0; j < 4; ++j) D[j] = j < n ? dp[j] : 0u;
             } else {
-                quad_depth(f, x0, yy, col, D);
+                quad_depth_tab(f, x0, yy, ks, btab, bx_lo, by_lo, bw, col, D);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) if (j >= n) D[j] = 0;
@@ -374,6 +425,70 @@ __device__ __forceinline__ void store_px_bytes(uint8_t* p, uint32_t c) {
     p[2] = (uint8_t)(c >> 16);
 }
 
+// The outputs of four pixels x0..x0+3 of row y from their left / right view
+// colours (R | G << 8 | B << 16): left and right views, the anaglyph (red
+// from the left view, green and blue from the right), and the half
+// side-by-side frame when requested (half column p = mean of view columns 2p,
+// 2p + 1 rounded up per byte; left view in the first floor(W/2) columns,
+// right view after them).  ALIGNED: W % 4 == 0 and 4-byte aligned buffers,
+// four pixels = three dwords.
+template <bool ALIGNED>
+__device__ __forceinline__ void store_quad_views(const FrameDesc& f, int y, int x0, const uint32_t* cl,
+                                                 const uint32_t* cr) {
+    const int W = f.w;
+    const int n = min(4, W - x0);
+    const size_t off = ((size_t)y * W + x0) * 3;
+    auto store4 = [&](uint8_t* out, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
+        if (!out) return;
+        if (ALIGNED) {
+            uint3 v;
+            v.x = perm(c1, c0, 0x04020100u);
+            v.y = perm(c2, c1, 0x05040201u);
+            v.z = perm(c3, c2, 0x06050402u);
+            *reinterpret_cast<uint3*>(out + off) = v;
+        } else {
+            const uint32_t c[4] = {c0, c1, c2, c3};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j < n) {
+                    out[off + 3 * j] = (uint8_t)c[j];
+                    out[off + 3 * j + 1] = (uint8_t)(c[j] >> 8);
+                    out[off + 3 * j + 2] = (uint8_t)(c[j] >> 16);
+                }
+            }
+        }
+    };
+    store4(f.out_l, cl[0], cl[1], cl[2], cl[3]);
+    store4(f.out_r, cr[0], cr[1], cr[2], cr[3]);
+    store4(f.out_a, (cl[0] & 0xFFu) | (cr[0] & 0xFFFF00u), (cl[1] & 0xFFu) | (cr[1] & 0xFFFF00u),
+           (cl[2] & 0xFFu) | (cr[2] & 0xFFFF00u), (cl[3] & 0xFFu) | (cr[3] & 0xFFFF00u));
+    if (f.out_h) {
+        const int hw = W >> 1;
+        const uint32_t l0 = avg_bytes(cl[0], cl[1]), l1 = avg_bytes(cl[2], cl[3]);
+        const uint32_t r0 = avg_bytes(cr[0], cr[1]), r1 = avg_bytes(cr[2], cr[3]);
+        const int p0 = x0 >> 1;
+        uint8_t* row = f.out_h + (size_t)y * W * 3;
+        if (ALIGNED) {
+            // W % 4 == 0: both pairs exist, and both halves start at even
+            // byte offsets
+            store_px2_u16(row + (size_t)p0 * 3, l0, l1);
+            store_px2_u16(row + (size_t)(hw + p0) * 3, r0, r1);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int xa = x0 + 2 * k;
+                if (xa >= W) break;
+                const int pc = p0 + k;
+                const bool pair = xa + 1 < W;
+                const uint32_t lm = pair ? (k ? l1 : l0) : cl[2 * k];
+                const uint32_t rm = pair ? (k ? r1 : r0) : cr[2 * k];
+                if (pc < hw) store_px_bytes(row + (size_t)pc * 3, lm);
+                store_px_bytes(row + (size_t)(hw + pc) * 3, rm);
+            }
+        }
+    }
+}
+
 __host__ __device__ constexpr size_t warp_lds_bytes(int w, int threads, int q) {
     return (size_t)(2 * (((w + 3) & ~3) + ((w + 3) & ~3) / 32 + 1) * 4 + 256 * 4 + ((w + 3) & ~3) +
                     4 * q * (threads / 64) * 4);
@@ -477,6 +592,26 @@ __device__ __forceinline__ void warp_row(const FrameDesc& f, int y, int t, int N
             const int s0 = 4 * ((i >> 2) * NT + t) + (i & 3) - o0R;
             if ((unsigned)s0 < (unsigned)W && drow_l[s0] == 0) vR |= 1u << i;
         }
+    }
+    if (f.ipc) {
+        // block-iterative inpainting follows: leave the warped colours and the
+        // holes, no row fill
+        const size_t plane = (size_t)f.w * f.h;
+#pragma unroll
+        for (int qi = 0; qi < Q; ++qi) {
+            const int x0 = 4 * (qi * NT + t);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = 4 * qi + j;
+                if (!((own >> i) & 1u)) continue;
+                const size_t o = (size_t)y * W + x0 + j;
+                f.ipc[o] = kl[i] & 0xFFFFFFu;
+                f.ipt[o] = ((vL >> i) & 1u) ? 0 : 0xFFFF;
+                f.ipc[plane + o] = kr[i] & 0xFFFFFFu;
+                f.ipt[plane + o] = ((vR >> i) & 1u) ? 0 : 0xFFFF;
+            }
+        }
+        return;
     }
     // per chunk: ballot of the quads holding a valid pixel; the chunk's
     // extremes go to LDS for the other chunks
@@ -588,69 +723,106 @@ __device__ __forceinline__ void warp_row(const FrameDesc& f, int y, int t, int N
         }
     }
 
-    // ---- anaglyph and stores: four R | G << 8 | B << 16 words -> three dwords
+    // ---- anaglyph and stores
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
         const int x0 = 4 * (qi * NT + t);
-        if (x0 >= W) continue;
-        const int n = min(4, W - x0);
-        const size_t off = ((size_t)y * W + x0) * 3;
-        auto store4 = [&](uint8_t* out, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
-            if (!out) return;
-            if (ALIGNED) {
-                uint3 v;
-                v.x = perm(c1, c0, 0x04020100u);
-                v.y = perm(c2, c1, 0x05040201u);
-                v.z = perm(c3, c2, 0x06050402u);
-                *reinterpret_cast<uint3*>(out + off) = v;
-            } else {
-                const uint32_t c[4] = {c0, c1, c2, c3};
+        if (x0 < W) store_quad_views<ALIGNED>(f, y, x0, &cl[4 * qi], &cr[4 * qi]);
+    }
+}
+
+// LDS bytes of the gather row: the shift table and the row's source colours.
+__host__ __device__ constexpr size_t gather_lds_bytes(int w) {
+    return (size_t)(256 + ((w + 3) & ~3) + (((w + 3) & ~3) >> 5) + 1) * 4;  // 256 + kidx(W4) + 1 words
+}
+
+// Image row y by the Fig. 3 gather (Section 4): each destination pixel reads
+// the filtered depth at its own position and copies the source pixel its
+// view's offset points back to (its own source pixel when that lies outside
+// the row); no occlusion test, no holes.  The source row's colours are staged
+// in LDS (padded every 32 words) so the gathers are LDS reads.
+template <bool ALIGNED>
+__device__ __forceinline__ void gather_row(const FrameDesc& f, int y, int t, int NT, uint32_t* lds) {
+    const int W = f.w;
+    uint32_t* lut = lds;           // 256 entries
+    uint32_t* rowc = lut + 256;    // source colours, kidx-indexed
+    for (int d = t; d < 256; d += NT) lut[d] = shift_entry(d, f.B, f.T);
+    const uint8_t* src = f.frame + (size_t)y * W * 3;
+    for (int x0 = 4 * t; x0 < W; x0 += 4 * NT) {
+        uint32_t c[4];
+        if (ALIGNED) {
+            quad_colours(*reinterpret_cast<const uint3*>(src + (size_t)x0 * 3), c);
+        } else {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (j < n) {
-                        out[off + 3 * j] = (uint8_t)c[j];
-                        out[off + 3 * j + 1] = (uint8_t)(c[j] >> 8);
-                        out[off + 3 * j + 2] = (uint8_t)(c[j] >> 16);
-                    }
-                }
-            }
-        };
-        store4(f.out_l, cl[4 * qi], cl[4 * qi + 1], cl[4 * qi + 2], cl[4 * qi + 3]);
-        store4(f.out_r, cr[4 * qi], cr[4 * qi + 1], cr[4 * qi + 2], cr[4 * qi + 3]);
-        // anaglyph: red from the left view, green and blue from the right
-        store4(f.out_a, (cl[4 * qi] & 0xFFu) | (cr[4 * qi] & 0xFFFF00u),
-               (cl[4 * qi + 1] & 0xFFu) | (cr[4 * qi + 1] & 0xFFFF00u),
-               (cl[4 * qi + 2] & 0xFFu) | (cr[4 * qi + 2] & 0xFFFF00u),
-               (cl[4 * qi + 3] & 0xFFu) | (cr[4 * qi + 3] & 0xFFFF00u));
-        // half side-by-side: half column p = mean of view columns 2p, 2p + 1
-        // (rounded up per byte); left view in the first floor(W/2) columns,
-        // right view after them
-        if (f.out_h) {
-            const int hw = W >> 1;
-            const uint32_t l0 = avg_bytes(cl[4 * qi], cl[4 * qi + 1]), l1 = avg_bytes(cl[4 * qi + 2], cl[4 * qi + 3]);
-            const uint32_t r0 = avg_bytes(cr[4 * qi], cr[4 * qi + 1]), r1 = avg_bytes(cr[4 * qi + 2], cr[4 * qi + 3]);
-            const int p0 = x0 >> 1;
-            uint8_t* row = f.out_h + (size_t)y * W * 3;
-            if (ALIGNED) {
-                // W % 4 == 0: both pairs exist, and both halves start at even
-                // byte offsets
-                store_px2_u16(row + (size_t)p0 * 3, l0, l1);
-                store_px2_u16(row + (size_t)(hw + p0) * 3, r0, r1);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const int xa = x0 + 2 * k;
-                    if (xa >= W) break;
-                    const int pc = p0 + k;
-                    const bool pair = xa + 1 < W;
-                    const uint32_t lm = pair ? (k ? l1 : l0) : cl[4 * qi + 2 * k];
-                    const uint32_t rm = pair ? (k ? r1 : r0) : cr[4 * qi + 2 * k];
-                    if (pc < hw) store_px_bytes(row + (size_t)pc * 3, lm);
-                    store_px_bytes(row + (size_t)(hw + pc) * 3, rm);
-                }
+            for (int j = 0; j < 4; ++j) {
+                const uint8_t* p = src + (size_t)(x0 + j) * 3;
+                c[j] = x0 + j < W ? (p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16)) : 0u;
             }
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rowc[kidx(x0 + j)] = c[j];
     }
+    __syncthreads();
+    const uint8_t* drow = f.df + (size_t)y * W;
+    for (int x0 = 4 * t; x0 < W; x0 += 4 * NT) {
+        uint32_t dq = 0;
+        if (ALIGNED) {
+            dq = *reinterpret_cast<const uint32_t*>(drow + x0);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (x0 + j < W) dq |= (uint32_t)drow[x0 + j] << (8 * j);
+        }
+        uint32_t cl[4], cr[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = x0 + j;
+            const uint32_t lv = lut[(dq >> (8 * j)) & 255u];
+            int xl = x - (int)(int16_t)(lv & 0xFFFFu);
+            int xr = x - (int)(int16_t)(lv >> 16);
+            if ((unsigned)xl >= (unsigned)W) xl = x;
+            if ((unsigned)xr >= (unsigned)W) xr = x;
+            cl[j] = x < W ? rowc[kidx(xl)] : 0u;
+            cr[j] = x < W ? rowc[kidx(xr)] : 0u;
+        }
+        store_quad_views<ALIGNED>(f, y, x0, cl, cr);
+    }
+}
+
+// One Jacobi sweep of the block-iterative inpainting over pixel p = (x, y) of
+// view v: a hole (tag 0xFFFF) with at least two undamaged 8-neighbours --
+// tag below `sweep`, so pixels filled in this same sweep do not count --
+// takes their per-channel mean rounded half up and the tag `sweep`.  Updates
+// in place are safe: a pixel written in this sweep is never read as
+// undamaged in it.  Returns 1 if p was filled.
+__device__ __forceinline__ int inpaint_pixel(const FrameDesc& f, int v, int x, int y, int sweep) {
+    const int W = f.w, H = f.h;
+    const size_t plane = (size_t)W * H * v;
+    const size_t o = plane + (size_t)y * W + x;
+    if (f.ipt[o] != 0xFFFF) return 0;
+    int cnt = 0;
+    uint32_t s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (!dx && !dy) continue;
+            const int xx = x + dx, yy = y + dy;
+            if ((unsigned)xx >= (unsigned)W || (unsigned)yy >= (unsigned)H) continue;
+            const size_t q = plane + (size_t)yy * W + xx;
+            if ((int)f.ipt[q] >= sweep) continue;
+            const uint32_t c = f.ipc[q];
+            ++cnt;
+            s0 += c & 255u;
+            s1 += (c >> 8) & 255u;
+            s2 += c >> 16;
+        }
+    }
+    if (cnt < 2) return 0;
+    const uint32_t h = (uint32_t)cnt >> 1;
+    f.ipc[o] = ((s0 + h) / cnt) | (((s1 + h) / cnt) << 8) | (((s2 + h) / cnt) << 16);
+    f.ipt[o] = (uint16_t)sweep;
+    return 1;
 }
 
 }  // namespace pstereo

@@ -177,11 +177,11 @@ __device__ __forceinline__ int frame_of(const int* first, int n, int idx) {
     return lo;
 }
 
-constexpr int kBsLdsMax = BsTile<64>::kLdsWords > BsTile<8>::kLdsWords ? BsTile<64>::kLdsWords : BsTile<8>::kLdsWords;
+constexpr int kBsLdsMax = BsTile<4>::kLdsWords;  // the largest: most blocks per tile
 
 __global__ void __launch_bounds__(256) k_mf_blockstats(const FrameDesc* frames, const int* first, int n) {
-    static_assert(BsTile<4>::kLdsWords <= kBsLdsMax && BsTile<16>::kLdsWords <= kBsLdsMax &&
-                  BsTile<32>::kLdsWords <= kBsLdsMax, "blockstats LDS");
+    static_assert(BsTile<8>::kLdsWords <= kBsLdsMax && BsTile<16>::kLdsWords <= kBsLdsMax &&
+                  BsTile<32>::kLdsWords <= kBsLdsMax && BsTile<64>::kLdsWords <= kBsLdsMax, "blockstats LDS");
     __shared__ uint32_t lds[kBsLdsMax];
     const int idx = blockIdx.x;
     const int fi = frame_of(first, n, idx);
@@ -261,7 +261,7 @@ hipError_t launch_staged(const FrameDesc* d_frames, const int* d_first, const St
 int batch_tasks(const FrameDesc& f, int phase, int* items, int* gx) {
     switch (phase) {
         case 0: {
-            const int th = f.K > 16 ? f.K : 16;
+            const int th = 64;  // block-statistics tile rows
             *gx = (f.w + 63) / 64;
             *items = *gx * ((f.h + th - 1) / th);
             return (*items + 3) / 4;

@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(256) k_rg_final(FrameDesc f) { rg_final_block(
 
 template <int K, bool A>
 static LaunchSpec bs_spec(const FrameDesc& f) {
-    constexpr int TH = K > 16 ? K : 16;
+    constexpr int TH = BsTile<K>::TH;
     return {reinterpret_cast<const void*>(&k_blockstats<K, A>), dim3((f.w + 63) / 64, (f.h + TH - 1) / TH),
             dim3(256), 0};
 }

@@ -19,6 +19,54 @@ __global__ void __launch_bounds__(1024) k_warp(FrameDesc f) {
     warp_row<ALIGNED, Q>(f, blockIdx.x, threadIdx.x, blockDim.x, lds, true);
 }
 
+template <bool ALIGNED>
+__global__ void __launch_bounds__(256) k_gather(FrameDesc f) {
+    extern __shared__ uint32_t lds[];
+    gather_row<ALIGNED>(f, blockIdx.x, threadIdx.x, blockDim.x, lds);
+}
+
+__global__ void k_inpaint_reset(FrameDesc f) {
+    for (int i = threadIdx.x; i <= kMaxSweeps; i += blockDim.x) f.ipn[i] = i == 0 ? 1u : 0u;
+}
+
+// Sweep `sweep` over both views (blockIdx.y); nothing to do once the
+// previous sweep filled no pixel.
+__global__ void __launch_bounds__(256) k_inpaint_sweep(FrameDesc f, int sweep) {
+    if (f.ipn[sweep - 1] == 0) return;
+    const int W = f.w;
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int qw = (W + 3) >> 2;
+    int filled = 0;
+    if (q < qw * f.h) {
+        const int y = q / qw, x0 = 4 * (q - y * qw);
+        for (int j = 0; j < 4 && x0 + j < W; ++j) filled += inpaint_pixel(f, blockIdx.y, x0 + j, y, sweep);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) filled += __shfl_xor(filled, o);
+    if ((threadIdx.x & 63) == 0 && filled) atomicAdd(&f.ipn[sweep], (uint32_t)filled);
+}
+
+// The views from the inpainted colours (pixels never filled keep their own
+// source pixel), then the anaglyph and the half side-by-side frame.
+template <bool ALIGNED>
+__global__ void __launch_bounds__(256) k_inpaint_final(FrameDesc f) {
+    const int W = f.w;
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int qw = (W + 3) >> 2;
+    if (q >= qw * f.h) return;
+    const int y = q / qw, x0 = 4 * (q - y * qw);
+    const size_t plane = (size_t)W * f.h;
+    uint32_t cl[4] = {0, 0, 0, 0}, cr[4] = {0, 0, 0, 0};
+    for (int j = 0; j < 4 && x0 + j < W; ++j) {
+        const size_t o = (size_t)y * W + x0 + j;
+        const uint8_t* sp = f.frame + o * 3;
+        const uint32_t src = sp[0] | ((uint32_t)sp[1] << 8) | ((uint32_t)sp[2] << 16);
+        cl[j] = f.ipt[o] == 0xFFFF ? src : f.ipc[o];
+        cr[j] = f.ipt[plane + o] == 0xFFFF ? src : f.ipc[plane + o];
+    }
+    store_quad_views<ALIGNED>(f, y, x0, cl, cr);
+}
+
 // ---------------------------------------------------------------------------
 // host-side launch helpers
 
@@ -67,6 +115,35 @@ static LaunchSpec warp_q(const FrameDesc& f, const WarpShape& ws) {
 
 LaunchSpec spec_warp(const FrameDesc& f, const WarpShape& ws) { return f.aligned ? warp_q<true>(f, ws) : warp_q<false>(f, ws); }
 
+bool gather_fits(int w) { return gather_lds_bytes(w) <= kMaxLds; }
+
+static dim3 quad_grid(const FrameDesc& f, int views) {
+    const long long quads = (long long)((f.w + 3) / 4) * f.h;
+    return dim3((unsigned)((quads + 255) / 256), views);
+}
+
+hipError_t launch_inpaint_reset(const FrameDesc& f, hipStream_t s) {
+    hipLaunchKernelGGL(k_inpaint_reset, dim3(1), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_inpaint_sweep(const FrameDesc& f, int sweep, hipStream_t s) {
+    hipLaunchKernelGGL(k_inpaint_sweep, quad_grid(f, 2), dim3(256), 0, s, f, sweep);
+    return hipGetLastError();
+}
+
+hipError_t launch_inpaint_final(const FrameDesc& f, hipStream_t s) {
+    if (f.aligned) hipLaunchKernelGGL(k_inpaint_final<true>, quad_grid(f, 1), dim3(256), 0, s, f);
+    else hipLaunchKernelGGL(k_inpaint_final<false>, quad_grid(f, 1), dim3(256), 0, s, f);
+    return hipGetLastError();
+}
+
+LaunchSpec spec_gather(const FrameDesc& f) {
+    const void* fn = f.aligned ? reinterpret_cast<const void*>(&k_gather<true>)
+                               : reinterpret_cast<const void*>(&k_gather<false>);
+    return {fn, dim3(f.h), dim3(256), gather_lds_bytes(f.w)};
+}
+
 template <bool A, int Q>
 static hipError_t allow_lds() {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_warp<A, Q>),
@@ -80,7 +157,12 @@ hipError_t prepare_render_kernels() {
     if ((e = allow_lds<true, 4>()) != hipSuccess) return e;
     if ((e = allow_lds<false, 1>()) != hipSuccess) return e;
     if ((e = allow_lds<false, 2>()) != hipSuccess) return e;
-    return allow_lds<false, 4>();
+    if ((e = allow_lds<false, 4>()) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds)) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
 }
 
 }  // namespace pstereo

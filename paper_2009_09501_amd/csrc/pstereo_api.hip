@@ -2,6 +2,7 @@
 // sequence of one frame, per-kernel event timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -36,6 +37,11 @@ struct pstereo_ctx {
     uint32_t* d_rrow = nullptr;
     uint32_t* d_rfin = nullptr;
     uint32_t* d_rctl = nullptr;
+    // block-iterative inpainting scratch, allocated on first use
+    uint32_t* d_ipc = nullptr;
+    uint16_t* d_ipt = nullptr;
+    uint32_t* d_ipn = nullptr;
+    uint32_t* h_ipn = nullptr;  // pinned read-back of one sweep counter
     std::string err;
     // last generated-depth call, for pstereo_debug_blocks
     bool have_blocks = false;
@@ -176,6 +182,10 @@ int pstereo_destroy(pstereo_ctx* c) {
     (void)hipFree(c->d_rrow);
     (void)hipFree(c->d_rfin);
     (void)hipFree(c->d_rctl);
+    (void)hipFree(c->d_ipc);
+    (void)hipFree(c->d_ipt);
+    (void)hipFree(c->d_ipn);
+    if (c->h_ipn) (void)hipHostFree(c->h_ipn);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     (void)hipGetLastError();
     delete c;
@@ -244,8 +254,13 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
         for (int j = i + 1; j < 6; ++j)
             if (overlap(rout[i], rout[j])) return fail(c, PSTEREO_E_ALIAS, "%s overlaps %s", rout[i].name, rout[j].name);
     }
-    if (!pstereo::warp_shape(w, ws))
+    const bool gather = (p.flags & PSTEREO_WARP_GATHER) != 0;
+    if (gather && (p.flags & PSTEREO_INPAINT_BLOCKS))
+        return fail(c, PSTEREO_E_INVALID, "PSTEREO_WARP_GATHER leaves no holes to inpaint");
+    if (!gather && !pstereo::warp_shape(w, ws))
         return fail(c, PSTEREO_E_UNSUPPORTED, "width %d exceeds the warp kernel's LDS budget", w);
+    if (gather && !pstereo::gather_fits(w))
+        return fail(c, PSTEREO_E_UNSUPPORTED, "width %d exceeds the gather kernel's LDS budget", w);
 
     FrameDesc f{};
     f.frame = frame;
@@ -278,6 +293,7 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
     f.r = p.cbf_radius;
     const uintptr_t al = (uintptr_t)frame | (uintptr_t)out_l | (uintptr_t)out_r | (uintptr_t)out_a;
     f.aligned = (w % 4 == 0) && (al % 4 == 0);
+    f.gather = gather ? 1 : 0;
     *fd = f;
     *stream = p.stream ? (hipStream_t)p.stream : c->stream;
     *flags = p.flags;
@@ -312,7 +328,7 @@ void frame_specs(const FrameDesc& f, const WarpShape& ws, pstereo::LaunchSpec (&
     st[n] = 2;
     ls[n++] = pstereo::spec_cbf(f);
     st[n] = 3;
-    ls[n++] = pstereo::spec_warp(f, ws);
+    ls[n++] = f.gather ? pstereo::spec_gather(f) : pstereo::spec_warp(f, ws);
     if (stage)
         for (int i = 0; i < n; ++i) (*stage)[i] = st[i];
 }
@@ -326,7 +342,7 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
     if (!c) return PSTEREO_E_INVALID;
     c->err.clear();
     FrameDesc f;
-    WarpShape ws;
+    WarpShape ws{};
     hipStream_t s;
     uint32_t flags;
     int rc = build_desc(c, frame, w, h, pin, out_l, out_r, out_a, &f, &ws, &s, &flags);
@@ -334,6 +350,29 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
     const bool ext = f.depth_in != nullptr;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return fail(c, PSTEREO_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+
+    const bool inpaint = (flags & PSTEREO_INPAINT_BLOCKS) != 0;
+    if (inpaint) {
+        if (!c->d_ipc) {
+            const size_t px = (size_t)c->max_w * c->max_h;
+            if (hipMalloc(&c->d_ipc, 2 * px * sizeof(uint32_t)) != hipSuccess ||
+                hipMalloc(&c->d_ipt, 2 * px * sizeof(uint16_t)) != hipSuccess ||
+                hipMalloc(&c->d_ipn, (pstereo::kMaxSweeps + 1) * sizeof(uint32_t)) != hipSuccess ||
+                hipHostMalloc(&c->h_ipn, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipFree(c->d_ipc);
+                (void)hipFree(c->d_ipt);
+                (void)hipFree(c->d_ipn);
+                c->d_ipc = nullptr;
+                c->d_ipt = nullptr;
+                c->d_ipn = nullptr;
+                return fail(c, PSTEREO_E_NOMEM, "inpainting scratch allocation failed");
+            }
+        }
+        f.ipc = c->d_ipc;
+        f.ipt = c->d_ipt;
+        f.ipn = c->d_ipn;
+    }
 
     const bool prof = (flags & PSTEREO_PROFILE) != 0;
     hipEvent_t* ev = nullptr;
@@ -366,8 +405,29 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
     for (int i = 0; i < n; ++i) {
         if ((e = pstereo::launch(ls[i], f, s)) != hipSuccess)
             return fail(c, PSTEREO_E_DEVICE, "%s launch: %s", names[stage[i]], hipGetErrorString(e));
-        // one event at the end of each stage
-        if (prof && (i + 1 == n || stage[i + 1] != stage[i])) (void)hipEventRecord(ev[stage[i] + 1], s);
+        // one event at the end of each stage (the inpainting sweeps belong
+        // to the warp stage)
+        if (prof && (i + 1 == n || stage[i + 1] != stage[i]) && !(inpaint && stage[i] == 3))
+            (void)hipEventRecord(ev[stage[i] + 1], s);
+    }
+    if (inpaint) {
+        // sweeps in chunks of 8 until one fills nothing (each sweep returns at
+        // once after a sweep that filled nothing)
+        if ((e = pstereo::launch_inpaint_reset(f, s)) != hipSuccess)
+            return fail(c, PSTEREO_E_DEVICE, "inpainting launch: %s", hipGetErrorString(e));
+        for (int sw = 1; sw <= pstereo::kMaxSweeps; sw += 8) {
+            const int last = std::min(sw + 7, pstereo::kMaxSweeps);
+            for (int k = sw; k <= last; ++k)
+                if ((e = pstereo::launch_inpaint_sweep(f, k, s)) != hipSuccess)
+                    return fail(c, PSTEREO_E_DEVICE, "inpainting sweep: %s", hipGetErrorString(e));
+            if ((e = hipMemcpyAsync(c->h_ipn, f.ipn + last, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return fail(c, PSTEREO_E_DEVICE, "inpainting convergence check: %s", hipGetErrorString(e));
+            if (*c->h_ipn == 0) break;
+        }
+        if ((e = pstereo::launch_inpaint_final(f, s)) != hipSuccess)
+            return fail(c, PSTEREO_E_DEVICE, "inpainting composition: %s", hipGetErrorString(e));
+        if (prof) (void)hipEventRecord(ev[4], s);
     }
     if (!ext) {
         c->have_blocks = true;
@@ -497,8 +557,9 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
             return fail(c, PSTEREO_E_INVALID, "params.struct_size %u != %zu", p->struct_size, sizeof(pstereo_params));
         pp = *p;
     }
-    if (pp.flags & PSTEREO_DEPTH_EXTERNAL)
-        return fail(c, PSTEREO_E_UNSUPPORTED, "video replay generates the depth map (no PSTEREO_DEPTH_EXTERNAL)");
+    if (pp.flags & (PSTEREO_DEPTH_EXTERNAL | PSTEREO_WARP_GATHER | PSTEREO_INPAINT_BLOCKS))
+        return fail(c, PSTEREO_E_UNSUPPORTED, "video replay generates the depth map and warps (no "
+                                              "PSTEREO_DEPTH_EXTERNAL / PSTEREO_WARP_GATHER)");
     if (pp.out_depth || pp.out_depth_raw || pp.out_hsbs)
         return fail(c, PSTEREO_E_UNSUPPORTED, "video replay takes no depth dumps");
     pstereo_video* v = new (std::nothrow) pstereo_video;
@@ -544,7 +605,7 @@ int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, 
     pstereo_ctx* c = v->ctx;
     c->err.clear();
     FrameDesc f;
-    WarpShape ws;
+    WarpShape ws{};
     hipStream_t s;
     uint32_t flags;
     int rc = build_desc(c, frame, v->w, v->h, &v->params, out_l, out_r, out_a, &f, &ws, &s, &flags);

@@ -190,7 +190,8 @@ int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, con
         if (pin->struct_size != sizeof(pstereo_params)) return bfail(b, PSTEREO_E_INVALID, "params.struct_size mismatch");
         p = *pin;
     }
-    if (p.flags & PSTEREO_DEPTH_EXTERNAL) return bfail(b, PSTEREO_E_UNSUPPORTED, "batches generate their depth maps");
+    if (p.flags & (PSTEREO_DEPTH_EXTERNAL | PSTEREO_WARP_GATHER | PSTEREO_INPAINT_BLOCKS))
+        return bfail(b, PSTEREO_E_UNSUPPORTED, "batches generate their depth maps and warp");
     if (p.out_depth || p.out_depth_raw || p.out_hsbs)
         return bfail(b, PSTEREO_E_UNSUPPORTED, "batches take no depth dumps or half side-by-side output");
     if (p.depth_threshold < -1 || p.depth_threshold > 255) return bfail(b, PSTEREO_E_INVALID, "depth_threshold out of range");

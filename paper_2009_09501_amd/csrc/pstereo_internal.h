@@ -34,6 +34,13 @@ struct FrameDesc {
     int K, gw, gh;           // depth block size and grid
     int B, T, g, tau, r;     // method parameters
     int aligned;             // w % 4 == 0 and every RGB24 pointer 4-byte aligned
+    int gather;              // reconstruct by the Fig. 3 gather instead of the warp and fill
+    // block-iterative inpainting (ipc != null): the warp leaves, per view, the
+    // warped colour and a fill tag (0 landed, 0xFFFF hole, s = filled by sweep
+    // s) for the sweeps and the final composition
+    uint32_t* ipc;           // colours, [2][h][w]
+    uint16_t* ipt;           // tags, [2][h][w]
+    uint32_t* ipn;           // pixels filled per sweep, [kMaxSweeps + 1]
 };
 
 // Launch shape of the warp kernel (one image row per workgroup).
@@ -66,6 +73,14 @@ LaunchSpec spec_rg_merge(const FrameDesc& f);
 LaunchSpec spec_rg_final(const FrameDesc& f);
 LaunchSpec spec_cbf(const FrameDesc& f);
 LaunchSpec spec_warp(const FrameDesc& f, const WarpShape& ws);
+// Block-iterative inpainting: counter reset, one Jacobi sweep, composition.
+constexpr int kMaxSweeps = 4096;
+hipError_t launch_inpaint_reset(const FrameDesc& f, hipStream_t s);
+hipError_t launch_inpaint_sweep(const FrameDesc& f, int sweep, hipStream_t s);
+hipError_t launch_inpaint_final(const FrameDesc& f, hipStream_t s);
+// Fig. 3 gather in place of the warp and the fill (one row per workgroup).
+bool gather_fits(int w);
+LaunchSpec spec_gather(const FrameDesc& f);
 
 // Launch one spec on a stream (hipSuccess or the launch error).
 inline hipError_t launch(const LaunchSpec& ls, const FrameDesc& f, hipStream_t s) {

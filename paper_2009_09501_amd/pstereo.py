@@ -26,6 +26,8 @@ PSTEREO_E_BUSY = -6
 PSTEREO_DEPTH_EXTERNAL = 0x1
 PSTEREO_SYNC = 0x2
 PSTEREO_PROFILE = 0x4
+PSTEREO_WARP_GATHER = 0x8
+PSTEREO_INPAINT_BLOCKS = 0x10
 
 PSTEREO_MAX_BLOCKS = 32768
 

@@ -210,3 +210,29 @@ def gather(frame, Df, B, T=150):
             R[y][x] = tuple(frame[y][xr])
             A[y][x] = (L[y][x][0], R[y][x][1], R[y][x][2])
     return L, R, A
+
+
+def inpaint_blocks(frame, warp):
+    """Block-iterative inpainting, written out: damaged = warp < 0; Jacobi
+    sweeps fill every damaged pixel with >= 2 undamaged 8-neighbours by their
+    rounded-half-up mean; stop when a sweep fills nothing; leftovers keep the
+    source pixel."""
+    h, w = len(warp), len(warp[0])
+    dmg = [[warp[y][x] < 0 for x in range(w)] for y in range(h)]
+    col = [[(0, 0, 0) if warp[y][x] < 0 else tuple(frame[y][warp[y][x]]) for x in range(w)] for y in range(h)]
+    while True:
+        upd = {}
+        for y in range(h):
+            for x in range(w):
+                if not dmg[y][x]:
+                    continue
+                nb = [col[yy][xx] for yy in range(y - 1, y + 2) for xx in range(x - 1, x + 2)
+                      if (yy, xx) != (y, x) and 0 <= yy < h and 0 <= xx < w and not dmg[yy][xx]]
+                if len(nb) >= 2:
+                    upd[(y, x)] = tuple(round_half_up(Fraction(sum(c[k] for c in nb), len(nb))) for k in range(3))
+        if not upd:
+            break
+        for (y, x), c in upd.items():
+            col[y][x] = c
+            dmg[y][x] = False
+    return [[tuple(frame[y][x]) if dmg[y][x] else col[y][x] for x in range(w)] for y in range(h)]

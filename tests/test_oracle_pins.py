@@ -500,3 +500,44 @@ def test_gather_invariants(oracle_mod):
     a, b = int(oL[200]), int(-oR[200])  # 5 and 4
     assert np.array_equal(gL[:, a:], fw.L[:, a:]) and np.array_equal(gL[:, :a], f[:, :a])
     assert np.array_equal(gR[:, :50 - b], fw.R[:, :50 - b]) and np.array_equal(gR[:, 50 - b:], f[:, 50 - b:])
+
+
+# --------------------------------------- block-iterative inpainting
+@pytest.mark.parametrize("seed", range(8))
+def test_inpaint_blocks_brute_force(oracle_mod, seed):
+    rng = np.random.default_rng(500 + seed)
+    h, w = int(rng.integers(1, 9)), int(rng.integers(1, 14))
+    f = rng.integers(0, 256, (h, w, 3), dtype=np.uint8)
+    warp = np.where(rng.random((h, w)) < 0.45, -1, rng.integers(0, w, (h, w))).astype(np.int32)
+    got, _ = oracle_mod.inpaint_blocks(f, warp)
+    want = np.array(brute.inpaint_blocks(f.tolist(), warp.tolist()), np.uint8).reshape(h, w, 3)
+    assert np.array_equal(got, want)
+
+
+def test_inpaint_blocks_closed_forms(oracle_mod):
+    rng = np.random.default_rng(8)
+    f = rng.integers(0, 256, (5, 9, 3), dtype=np.uint8)
+    ident = np.tile(np.arange(9, dtype=np.int32), (5, 1))
+    # no holes: the warped view itself
+    v, sweeps = oracle_mod.inpaint_blocks(f, ident)
+    assert np.array_equal(v, f) and sweeps == 0
+    # a single hole inside a constant image takes the constant in one sweep
+    c = np.full((5, 9, 3), 90, np.uint8)
+    wp = ident.copy()
+    wp[2, 4] = -1
+    v, sweeps = oracle_mod.inpaint_blocks(c, wp)
+    assert np.array_equal(v, c) and sweeps == 1
+    # a 1-row frame: a hole with one undamaged neighbour is never filled and
+    # keeps its source pixel; one between two valid pixels takes their mean
+    row = np.array([[[10, 0, 0], [20, 0, 0], [30, 0, 0], [71, 0, 0]]], np.uint8)
+    v, _ = oracle_mod.inpaint_blocks(row, np.array([[-1, 1, -1, 3]], np.int32))
+    assert v[0, 0].tolist() == [10, 0, 0] and v[0, 2].tolist() == [46, 0, 0]  # (20 + 71 + 1) // 2
+    v, _ = oracle_mod.inpaint_blocks(row, np.array([[0, -1, -1, 3]], np.int32))
+    assert v[0, 1].tolist() == [20, 0, 0] and v[0, 2].tolist() == [30, 0, 0]
+    # a vertical 2-px-wide hole band in a 3-row frame fills from both sides in one sweep
+    band = np.tile(np.arange(6, dtype=np.int32), (3, 1))
+    band[:, 2:4] = -1
+    v, sweeps = oracle_mod.inpaint_blocks(f[:3, :6], band)
+    assert sweeps == 1
+    top = [f[0, 1], f[1, 1]]
+    assert v[0, 2].tolist() == [int((int(top[0][k]) + int(top[1][k]) + 1) // 2) for k in range(3)]
