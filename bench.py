@@ -319,8 +319,8 @@ def main() -> int:
                     help="extra launch forms measured after the plain path (video, batch, serve, host; "
                          "empty = none)")
     ap.add_argument("--host-frames", type=int, default=120)
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain device copy of a known size (to scale HBM byte counters)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device copies of MIB MiB (to scale HBM byte counters)")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-burst", type=int, default=16)
     ap.add_argument("--form-steps", type=int, default=60)
@@ -337,9 +337,9 @@ def main() -> int:
     import torch
 
     if args.calibrate_copy:
-        # 512 MiB device-to-device copies: a kernel whose HBM traffic is known
-        # (read 512 MiB + write 512 MiB per launch)
-        n = 512 << 20
+        # device-to-device copies of a known size, larger than the 256 MB
+        # Infinity Cache: a kernel whose HBM traffic is known (read n + write n)
+        n = args.calibrate_copy << 20
         src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(10):

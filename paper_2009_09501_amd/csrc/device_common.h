@@ -88,4 +88,15 @@ __device__ __forceinline__ void store_quad(uint8_t* p, int n, const int (&r)[4],
 
 constexpr size_t kMaxLds = 160 * 1024;
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear workgroup id.
+// Tile for workgroup bid of n: each XCD gets one contiguous run of tiles in
+// raster order, so neighbouring tiles -- sharing halo rows and the 128-byte
+// lines across tile borders -- meet in the same L2.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_tile(int bid, int n) {
+    constexpr int X = 8;
+    const int q = n / X, r = n - q * X;
+    const int xcd = bid % X, idx = bid / X;
+    return xcd * q + min(xcd, r) + idx;
+}
+
 }  // namespace pstereo

@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(256) k_mf_blockstats(const FrameDesc* frames, 
     static_assert(BsTile<8>::kLdsWords <= kBsLdsMax && BsTile<16>::kLdsWords <= kBsLdsMax &&
                   BsTile<32>::kLdsWords <= kBsLdsMax && BsTile<64>::kLdsWords <= kBsLdsMax, "blockstats LDS");
     __shared__ uint32_t lds[kBsLdsMax];
-    const int idx = blockIdx.x;
+    const int idx = xcd_tile(blockIdx.x, gridDim.x);
     const int fi = frame_of(first, n, idx);
     const FrameDesc f = frames[fi];
     const int local = idx - first[fi];
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(kRegionThreads) k_mf_regions(const FrameDesc* 
 template <int R>
 __global__ void __launch_bounds__(256) k_mf_cbf(const FrameDesc* frames, const int* first, int n) {
     __shared__ uint32_t lds[CbfTile<R>::kLdsWords];
-    const int idx = blockIdx.x;
+    const int idx = xcd_tile(blockIdx.x, gridDim.x);
     const int fi = frame_of(first, n, idx);
     const FrameDesc f = frames[fi];
     const int local = idx - first[fi];

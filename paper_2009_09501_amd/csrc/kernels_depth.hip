@@ -11,7 +11,10 @@ namespace pstereo {
 template <int K, bool ALIGNED>
 __global__ void __launch_bounds__(256) k_blockstats(FrameDesc f) {
     __shared__ uint32_t lds[BsTile<K>::kLdsWords];
-    bs_tile<K, ALIGNED>(f, blockIdx.x, blockIdx.y, threadIdx.x, lds, true);
+    const int gx = gridDim.x;
+    const int tile = xcd_tile(blockIdx.y * gx + blockIdx.x, gx * gridDim.y);
+    const int ty = tile / gx;
+    bs_tile<K, ALIGNED>(f, tile - ty * gx, ty, threadIdx.x, lds, true);
 }
 
 __global__ void __launch_bounds__(kRegionThreads) k_regions(FrameDesc f) {

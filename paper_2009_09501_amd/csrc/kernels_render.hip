@@ -10,7 +10,10 @@ namespace pstereo {
 template <int R, bool ALIGNED>
 __global__ void __launch_bounds__(256) k_cbf(FrameDesc f) {
     __shared__ uint32_t lds[CbfTile<R>::kLdsWords];
-    cbf_tile<R, ALIGNED>(f, blockIdx.x, blockIdx.y, threadIdx.x, lds, true);
+    const int gx = gridDim.x;
+    const int tile = xcd_tile(blockIdx.y * gx + blockIdx.x, gx * gridDim.y);
+    const int ty = tile / gx;
+    cbf_tile<R, ALIGNED>(f, tile - ty * gx, ty, threadIdx.x, lds, true);
 }
 
 template <bool ALIGNED, int Q>
