@@ -151,24 +151,27 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
     // per row group k: combine the lanes of one block -- quads of a block
     // row, and the four rows a wave covers (inside one block row: they start
     // at a multiple of 4 and K >= 4)
+    // Two 16-bit sums per register: a wave holds at most 64 quads of a block
+    // (16 per row x 4 rows at K = 64), 64 x 4 x 255 < 2^16.
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-        uint32_t a = sr[k], b = sg[k], c = sb[k];
-        int e = edge[k];
+        uint32_t rg = sr[k] | (sg[k] << 16), be = sb[k] | ((uint32_t)edge[k] << 16);
 #pragma unroll
         for (int o = 1; o < QB && o < 16; o <<= 1) {
-            a += __shfl_xor(a, o); b += __shfl_xor(b, o); c += __shfl_xor(c, o); e |= __shfl_xor(e, o);
+            rg += __shfl_xor(rg, o);
+            be += __shfl_xor(be, o);
         }
 #pragma unroll
         for (int o = 16; o < 64; o <<= 1) {
-            a += __shfl_xor(a, o); b += __shfl_xor(b, o); c += __shfl_xor(c, o); e |= __shfl_xor(e, o);
+            rg += __shfl_xor(rg, o);
+            be += __shfl_xor(be, o);
         }
         if (lane < 16 && (qx % QB) == 0) {
             const int blk = (qx / QB) + BC * ((16 * k + 4 * wave) / K);
-            atomicAdd(&acc[4 * blk + 0], a);
-            atomicAdd(&acc[4 * blk + 1], b);
-            atomicAdd(&acc[4 * blk + 2], c);
-            if (e) atomicOr(&acc[4 * blk + 3], 1u);
+            atomicAdd(&acc[4 * blk + 0], rg & 0xFFFFu);
+            atomicAdd(&acc[4 * blk + 1], rg >> 16);
+            atomicAdd(&acc[4 * blk + 2], be & 0xFFFFu);
+            if (be >> 16) atomicOr(&acc[4 * blk + 3], 1u);
         }
     }
     __syncthreads();

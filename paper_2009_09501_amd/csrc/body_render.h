@@ -242,6 +242,22 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
     const int W = f.w, H = active ? f.h : 0;
     const int tx0 = tile_x * kTileW, ty0 = tile_y * kTileH;
 
+    // the frame loads of all of a lane's quads of the tile and its halo go
+    // out first, to arrive while the block table is staged
+    constexpr int NQ = (TR * kTileQuads + 255) / 256;
+    uint3 vq[NQ];
+    if (ALIGNED) {
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) {
+            const int i = t + 256 * k;
+            const int tr = i / kTileQuads, tq = i - tr * kTileQuads;
+            const int yy = ty0 - R + tr, x0 = tx0 - 4 + 4 * tq;
+            vq[k] = make_uint3(0, 0, 0);
+            if (i < TR * kTileQuads && yy >= 0 && yy < H && x0 >= 0 && x0 < W)
+                vq[k] = *reinterpret_cast<const uint3*>(f.frame + ((size_t)yy * W + x0) * 3);
+        }
+    }
+
     // the tile's block table (halo and one ring of neighbours, clipped to the
     // grid) into LDS, so the raw depth needs no global lookups
     const int ks = __builtin_ctz((unsigned)f.K);
@@ -261,8 +277,12 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
     for (int i = t; i < NK * 256; i += 256) wtab[i] = (uint16_t)(spatial_w(k_value(i >> 8)) * range_w(i & 255));
     if (t == 0) nwork = 0;
 
-    // doubled luma + raw depth of the tile and its halo (columns tx0-4 .. tx0+67)
-    for (int i = t; i < TR * kTileQuads; i += 256) {
+    // doubled luma + raw depth of the tile and its halo (columns tx0-4 ..
+    // tx0+67)
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        const int i = t + 256 * k;
+        if (i >= TR * kTileQuads) break;
         const int tr = i / kTileQuads, tq = i - tr * kTileQuads;
         const int yy = ty0 - R + tr;
         const int x0 = tx0 - 4 + 4 * tq;
@@ -272,7 +292,7 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
             const uint8_t* p = f.frame + ((size_t)yy * W + x0) * 3;
             uint32_t col[4], D[4];
             if (ALIGNED) {
-                const uint3 v = *reinterpret_cast<const uint3*>(p);
+                const uint3 v = vq[k];
                 quad_luma2(v, y01, y23);
                 quad_colours(v, col);
             } else {
@@ -494,11 +514,54 @@ __host__ __device__ constexpr size_t warp_lds_bytes(int w, int threads, int q) {
                     4 * q * (threads / 64) * 4);
 }
 
-// Image row y on NT lanes t = 0..NT-1 (whole waves).  lds: warp_lds_bytes(w,
-// NT, Q) bytes.  Inactive lane groups do no memory work but pass the same
-// three barriers.
+// A lane's share of one image row: the frame bytes of its Q quads (three
+// raw dwords per quad when aligned, else four decoded R | G << 8 | B << 16
+// colours) and their filtered depths.
 template <bool ALIGNED, int Q>
-__device__ __forceinline__ void warp_row(const FrameDesc& f, int y, int t, int NT, uint32_t* lds, bool active) {
+struct WarpRowIn {
+    static constexpr int kPerQuad = ALIGNED ? 3 : 4;
+    uint32_t c[kPerQuad * Q];
+    uint32_t dq[Q];
+};
+
+template <bool ALIGNED, int Q>
+__device__ __forceinline__ void warp_load(const FrameDesc& f, int y, int t, int NT, WarpRowIn<ALIGNED, Q>& in) {
+    constexpr int P = WarpRowIn<ALIGNED, Q>::kPerQuad;
+    const int W = f.w;
+    const uint8_t* drow = f.df + (size_t)y * W;
+#pragma unroll
+    for (int qi = 0; qi < Q; ++qi) {
+        const int x0 = 4 * (qi * NT + t);
+#pragma unroll
+        for (int j = 0; j < P; ++j) in.c[P * qi + j] = 0;
+        in.dq[qi] = 0;
+        if (x0 >= W) continue;
+        if (ALIGNED) {
+            const uint3 v = *reinterpret_cast<const uint3*>(f.frame + ((size_t)y * W + x0) * 3);
+            in.c[P * qi] = v.x;
+            in.c[P * qi + 1] = v.y;
+            in.c[P * qi + 2] = v.z;
+            in.dq[qi] = *reinterpret_cast<const uint32_t*>(drow + x0);
+        } else {
+            const int n = min(4, W - x0);
+            const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                in.c[P * qi + j] = j < n ? (p[3 * j] | ((uint32_t)p[3 * j + 1] << 8) | ((uint32_t)p[3 * j + 2] << 16)) : 0u;
+                if (j < n) in.dq[qi] |= (uint32_t)drow[x0 + j] << (8 * j);
+            }
+        }
+    }
+}
+
+// Image row y on NT lanes t = 0..NT-1 (whole waves) from the lane's loaded
+// share `in`; when next_y >= 0 the share of row next_y is loaded into `next`
+// while this row's holes are filled.  lds: warp_lds_bytes(w, NT, Q) bytes.
+// Inactive lane groups do no memory work but pass the same three barriers.
+template <bool ALIGNED, int Q>
+__device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, int NT, uint32_t* lds, bool active,
+                                              const WarpRowIn<ALIGNED, Q>& in, int next_y,
+                                              WarpRowIn<ALIGNED, Q>& next) {
     const int W = active ? f.w : 0;
     const int lane = t & 63, wave = t >> 6, NW = NT >> 6;
     const int NC = Q * NW;  // chunks per row
@@ -517,32 +580,29 @@ __device__ __forceinline__ void warp_row(const FrameDesc& f, int y, int t, int N
     // ---- forward warp of the row's pixels into both views; the key carries
     // the depth above the colour, so the atomic max keeps the nearer source
     // and its colour
-    const uint8_t* drow = f.df + (size_t)y * W;
     uint32_t col[4 * Q];  // own source colours, R | G << 8 | B << 16
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
-        const int x0 = 4 * (qi * NT + t);
+        if (ALIGNED) {
+            uint32_t c4[4];
+            quad_colours(make_uint3(in.c[3 * qi], in.c[3 * qi + 1], in.c[3 * qi + 2]), c4);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) col[4 * qi + j] = 0;
+            for (int j = 0; j < 4; ++j) col[4 * qi + j] = c4[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) col[4 * qi + j] = in.c[4 * qi + j];
+        }
+    }
+#pragma unroll
+    for (int qi = 0; qi < Q; ++qi) {
+        const int x0 = 4 * (qi * NT + t);
         if (x0 >= W) continue;
         const int n = min(4, W - x0);
-        uint32_t dq = 0;
-        uint32_t c[4];
-        if (ALIGNED) {
-            quad_colours(*reinterpret_cast<const uint3*>(f.frame + ((size_t)y * W + x0) * 3), c);
-            dq = *reinterpret_cast<const uint32_t*>(drow + x0);
-        } else {
-            const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                c[j] = j < n ? (p[3 * j] | ((uint32_t)p[3 * j + 1] << 8) | ((uint32_t)p[3 * j + 2] << 16)) : 0u;
-                if (j < n) dq |= (uint32_t)drow[x0 + j] << (8 * j);
-            }
-        }
+        const uint32_t dq = in.dq[qi];
+        const uint32_t* c = &col[4 * qi];
         *reinterpret_cast<uint32_t*>(drow_l + x0) = dq;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            col[4 * qi + j] = c[j];
             if (j >= n) continue;
             const int x = x0 + j;
             const uint32_t d = (dq >> (8 * j)) & 255u;
@@ -555,6 +615,9 @@ __device__ __forceinline__ void warp_row(const FrameDesc& f, int y, int t, int N
         }
     }
     __syncthreads();
+
+    // the next row's share is loaded while this row is resolved and filled
+    if (next_y >= 0) warp_load<ALIGNED, Q>(f, next_y, t, NT, next);
 
     // ---- validity: a landed source has a non-zero key, except a black source
     // of depth 0, whose key is 0; such a source is the only one that can land
@@ -823,6 +886,36 @@ __device__ __forceinline__ int inpaint_pixel(const FrameDesc& f, int v, int x, i
     f.ipc[o] = ((s0 + h) / cnt) | (((s1 + h) / cnt) << 8) | (((s2 + h) / cnt) << 16);
     f.ipt[o] = (uint16_t)sweep;
     return 1;
+}
+
+// One image row (the single-row form used by the batch kernels).
+template <bool ALIGNED, int Q>
+__device__ __forceinline__ void warp_row(const FrameDesc& f, int y, int t, int NT, uint32_t* lds, bool active) {
+    WarpRowIn<ALIGNED, Q> in, unused;
+    if (active) {
+        warp_load<ALIGNED, Q>(f, y, t, NT, in);
+    } else {
+#pragma unroll
+        for (int i = 0; i < WarpRowIn<ALIGNED, Q>::kPerQuad * Q; ++i) in.c[i] = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) in.dq[i] = 0;
+    }
+    warp_row_body<ALIGNED, Q>(f, y, t, NT, lds, active, in, -1, unused);
+}
+
+// Rows y0, y0 + step, ... of the frame, each row's loads issued during the
+// previous row's hole fill.
+template <bool ALIGNED, int Q>
+__device__ __forceinline__ void warp_rows(const FrameDesc& f, int y0, int step, int t, int NT, uint32_t* lds) {
+    if (y0 >= f.h) return;
+    WarpRowIn<ALIGNED, Q> cur, nxt;
+    warp_load<ALIGNED, Q>(f, y0, t, NT, cur);
+    for (int y = y0; y < f.h; y += step) {
+        if (y != y0) __syncthreads();  // the previous row's last LDS reads are done
+        const int ny = y + step < f.h ? y + step : -1;
+        warp_row_body<ALIGNED, Q>(f, y, t, NT, lds, true, cur, ny, nxt);
+        cur = nxt;
+    }
 }
 
 }  // namespace pstereo

@@ -3,6 +3,8 @@
 // body_render.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "body_render.h"
 
 namespace pstereo {
@@ -16,10 +18,22 @@ __global__ void __launch_bounds__(256) k_cbf(FrameDesc f) {
     cbf_tile<R, ALIGNED>(f, tile - ty * gx, ty, threadIdx.x, lds, true);
 }
 
+// Rows blockIdx.x, blockIdx.x + gridDim.x, ...: a grid of at most a few
+// workgroups per CU walks the rows, loading each next row during the current
+// one.
 template <bool ALIGNED, int Q>
-__global__ void __launch_bounds__(1024) k_warp(FrameDesc f) {
+__global__ void __launch_bounds__(512) k_warp(FrameDesc f) {
     extern __shared__ uint32_t lds[];
-    warp_row<ALIGNED, Q>(f, blockIdx.x, threadIdx.x, blockDim.x, lds, true);
+    warp_rows<ALIGNED, Q>(f, blockIdx.x, gridDim.x, threadIdx.x, blockDim.x, lds);
+}
+
+// Rows needing four quads per lane (wider than 4096 px): one row per
+// workgroup of up to 1024 lanes (a second row's prefetched share would not
+// fit the register budget).
+template <bool ALIGNED>
+__global__ void __launch_bounds__(1024) k_warp_wide(FrameDesc f) {
+    extern __shared__ uint32_t lds[];
+    warp_row<ALIGNED, 4>(f, blockIdx.x, threadIdx.x, blockDim.x, lds, true);
 }
 
 template <bool ALIGNED>
@@ -73,7 +87,8 @@ __global__ void __launch_bounds__(256) k_inpaint_final(FrameDesc f) {
 // ---------------------------------------------------------------------------
 // host-side launch helpers
 
-bool warp_shape(int w, WarpShape* out) { return warp_shape_cap(w, 256, out); }
+// The plain path: up to 512 lanes per row before four quads per lane.
+bool warp_shape(int w, WarpShape* out) { return warp_shape_cap(w, 512, out); }
 
 bool warp_shape_cap(int w, int cap, WarpShape* out) {
     const int quads = (w + 3) / 4;
@@ -110,10 +125,16 @@ LaunchSpec spec_cbf(const FrameDesc& f) { return f.aligned ? cbf_r<true>(f) : cb
 
 template <bool A>
 static LaunchSpec warp_q(const FrameDesc& f, const WarpShape& ws) {
+    if (ws.quads == 4)
+        return {reinterpret_cast<const void*>(&k_warp_wide<A>), dim3(f.h), dim3(ws.threads), ws.lds_bytes};
     const void* fn = ws.quads == 1 ? reinterpret_cast<const void*>(&k_warp<A, 1>)
-                   : ws.quads == 2 ? reinterpret_cast<const void*>(&k_warp<A, 2>)
-                   : ws.quads == 4 ? reinterpret_cast<const void*>(&k_warp<A, 4>) : nullptr;
-    return {fn, dim3(f.h), dim3(ws.threads), ws.lds_bytes};
+                   : ws.quads == 2 ? reinterpret_cast<const void*>(&k_warp<A, 2>) : nullptr;
+    // resident workgroups per CU by LDS and lanes, times 256 CUs; every
+    // workgroup gets at least one row
+    const int by_lds = std::max(1, (int)(kMaxLds / std::max<size_t>(ws.lds_bytes, 1)));
+    const int by_lanes = std::max(1, 2048 / ws.threads);
+    const int resident = std::min(by_lds, by_lanes) * 256;
+    return {fn, dim3(std::min(f.h, resident)), dim3(ws.threads), ws.lds_bytes};
 }
 
 LaunchSpec spec_warp(const FrameDesc& f, const WarpShape& ws) { return f.aligned ? warp_q<true>(f, ws) : warp_q<false>(f, ws); }
@@ -147,6 +168,12 @@ LaunchSpec spec_gather(const FrameDesc& f) {
     return {fn, dim3(f.h), dim3(256), gather_lds_bytes(f.w)};
 }
 
+template <bool A>
+static hipError_t allow_lds_wide() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_warp_wide<A>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+}
+
 template <bool A, int Q>
 static hipError_t allow_lds() {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_warp<A, Q>),
@@ -157,10 +184,10 @@ hipError_t prepare_render_kernels() {
     hipError_t e;
     if ((e = allow_lds<true, 1>()) != hipSuccess) return e;
     if ((e = allow_lds<true, 2>()) != hipSuccess) return e;
-    if ((e = allow_lds<true, 4>()) != hipSuccess) return e;
     if ((e = allow_lds<false, 1>()) != hipSuccess) return e;
     if ((e = allow_lds<false, 2>()) != hipSuccess) return e;
-    if ((e = allow_lds<false, 4>()) != hipSuccess) return e;
+    if ((e = allow_lds_wide<true>()) != hipSuccess) return e;
+    if ((e = allow_lds_wide<false>()) != hipSuccess) return e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<true>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds)) != hipSuccess)
         return e;
