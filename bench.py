@@ -314,6 +314,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--frames", type=int, default=4, help="distinct synthetic frames cycled")
+    ap.add_argument("--profile-every", type=int, default=8,
+                    help="record per-stage HIP events on every N-th timed step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="video,batch,serve,host",
                     help="extra launch forms measured after the plain path (video, batch, serve, host; "
@@ -369,11 +371,23 @@ def main() -> int:
         ctx.synthesize(frames[i % len(frames)], out=outs, stream=stream, **params)
     torch.cuda.synchronize()
     pstereo_profile_collect(ctx.handle)  # clear
+    # the cost of an event record itself, from back-to-back event pairs on
+    # the same stream; subtracted from the event-bracketed stage durations
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(64)]
+    for a, b in pairs:
+        a.record(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ev_overhead_ms = statistics.median(a.elapsed_time(b) for a, b in pairs)
 
+    # per-stage HIP events on every `sample`-th timed step: each event record
+    # adds a few microseconds of stream time, so recording them on every step
+    # would slow the throughput being measured
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        ctx.synthesize(frames[i % len(frames)], out=outs, stream=stream, flags=PSTEREO_PROFILE, **params)
+        fl = PSTEREO_PROFILE if i % args.profile_every == 0 else 0
+        ctx.synthesize(frames[i % len(frames)], out=outs, stream=stream, flags=fl, **params)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_sum, count, per_call = pstereo_profile_collect(ctx.handle)
@@ -382,7 +396,8 @@ def main() -> int:
     px = W * H
     kern_s = {k: ms_sum[i] / count / 1e3 for i, k in enumerate(KERNELS)}
     dom = max(kern_s, key=kern_s.get)
-    achieved = KERNEL_BYTES_PER_PX[dom] * px / kern_s[dom] / 1e9
+    dom_s = max(kern_s[dom] - ev_overhead_ms / 1e3, 1e-9)
+    achieved = KERNEL_BYTES_PER_PX[dom] * px / dom_s / 1e9
     pipe_s = sum(ms_sum) / count / 1e3
     lat = sorted(per_call)
     traffic = _traffic(dom, "4k")
@@ -406,7 +421,9 @@ def main() -> int:
                    "path": "plain"},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "duration_us": round(dom_s * 1e6, 3), "event_overhead_us": round(ev_overhead_ms * 1e3, 3),
+                     "bytes_per_launch": KERNEL_BYTES_PER_PX[dom] * px},
         "kernels_ms": {k: round(v * 1e3, 5) for k, v in kern_s.items()},
         "kernels_hbm_frac": {k: round(KERNEL_BYTES_PER_PX[k] * px / v / 1e9 / HBM_PEAK_GBS, 4)
                              for k, v in kern_s.items()},
