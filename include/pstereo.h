@@ -151,8 +151,11 @@ const char *pstereo_last_error(const pstereo_ctx *ctx);
 
 /*
  * Per-block intermediate results of the last pstereo_synthesize on ctx with a
- * generated depth map (for inspection and parity tests).  Waits for that
- * call's stream.  Host buffers of `cap` entries each (any may be NULL):
+ * generated depth map (for inspection and parity tests); no other call may
+ * have used the context since.  The per-block labels and depths are
+ * materialised here (one small kernel on that call's stream, the first time),
+ * then the call waits for the stream.  Host buffers of `cap` entries each
+ * (any may be NULL):
  *   stats   uint32 per block: mean R | mean G << 8 | mean B << 16 | edge << 24
  *   labels  int32 per block: region label = smallest block index of the region
  *   dblk    uint8 per block: region depth
@@ -164,8 +167,8 @@ int pstereo_debug_blocks(pstereo_ctx *ctx, uint32_t *stats, int32_t *labels,
 
 /*
  * Kernel timing.  Each pstereo_synthesize with PSTEREO_PROFILE records HIP
- * events on its stream around its four kernels (block statistics, region
- * grouping, depth filter, warp).  This call waits for the recorded events,
+ * events on its stream at the ends of its four stages (block statistics,
+ * region grouping, depth filter, warp; a stage may be several kernels).  This call waits for the recorded events,
  * writes the summed kernel durations in milliseconds to ms_sum[0..3] and the number
  * of profiled calls to *count, and clears the record.  If per_call_ms is not
  * NULL it receives, in call order, up to cap per-call durations (first event

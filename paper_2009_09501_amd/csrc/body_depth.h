@@ -611,7 +611,7 @@ __device__ __forceinline__ bool linked(uint32_t s, uint32_t n, int tau) {
     return !((s | n) >> 24) && (int)__builtin_amdgcn_sad_u8(s, n, 0u) <= tau;
 }
 
-__host__ __device__ constexpr size_t rg_strip_lds_words() { return 2 * kStripBlocks + 3 * kStripBlocks + 4; }
+__host__ __device__ constexpr size_t rg_strip_lds_words() { return 3 * kStripBlocks + 3 * kStripBlocks + 4; }
 
 __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uint32_t* lds) {
     const int gw = f.gw, gh = f.gh, SR = f.rstrip;
@@ -621,10 +621,12 @@ __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uin
     const int n = rows * gw, base = r0 * gw;
     const int nload = (r0 + rows < gh ? rows + 1 : rows) * gw;
     uint32_t* st = lds;                      // statistics of the strip and the row below
-    uint32_t* par = st + 2 * kStripBlocks;   // union-find
+    uint32_t* sa = st + 2 * kStripBlocks;    // statistics of the row above the strip
+    uint32_t* par = sa + kStripBlocks;       // union-find
     uint32_t* cnt = par + kStripBlocks;      // per root: non-edge blocks
     uint32_t* row = cnt + kStripBlocks;      // per root: lowest local row + 1
-    uint32_t* misc = row + kStripBlocks;     // [0]: slots of this strip, [1]: first slot
+    uint32_t* misc = row + kStripBlocks;     // [0]: slots of this strip, [1]: its first slot,
+                                             // [2]: its join candidates, [3]: their first entry
     uint32_t* binfo_w = reinterpret_cast<uint32_t*>(f.binfo);
     const uint32_t gwm = gw > 1 ? (uint32_t)((0x100000000ull + (uint32_t)gw - 1) / (uint32_t)gw) : 0u;
 
@@ -633,6 +635,8 @@ __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uin
         st[j] = s;
         if (j < n) binfo_w[2 * (base + j)] = s;
     }
+    if (r0 > 0)
+        for (int j = t; j < gw; j += kStripLanes) sa[j] = f.stats[base - gw + j];
     for (int j = t; j < n; j += kStripLanes) {
         par[j] = j;
         cnt[j] = 0;
@@ -715,6 +719,35 @@ __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uin
             }
         }
     }
+
+    // join candidates across the boundary above the strip: the down links
+    // from the row above into the first row, except where block x - 1 links
+    // the same pair of components (right links in both rows and a down link)
+    if (r0 > 0) {
+        if (t == 0) misc[2] = 0;
+        __syncthreads();
+        uint32_t cand[2] = {0u, 0u};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int x = t + k * kStripLanes;
+            if (x >= gw || !linked(sa[x], st[x], f.tau)) continue;
+            if (x > 0 && linked(sa[x - 1], st[x - 1], f.tau) && linked(sa[x - 1], sa[x], f.tau) &&
+                linked(st[x - 1], st[x], f.tau))
+                continue;
+            cand[k] = atomicAdd(&misc[2], 1u) + 1u;
+        }
+        __syncthreads();
+        if (t == 0) misc[3] = atomicAdd(&f.rctl[2], misc[2]);
+        __syncthreads();
+        const uint32_t bfirst = misc[3];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int x = t + k * kStripLanes;
+            if (!cand[k]) continue;
+            const uint32_t idx = bfirst + cand[k] - 1u;
+            if (idx < (uint32_t)kBoundSlots) f.rbnd[idx] = make_uint2((uint32_t)(base - gw + x), (uint32_t)base + root[k]);
+        }
+    }
 }
 
 __host__ __device__ constexpr size_t rg_merge_lds_words() { return 4 * (size_t)kRegionSlots + 4; }
@@ -729,6 +762,7 @@ __device__ __forceinline__ void rg_merge_body(const FrameDesc& f, uint32_t* lds)
         if (t == 0) {
             f.rctl[0] = 0;
             f.rctl[1] = 1;
+            f.rctl[2] = 0;
         }
         return;
     }
@@ -755,8 +789,16 @@ __device__ __forceinline__ void rg_merge_body(const FrameDesc& f, uint32_t* lds)
     const int nbnd = (gh + SR - 1) / SR - 1;
     const int total = nbnd * gw;
     const uint32_t gwm = gw > 1 ? (uint32_t)((0x100000000ull + (uint32_t)gw - 1) / (uint32_t)gw) : 0u;
-    // four boundary positions per lane at a time, every global load of the
-    // four issued before any is used
+    const uint32_t ncand = f.rctl[2];
+    if (ncand <= (uint32_t)kBoundSlots) {
+        // the strips' compacted join candidates
+        for (uint32_t q = t; q < ncand; q += kStripLanes) {
+            const uint2 e = f.rbnd[q];
+            ufl_unite(par, (uint32_t)f.rcid[f.labels[e.x]], (uint32_t)f.rcid[e.y], lab);
+        }
+    } else
+    // every boundary position, four per lane at a time, every global load of
+    // the four issued before any is used
     for (int q0 = t; q0 < total; q0 += 4 * kStripLanes) {
         uint32_t sb[4], sc[4], sb1[4], sc1[4];
         int la[4], lc[4], la1[4], lc1[4], xs[4];
@@ -822,6 +864,7 @@ __device__ __forceinline__ void rg_merge_body(const FrameDesc& f, uint32_t* lds)
     if (t == 0) {
         f.rctl[0] = 0;
         f.rctl[1] = 0;
+        f.rctl[2] = 0;
     }
 }
 

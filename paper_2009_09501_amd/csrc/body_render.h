@@ -85,16 +85,23 @@ __device__ __forceinline__ void quad_luma2(uint3 v, uint32_t& y01, uint32_t& y23
     y23 = perm(r3, r2, 0x0c050c01u) << 1;
 }
 
+// Region depth of block b (row by, statistics s) after the strip-parallel
+// grouping: edge blocks and the background follow the row ramp, other blocks
+// take their merged component's depth from the slot of their strip-local
+// label.
+__device__ __forceinline__ uint32_t block_depth_from_slots(const FrameDesc& f, int b, int by, uint32_t s) {
+    if (s >> 24) return (uint32_t)ramp(by, f.gh);
+    const uint32_t v = f.rfin[f.rcid[f.labels[b]]];
+    return ((v >> 8) & 1u) ? (uint32_t)ramp(by, f.gh) : (v & 255u);
+}
+
 // Raw depth of the four pixels of a quad: the region depth of their block, or
 // for an edge block that of the non-edge 3x3 neighbour block whose mean colour
 // is nearest (L1), first strict minimum in raster order; with no candidate
 // the ramp of the block row.  col[j] = R | G << 8 | B << 16 of pixel j; the
 // L1 distance to a block mean (stats word, edge byte zero for candidates) is
-// one v_sad_u8.  The nine neighbour loads are unconditional (clamped) so they
-// are all in flight together.
-// Raw depth of four pixels from a block table staged in LDS: tab holds the
-// blocks [bx_lo, bx_lo + bw) x [by_lo, ...) and covers every in-grid block the
-// lookup can touch; K = 1 << ks.
+// one v_sad_u8.  The blocks come from a table staged in LDS: tab holds the blocks [bx_lo, bx_lo + bw) x [by_lo, ...) and covers every
+// in-grid block the lookup can touch; K = 1 << ks.
 __device__ __forceinline__ void quad_depth_tab(const FrameDesc& f, int x0, int yy, int ks, const uint2* tab,
                                                int bx_lo, int by_lo, int bw, const uint32_t (&col)[4],
                                                uint32_t (&D)[4]) {
@@ -266,9 +273,16 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
     const int bw = bx_hi - bx_lo + 1;
     if (!f.depth_in && H > 0) {
         const int nbt = bw * (by_hi - by_lo + 1);
+        // after the strip-parallel grouping (unless its merge grouped the
+        // whole frame itself) a block's region depth is resolved here from
+        // its strip-local label and the merge's slot table
+        const bool strips = f.rstrip > 0 && f.rctl[1] == 0;
         for (int i = t; i < nbt; i += 256) {
             const int r = i / bw;
-            btab[i] = f.binfo[(by_lo + r) * f.gw + bx_lo + (i - r * bw)];
+            const int by = by_lo + r, b = by * f.gw + bx_lo + (i - r * bw);
+            uint2 e = f.binfo[b];
+            if (strips) e.y = block_depth_from_slots(f, b, by, e.x);
+            btab[i] = e;
         }
     }
     __syncthreads();

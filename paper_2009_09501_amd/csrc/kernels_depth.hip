@@ -64,7 +64,12 @@ LaunchSpec spec_regions(const FrameDesc& f) {
     return {reinterpret_cast<const void*>(&k_regions), dim3(1), dim3(kRegionThreads), regions_lds_bytes(f.gw * f.gh)};
 }
 
-int strip_rows(int gw) { return gw >= 1 && gw <= kStripBlocks ? kStripBlocks / gw : 0; }
+// Rows per strip: about one block per lane (two for rows wider than the
+// workgroup), 0 when a row does not fit a strip.
+int strip_rows(int gw) {
+    if (gw < 1 || gw > kStripBlocks) return 0;
+    return gw <= kStripLanes ? kStripLanes / gw : 1;
+}
 
 LaunchSpec spec_rg_strip(const FrameDesc& f) {
     return {reinterpret_cast<const void*>(&k_rg_strip), dim3((f.gh + f.rstrip - 1) / f.rstrip), dim3(kStripLanes), 0};

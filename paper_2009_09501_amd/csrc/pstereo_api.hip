@@ -36,6 +36,7 @@ struct pstereo_ctx {
     uint2* d_rent = nullptr;
     uint32_t* d_rrow = nullptr;
     uint32_t* d_rfin = nullptr;
+    uint2* d_rbnd = nullptr;
     uint32_t* d_rctl = nullptr;
     // block-iterative inpainting scratch, allocated on first use
     uint32_t* d_ipc = nullptr;
@@ -47,6 +48,8 @@ struct pstereo_ctx {
     bool have_blocks = false;
     int last_gw = 0, last_gh = 0;
     hipStream_t last_stream = nullptr;
+    FrameDesc last_fd{};         // descriptor of the last generated-depth frame
+    bool blocks_final = false;   // its per-block labels and depths are final
     // profiling ring
     std::vector<hipEvent_t> prof_ev;
     std::vector<uint8_t> prof_has_depth;
@@ -158,6 +161,7 @@ int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
         hipMalloc(&c->d_rent, pstereo::kRegionSlots * sizeof(uint2)) != hipSuccess ||
         hipMalloc(&c->d_rrow, pstereo::kRegionSlots * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_rfin, pstereo::kRegionSlots * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_rbnd, pstereo::kBoundSlots * sizeof(uint2)) != hipSuccess ||
         hipMalloc(&c->d_rctl, 4 * sizeof(uint32_t)) != hipSuccess ||
         hipMemset(c->d_rctl, 0, 4 * sizeof(uint32_t)) != hipSuccess) {
         (void)hipGetLastError();
@@ -181,6 +185,7 @@ int pstereo_destroy(pstereo_ctx* c) {
     (void)hipFree(c->d_rent);
     (void)hipFree(c->d_rrow);
     (void)hipFree(c->d_rfin);
+    (void)hipFree(c->d_rbnd);
     (void)hipFree(c->d_rctl);
     (void)hipFree(c->d_ipc);
     (void)hipFree(c->d_ipt);
@@ -279,6 +284,7 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
     f.rent = c->d_rent;
     f.rrow = c->d_rrow;
     f.rfin = c->d_rfin;
+    f.rbnd = c->d_rbnd;
     f.rctl = c->d_rctl;
     f.rstrip = pstereo::strip_rows(gw);
     f.w = w;
@@ -314,12 +320,13 @@ void frame_specs(const FrameDesc& f, const WarpShape& ws, pstereo::LaunchSpec (&
         st[n] = 0;
         ls[n++] = pstereo::spec_blockstats(f);
         if (f.rstrip > 0) {
+            // the per-block final labels and depths (k_rg_final) are only
+            // materialised on request (pstereo_debug_blocks): the depth filter
+            // resolves the depths it needs from the slot table
             st[n] = 1;
             ls[n++] = pstereo::spec_rg_strip(f);
             st[n] = 1;
             ls[n++] = pstereo::spec_rg_merge(f);
-            st[n] = 1;
-            ls[n++] = pstereo::spec_rg_final(f);
         } else {
             st[n] = 1;
             ls[n++] = pstereo::spec_regions(f);
@@ -431,6 +438,8 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
     }
     if (!ext) {
         c->have_blocks = true;
+        c->last_fd = f;
+        c->blocks_final = f.rstrip == 0;
         c->last_gw = f.gw;
         c->last_gh = f.gh;
         c->last_stream = s;
@@ -452,7 +461,14 @@ int pstereo_debug_blocks(pstereo_ctx* c, uint32_t* stats, int32_t* labels, uint8
     if (gh) *gh = c->last_gh;
     if (cap < nb) return fail(c, PSTEREO_E_INVALID, "capacity %d < %d blocks", cap, nb);
     (void)hipSetDevice(c->device);
-    hipError_t e = hipStreamSynchronize(c->last_stream);
+    hipError_t e;
+    if (!c->blocks_final) {
+        // turn the strip-local labels into final labels and depths
+        if ((e = pstereo::launch(pstereo::spec_rg_final(c->last_fd), c->last_fd, c->last_stream)) != hipSuccess)
+            return fail(c, PSTEREO_E_DEVICE, "block resolution launch: %s", hipGetErrorString(e));
+        c->blocks_final = true;
+    }
+    e = hipStreamSynchronize(c->last_stream);
     if (e != hipSuccess) return fail(c, PSTEREO_E_DEVICE, "stream synchronize: %s", hipGetErrorString(e));
     std::vector<uint2> bi(nb);
     if ((e = hipMemcpy(bi.data(), c->d_binfo, nb * sizeof(uint2), hipMemcpyDeviceToHost)) != hipSuccess)
@@ -638,6 +654,8 @@ int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, 
     v->pending[k] = true;
     v->count++;
     c->have_blocks = true;
+    c->last_fd = f;
+    c->blocks_final = f.rstrip == 0;
     c->last_gw = f.gw;
     c->last_gh = f.gh;
     c->last_stream = v->stream;

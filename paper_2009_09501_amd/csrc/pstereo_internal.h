@@ -28,7 +28,9 @@ struct FrameDesc {
     uint2* rent;             // per slot: {strip-local label, non-edge count}
     uint32_t* rrow;          // per slot: lowest block row + 1
     uint32_t* rfin;          // per slot: final label << 9 | background << 8 | depth
-    uint32_t* rctl;          // [0]: slots taken, [1]: 1 if the merge fell back to one workgroup
+    uint2* rbnd;             // boundary join candidates: {block above the strip, strip-local label below}
+    uint32_t* rctl;          // [0]: slots taken, [1]: 1 if the merge fell back to one workgroup,
+                             // [2]: boundary candidates
     int rstrip;              // block rows per strip, 0 = single-workgroup grouping
     int w, h;
     int K, gw, gh;           // depth block size and grid
@@ -68,6 +70,7 @@ LaunchSpec spec_regions(const FrameDesc& f);
 // Strip-parallel grouping: strips, merge, per-block resolution.
 int strip_rows(int gw);
 constexpr int kRegionSlots = 4096;
+constexpr int kBoundSlots = 8192;
 LaunchSpec spec_rg_strip(const FrameDesc& f);
 LaunchSpec spec_rg_merge(const FrameDesc& f);
 LaunchSpec spec_rg_final(const FrameDesc& f);
