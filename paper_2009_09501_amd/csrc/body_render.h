@@ -173,27 +173,40 @@ constexpr int kTileH = 32;                   // rows
 constexpr int kTileQuads = kTileQ + 2;       // quads per LDS row: one extra each side
 constexpr int kRowWords = 2 * kTileQuads;    // 36 dwords per LDS row and plane
 
-// Filtered depth of the four pixels x0..x0+3 of one row.  yw / dw: six dwords
-// per window row = columns x0-4 .. x0+7 as u16 pairs.  Tap (dx, dy) of pixel
-// j reads column c = 4 + j + dx; taps are paired (dx, dx+1) so the weighted
+// Window of a pixel pair at an even LDS column c0: the words from the one
+// holding column c0 - R through the one holding c0 + 1 + R, plus one so that
+// an unpaired last tap may read its (zero-weight) neighbour.
+template <int R>
+struct CbfPairWin {
+    static constexpr int kW0 = (R + 1) >> 1;  // words before c0's word
+    static constexpr int kWords = kW0 + 1 + ((R + 2) >> 1);
+};
+
+// Filtered depth of the two pixels x0, x0 + 1 of one row.  yw / dw: the
+// window words of each of the 2R + 1 rows, luma doubled and raw depth as u16
+// pairs; pixel j sits at window column 2 kW0 + j, so every tap's word and half
+// are compile-time constants.  Taps are paired (dx, dx + 1) so the weighted
 // depth sum and the weight sum each take one dot2 per pair.  CLIP: some
 // window column lies outside the image and gets weight 0.
 template <int R, bool CLIP>
-__device__ __forceinline__ void cbf_quad(const uint32_t (&yw)[2 * R + 1][6], const uint32_t (&dw)[2 * R + 1][6],
-                                         uint32_t rows_ok, int x0, int W, const uint16_t* wtab, uint32_t (&df)[4]) {
+__device__ __forceinline__ void cbf_pair(const uint32_t (&yw)[2 * R + 1][CbfPairWin<R>::kWords],
+                                         const uint32_t (&dw)[2 * R + 1][CbfPairWin<R>::kWords], uint32_t rows_ok,
+                                         int x0, int W, const uint16_t* wtab, uint32_t (&df)[2]) {
+    constexpr int PW = CbfPairWin<R>::kWords;
     const uint8_t* wt = reinterpret_cast<const uint8_t*>(wtab);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t yp = (yw[R][(4 + j) >> 1] >> (16 * ((4 + j) & 1))) & 0xFFFFu;
+    for (int j = 0; j < 2; ++j) {
+        const int pc = 2 * CbfPairWin<R>::kW0 + j;
+        const uint32_t yp = (yw[R][pc >> 1] >> (16 * (pc & 1))) & 0xFFFFu;
         uint32_t acc = 0, wsum = 0;
 #pragma unroll
         for (int dy = -R; dy <= R; ++dy) {
             if (!((rows_ok >> (dy + R)) & 1u)) continue;
-            const uint32_t(&yr)[6] = yw[dy + R];
-            const uint32_t(&dr)[6] = dw[dy + R];
+            const uint32_t(&yr)[PW] = yw[dy + R];
+            const uint32_t(&dr)[PW] = dw[dy + R];
 #pragma unroll
             for (int dx = -R; dx <= R; dx += 2) {
-                const int c = 4 + j + dx;
+                const int c = pc + dx;
                 const bool pair = dx + 1 <= R;
                 const uint32_t y0 = (yr[c >> 1] >> (16 * (c & 1))) & 0xFFFFu;
                 // weight table: u16 entries indexed by |dY|, i.e. byte offset 2|dY|
@@ -348,18 +361,6 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
     }
     __syncthreads();
 
-    auto window = [&](int qx_, int ty_, uint32_t (&yw)[S][6], uint32_t (&dw)[S][6], uint32_t& rows_ok) {
-        const int y_ = ty0 + ty_;
-        rows_ok = 0;
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-            const int yy = y_ + i - R;
-            if (yy >= 0 && yy < H) rows_ok |= 1u << i;
-            const int base = (ty_ + i) * kRowWords + 2 * qx_;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) { yw[i][k] = tY[base + k]; dw[i][k] = tD[base + k]; }
-        }
-    };
     auto store_df = [&](int x0_, int y_, const uint32_t (&df)[4]) {
         const int n = min(4, W - x0_);
         const size_t o = (size_t)y_ * W + x0_;
@@ -416,16 +417,40 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
         }
     }
     __syncthreads();
-    const int nw = nwork;
-    for (int i = t; i < nw; i += 256) {
-        const int q = work[i];
+    // the full filter: two lanes per listed quad, two pixels each (half the
+    // serial length of one lane per quad); the even lane of a pair takes its
+    // partner's two results by a lane shuffle and stores all four
+    constexpr int PW = CbfPairWin<R>::kWords;
+    const int nw2 = 2 * nwork;
+    for (int i0 = 0; i0 < nw2; i0 += 256) {
+        const int i = i0 + t;
+        const bool on = i < nw2;
+        const int q = on ? work[i >> 1] : 0;
+        const int hf = i & 1;
         const int qx_ = q & (kTileQ - 1), ty_ = (q & 255) / kTileQ + 16 * (q >> 8);
         const int x0_ = tx0 + 4 * qx_, y_ = ty0 + ty_;
-        uint32_t yw[S][6], dw[S][6], rows_ok, df[4];
-        window(qx_, ty_, yw, dw, rows_ok);
-        if (x0_ - R >= 0 && x0_ + 3 + R < W) cbf_quad<R, false>(yw, dw, rows_ok, x0_, W, wtab, df);
-        else cbf_quad<R, true>(yw, dw, rows_ok, x0_, W, wtab, df);
-        store_df(x0_, y_, df);
+        uint32_t df2[2] = {0u, 0u};
+        if (on) {
+            // the pair's first pixel is LDS column 4 qx + 4 + 2 hf
+            const int wb = 2 * qx_ + 2 + hf - CbfPairWin<R>::kW0;
+            uint32_t yw[S][PW], dw[S][PW], rows_ok = 0;
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+                const int yy = y_ + r - R;
+                if (yy >= 0 && yy < H) rows_ok |= 1u << r;
+                const int base = (ty_ + r) * kRowWords + wb;
+#pragma unroll
+                for (int k = 0; k < PW; ++k) { yw[r][k] = tY[base + k]; dw[r][k] = tD[base + k]; }
+            }
+            const int xp = x0_ + 2 * hf;
+            if (xp - R >= 0 && xp + 1 + R < W) cbf_pair<R, false>(yw, dw, rows_ok, xp, W, wtab, df2);
+            else cbf_pair<R, true>(yw, dw, rows_ok, xp, W, wtab, df2);
+        }
+        const uint32_t other = (uint32_t)__shfl_xor((int)(df2[0] | (df2[1] << 8)), 1);
+        if (on && !hf) {
+            const uint32_t df[4] = {df2[0], df2[1], other & 255u, other >> 8};
+            store_df(x0_, y_, df);
+        }
     }
 }
 
