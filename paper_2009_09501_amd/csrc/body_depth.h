@@ -627,14 +627,9 @@ __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uin
     uint32_t* row = cnt + kStripBlocks;      // per root: lowest local row + 1
     uint32_t* misc = row + kStripBlocks;     // [0]: slots of this strip, [1]: its first slot,
                                              // [2]: its join candidates, [3]: their first entry
-    uint32_t* binfo_w = reinterpret_cast<uint32_t*>(f.binfo);
     const uint32_t gwm = gw > 1 ? (uint32_t)((0x100000000ull + (uint32_t)gw - 1) / (uint32_t)gw) : 0u;
 
-    for (int j = t; j < nload; j += kStripLanes) {
-        const uint32_t s = f.stats[base + j];
-        st[j] = s;
-        if (j < n) binfo_w[2 * (base + j)] = s;
-    }
+    for (int j = t; j < nload; j += kStripLanes) st[j] = f.stats[base + j];
     if (r0 > 0)
         for (int j = t; j < gw; j += kStripLanes) sa[j] = f.stats[base - gw + j];
     for (int j = t; j < n; j += kStripLanes) {
@@ -704,20 +699,26 @@ __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uin
     if (t == 0) misc[1] = atomicAdd(&f.rctl[0], misc[0]);
     __syncthreads();
     const uint32_t first = misc[1];
+    // each root's slot replaces its union-find entry (the finds are done)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int j = t + k * kStripLanes;
+        if (!slot[k]) continue;
+        const uint32_t sidx = first + slot[k] - 1u;
+        par[j] = sidx;
+        if (sidx < (uint32_t)kRegionSlots) {
+            f.rent[sidx] = make_uint2((uint32_t)(base + j), cnt[j]);
+            f.rrow[sidx] = (uint32_t)r0 + row[j];
+        }
+    }
+    __syncthreads();
+    // per block: statistics and the slot of its component (0 for edge blocks)
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int j = t + k * kStripLanes;
         if (j >= n) continue;
-        const uint32_t lab = (uint32_t)base + root[k];
-        f.labels[base + j] = (int32_t)lab;
-        if (slot[k]) {
-            const uint32_t sidx = first + slot[k] - 1u;
-            if (sidx < (uint32_t)kRegionSlots) {
-                f.rent[sidx] = make_uint2(lab, cnt[j]);
-                f.rrow[sidx] = (uint32_t)r0 + row[j];
-                f.rcid[lab] = (int32_t)sidx;
-            }
-        }
+        const uint32_t s = st[j];
+        f.binfo[base + j] = make_uint2(s, (s >> 24) ? 0u : par[root[k]]);
     }
 
     // join candidates across the boundary above the strip: the down links
@@ -745,7 +746,7 @@ __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uin
             const int x = t + k * kStripLanes;
             if (!cand[k]) continue;
             const uint32_t idx = bfirst + cand[k] - 1u;
-            if (idx < (uint32_t)kBoundSlots) f.rbnd[idx] = make_uint2((uint32_t)(base - gw + x), (uint32_t)base + root[k]);
+            if (idx < (uint32_t)kBoundSlots) f.rbnd[idx] = make_uint2((uint32_t)(base - gw + x), par[root[k]]);
         }
     }
 }
@@ -794,14 +795,15 @@ __device__ __forceinline__ void rg_merge_body(const FrameDesc& f, uint32_t* lds)
         // the strips' compacted join candidates
         for (uint32_t q = t; q < ncand; q += kStripLanes) {
             const uint2 e = f.rbnd[q];
-            ufl_unite(par, (uint32_t)f.rcid[f.labels[e.x]], (uint32_t)f.rcid[e.y], lab);
+            ufl_unite(par, f.binfo[e.x].y, e.y, lab);
         }
     } else
     // every boundary position, four per lane at a time, every global load of
     // the four issued before any is used
     for (int q0 = t; q0 < total; q0 += 4 * kStripLanes) {
-        uint32_t sb[4], sc[4], sb1[4], sc1[4];
-        int la[4], lc[4], la1[4], lc1[4], xs[4];
+        // {statistics, slot} of the two blocks and of their left neighbours
+        uint2 eb[4], ec[4], eb1[4], ec1[4];
+        int xs[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int q = q0 + u * kStripLanes;
@@ -811,28 +813,18 @@ __device__ __forceinline__ void rg_merge_body(const FrameDesc& f, uint32_t* lds)
             const int b = ((kb + 1) * SR - 1) * gw + x, c = b + gw;
             const int bl = x > 0 ? b - 1 : b, cl = x > 0 ? c - 1 : c;
             xs[u] = q < total ? x : -1;
-            sb[u] = f.stats[b];
-            sc[u] = f.stats[c];
-            la[u] = f.labels[b];
-            lc[u] = f.labels[c];
-            sb1[u] = f.stats[bl];
-            sc1[u] = f.stats[cl];
-            la1[u] = f.labels[bl];
-            lc1[u] = f.labels[cl];
+            eb[u] = f.binfo[b];
+            ec[u] = f.binfo[c];
+            eb1[u] = f.binfo[bl];
+            ec1[u] = f.binfo[cl];
         }
-        uint32_t ua[4], uc[4];
-        bool join[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            join[u] = xs[u] >= 0 && linked(sb[u], sc[u], f.tau);
-            if (join[u] && xs[u] > 0 && linked(sb1[u], sc1[u], f.tau) && la1[u] == la[u] && lc1[u] == lc[u])
-                join[u] = false;
-            ua[u] = join[u] ? (uint32_t)f.rcid[la[u]] : 0u;
-            uc[u] = join[u] ? (uint32_t)f.rcid[lc[u]] : 0u;
+            bool join = xs[u] >= 0 && linked(eb[u].x, ec[u].x, f.tau);
+            if (join && xs[u] > 0 && linked(eb1[u].x, ec1[u].x, f.tau) && eb1[u].y == eb[u].y && ec1[u].y == ec[u].y)
+                join = false;
+            if (join) ufl_unite(par, eb[u].y, ec[u].y, lab);
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (join[u]) ufl_unite(par, ua[u], uc[u], lab);
     }
     __syncthreads();
 
@@ -880,8 +872,7 @@ __device__ __forceinline__ void rg_final_block(const FrameDesc& f, int b) {
     if (s >> 24) {
         d = ramp(by, gh);
     } else {
-        const int L = f.labels[b];
-        const uint32_t v = f.rfin[f.rcid[L]];
+        const uint32_t v = f.rfin[binfo_w[2 * b + 1]];
         label = v >> 9;
         d = ((v >> 8) & 1u) ? ramp(by, gh) : (int)(v & 255u);
     }

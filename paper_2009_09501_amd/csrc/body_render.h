@@ -37,6 +37,22 @@ __host__ __device__ constexpr int k_index(int k) {
 }
 __host__ __device__ constexpr int k_count(int r) { return r == 0 ? 1 : r == 1 ? 3 : r == 2 ? 6 : 10; }
 
+// Product weights ws(k) * wr(d) of the cross-bilateral filter for every
+// distinct squared distance k (k_index order) and luma difference d = 0..255,
+// as u16 pairs (d even low, d + 1 high); the table for radius r is the prefix
+// of k_count(r) rows.  Built at compile time, copied into LDS per tile.
+struct CbfWeightTable {
+    uint32_t w[10 * 128];
+};
+__host__ __device__ constexpr CbfWeightTable make_cbf_weights() {
+    CbfWeightTable t{};
+    for (int k = 0; k < 10; ++k)
+        for (int d = 0; d < 256; d += 2)
+            t.w[k * 128 + d / 2] = spatial_w(k_value(k)) * range_w(d) | (spatial_w(k_value(k)) * range_w(d + 1)) << 16;
+    return t;
+}
+__device__ const CbfWeightTable kCbfWeights = make_cbf_weights();
+
 __device__ __forceinline__ uint32_t byte_of(uint32_t w, int i) { return (w >> (8 * i)) & 255u; }
 
 // Depth -> (left offset, right offset) of the Fig. 3 rule with the rounding
@@ -85,13 +101,12 @@ __device__ __forceinline__ void quad_luma2(uint3 v, uint32_t& y01, uint32_t& y23
     y23 = perm(r3, r2, 0x0c050c01u) << 1;
 }
 
-// Region depth of block b (row by, statistics s) after the strip-parallel
-// grouping: edge blocks and the background follow the row ramp, other blocks
-// take their merged component's depth from the slot of their strip-local
-// label.
-__device__ __forceinline__ uint32_t block_depth_from_slots(const FrameDesc& f, int b, int by, uint32_t s) {
-    if (s >> 24) return (uint32_t)ramp(by, f.gh);
-    const uint32_t v = f.rfin[f.rcid[f.labels[b]]];
+// Region depth of a block in row by after the strip-parallel grouping, from
+// its {statistics, component slot}: edge blocks and the background follow
+// the row ramp, other blocks take their merged component's depth.
+__device__ __forceinline__ uint32_t block_depth_from_slots(const FrameDesc& f, int by, uint2 e) {
+    if (e.x >> 24) return (uint32_t)ramp(by, f.gh);
+    const uint32_t v = f.rfin[e.y];
     return ((v >> 8) & 1u) ? (uint32_t)ramp(by, f.gh) : (v & 255u);
 }
 
@@ -278,6 +293,13 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
         }
     }
 
+    // the weight table (NK * 32 16-byte pieces) likewise
+    constexpr int NW4 = NK * 32, NWL = (NW4 + 255) / 256;
+    uint4 wq[NWL];
+#pragma unroll
+    for (int k = 0; k < NWL; ++k)
+        if (t + 256 * k < NW4) wq[k] = reinterpret_cast<const uint4*>(kCbfWeights.w)[t + 256 * k];
+
     // the tile's block table (halo and one ring of neighbours, clipped to the
     // grid) into LDS, so the raw depth needs no global lookups
     const int ks = __builtin_ctz((unsigned)f.K);
@@ -294,15 +316,15 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
             const int r = i / bw;
             const int by = by_lo + r, b = by * f.gw + bx_lo + (i - r * bw);
             uint2 e = f.binfo[b];
-            if (strips) e.y = block_depth_from_slots(f, b, by, e.x);
+            if (strips) e.y = block_depth_from_slots(f, by, e);
             btab[i] = e;
         }
     }
-    __syncthreads();
-
-    // product weights ws[k] * wr[d] per distinct squared distance k
-    for (int i = t; i < NK * 256; i += 256) wtab[i] = (uint16_t)(spatial_w(k_value(i >> 8)) * range_w(i & 255));
+#pragma unroll
+    for (int k = 0; k < NWL; ++k)
+        if (t + 256 * k < NW4) reinterpret_cast<uint4*>(wtab)[t + 256 * k] = wq[k];
     if (t == 0) nwork = 0;
+    __syncthreads();
 
     // doubled luma + raw depth of the tile and its halo (columns tx0-4 ..
     // tx0+67)

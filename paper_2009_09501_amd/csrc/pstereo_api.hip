@@ -32,7 +32,6 @@ struct pstereo_ctx {
     uint2* d_binfo = nullptr;
     int32_t* d_labels = nullptr;
     uint8_t* d_df = nullptr;  // filtered depth, max_w * max_h bytes
-    int32_t* d_rcid = nullptr;  // strip-parallel region grouping scratch
     uint2* d_rent = nullptr;
     uint32_t* d_rrow = nullptr;
     uint32_t* d_rfin = nullptr;
@@ -157,7 +156,6 @@ int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
         hipMalloc(&c->d_binfo, nb * sizeof(uint2)) != hipSuccess ||
         hipMalloc(&c->d_labels, nb * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&c->d_df, (size_t)max_w * max_h) != hipSuccess ||
-        hipMalloc(&c->d_rcid, nb * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&c->d_rent, pstereo::kRegionSlots * sizeof(uint2)) != hipSuccess ||
         hipMalloc(&c->d_rrow, pstereo::kRegionSlots * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_rfin, pstereo::kRegionSlots * sizeof(uint32_t)) != hipSuccess ||
@@ -181,7 +179,6 @@ int pstereo_destroy(pstereo_ctx* c) {
     (void)hipFree(c->d_binfo);
     (void)hipFree(c->d_labels);
     (void)hipFree(c->d_df);
-    (void)hipFree(c->d_rcid);
     (void)hipFree(c->d_rent);
     (void)hipFree(c->d_rrow);
     (void)hipFree(c->d_rfin);
@@ -280,7 +277,6 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
     f.binfo = c->d_binfo;
     f.labels = c->d_labels;
     f.df = c->d_df;
-    f.rcid = c->d_rcid;
     f.rent = c->d_rent;
     f.rrow = c->d_rrow;
     f.rfin = c->d_rfin;

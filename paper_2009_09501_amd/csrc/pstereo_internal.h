@@ -23,12 +23,12 @@ struct FrameDesc {
     int32_t* labels;         // per block: region label
     uint8_t* df;             // filtered depth scratch, u8 [h][w] (4-byte aligned)
     // strip-parallel region grouping (rstrip > 0): strip-local components are
-    // merged across strip boundaries through a table of slots
-    int32_t* rcid;           // per block: slot of the strip-local component it labels
+    // merged across strip boundaries through a table of slots; binfo then
+    // holds {statistics, slot of the block's component} until resolved
     uint2* rent;             // per slot: {strip-local label, non-edge count}
     uint32_t* rrow;          // per slot: lowest block row + 1
     uint32_t* rfin;          // per slot: final label << 9 | background << 8 | depth
-    uint2* rbnd;             // boundary join candidates: {block above the strip, strip-local label below}
+    uint2* rbnd;             // boundary join candidates: {block above the strip, slot below}
     uint32_t* rctl;          // [0]: slots taken, [1]: 1 if the merge fell back to one workgroup,
                              // [2]: boundary candidates
     int rstrip;              // block rows per strip, 0 = single-workgroup grouping
