@@ -570,9 +570,12 @@ __device__ __forceinline__ void store_quad_views(const FrameDesc& f, int y, int 
     }
 }
 
+// LDS of the warp of one row: both z-buffers (kidx-padded), the shift
+// table, the row's filtered depth and per chunk (Q x 64 lanes' quads) the
+// keys at its valid extremes.
 __host__ __device__ constexpr size_t warp_lds_bytes(int w, int threads, int q) {
     return (size_t)(2 * (((w + 3) & ~3) + ((w + 3) & ~3) / 32 + 1) * 4 + 256 * 4 + ((w + 3) & ~3) +
-                    4 * q * (threads / 64) * 4);
+                    8 * q * (threads / 64) * 4);
 }
 
 // A lane's share of one image row: the frame bytes of its Q quads (three
@@ -615,10 +618,76 @@ __device__ __forceinline__ void warp_load(const FrameDesc& f, int y, int t, int 
     }
 }
 
+// The warp's standing LDS state for rows of width W: the shift table, and
+// both z-buffers zero (each row's validity pass zeroes what its scatter
+// wrote, so the state holds from row to row).  A barrier must follow before
+// the first row.
+__device__ __forceinline__ void warp_prepare(const FrameDesc& f, int W, int t, int NT, uint32_t* lds) {
+    const int KW = kidx((W + 3) & ~3) + 1;
+    uint32_t* lut = lds + 2 * KW;
+    for (int d = t; d < 256; d += NT) lut[d] = shift_entry(d, f.B, f.T);
+    for (int i = t; i < 2 * KW; i += NT) lds[i] = 0;
+}
+
+// Key of the last (LAST) or first valid pixel of a quad: mask m (bit j =
+// pixel j valid) over keys k[0..3]; 0 when none.
+template <bool LAST>
+__device__ __forceinline__ uint32_t quad_extreme_key(uint32_t m, const uint32_t* k) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+        const int j = LAST ? jj : 3 - jj;
+        if ((m >> j) & 1u) r = k[j];
+    }
+    return r;
+}
+
+// Hole fill of one view's quad: pixel j with valid bit clear takes the
+// nearer valid pixel on either side of the row, the smaller depth winning
+// and ties going left (LEFT_TIES, the left view) or right; with a valid
+// pixel on one side only that one; with none, the source pixel (need bit j).
+// k: the quad's keys; ex / ef: key of the nearest valid pixel before / after
+// the quad, hx / hf: whether it exists.  Returns the four colours.
+template <bool LEFT_TIES>
+__device__ __forceinline__ void fill_quad(uint32_t m, uint32_t own, const uint32_t* k, uint32_t ex, bool hx,
+                                          uint32_t ef, bool hf, uint32_t* c, uint32_t& need) {
+    uint32_t lk[4], rk[4], lh = 0, rh = 0;
+    uint32_t run = ex;
+    bool has = hx;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        lk[j] = run;
+        if (has) lh |= 1u << j;
+        if ((m >> j) & 1u) { run = k[j]; has = true; }
+    }
+    run = ef;
+    has = hf;
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {
+        rk[j] = run;
+        if (has) rh |= 1u << j;
+        if ((m >> j) & 1u) { run = k[j]; has = true; }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint32_t v = k[j];
+        if (!((m >> j) & 1u)) {
+            const bool a = (lh >> j) & 1u, b = (rh >> j) & 1u;
+            const uint32_t ka = lk[j], kb = rk[j];
+            if (a && b) v = LEFT_TIES ? ((kb >> 24) < (ka >> 24) ? kb : ka) : ((ka >> 24) < (kb >> 24) ? ka : kb);
+            else if (a) v = ka;
+            else if (b) v = kb;
+            else if ((own >> j) & 1u) need |= 1u << j;
+        }
+        c[j] = v & 0xFFFFFFu;
+    }
+}
+
 // Image row y on NT lanes t = 0..NT-1 (whole waves) from the lane's loaded
 // share `in`; when next_y >= 0 the share of row next_y is loaded into `next`
-// while this row's holes are filled.  lds: warp_lds_bytes(w, NT, Q) bytes.
-// Inactive lane groups do no memory work but pass the same three barriers.
+// while this row is resolved.  lds: warp_lds_bytes(w, NT, Q) bytes in the
+// state warp_prepare leaves, which the row restores.  Two barriers; inactive
+// lane groups do no memory work but pass them too.
 template <bool ALIGNED, int Q>
 __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, int NT, uint32_t* lds, bool active,
                                               const WarpRowIn<ALIGNED, Q>& in, int next_y,
@@ -630,37 +699,26 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
     const int KW = kidx(W4) + 1;
     uint32_t* keyL = lds;
     uint32_t* keyR = keyL + KW;
-    uint32_t* lut = keyR + KW;                                        // 256 entries
-    uint8_t* drow_l = reinterpret_cast<uint8_t*>(lut + 256);          // the row's filtered depth, W4 bytes
-    int* pub = reinterpret_cast<int*>(drow_l + W4);                   // per chunk: last L, first L, last R, first R
-
-    for (int d = t; d < 256; d += NT) lut[d] = shift_entry(d, f.B, f.T);
-    for (int i = t; i < KW; i += NT) { keyL[i] = 0; keyR[i] = 0; }
-    __syncthreads();
+    const uint32_t* lut = keyR + KW;                                  // 256 entries
+    uint8_t* drow_l = reinterpret_cast<uint8_t*>(keyR + KW + 256);    // the row's filtered depth, W4 bytes
+    uint32_t* pub = reinterpret_cast<uint32_t*>(drow_l + W4);         // per chunk: 8 words
 
     // ---- forward warp of the row's pixels into both views; the key carries
     // the depth above the colour, so the atomic max keeps the nearer source
     // and its colour
-    uint32_t col[4 * Q];  // own source colours, R | G << 8 | B << 16
-#pragma unroll
-    for (int qi = 0; qi < Q; ++qi) {
-        if (ALIGNED) {
-            uint32_t c4[4];
-            quad_colours(make_uint3(in.c[3 * qi], in.c[3 * qi + 1], in.c[3 * qi + 2]), c4);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) col[4 * qi + j] = c4[j];
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) col[4 * qi + j] = in.c[4 * qi + j];
-        }
-    }
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
         const int x0 = 4 * (qi * NT + t);
         if (x0 >= W) continue;
         const int n = min(4, W - x0);
+        uint32_t c[4];
+        if (ALIGNED) {
+            quad_colours(make_uint3(in.c[3 * qi], in.c[3 * qi + 1], in.c[3 * qi + 2]), c);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[j] = in.c[4 * qi + j];
+        }
         const uint32_t dq = in.dq[qi];
-        const uint32_t* c = &col[4 * qi];
         *reinterpret_cast<uint32_t*>(drow_l + x0) = dq;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -677,12 +735,13 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
     }
     __syncthreads();
 
-    // the next row's share is loaded while this row is resolved and filled
+    // the next row's share is loaded while this row is resolved
     if (next_y >= 0) warp_load<ALIGNED, Q>(f, next_y, t, NT, next);
 
-    // ---- validity: a landed source has a non-zero key, except a black source
-    // of depth 0, whose key is 0; such a source is the only one that can land
-    // on a zero key, so zero keys check it directly
+    // ---- validity, and the z-buffers back to zero: a landed source has a
+    // non-zero key, except a black source of depth 0, whose key is 0; such a
+    // source is the only one that can land on a zero key, so zero keys check
+    // the depth at their depth-0 source position directly
     uint32_t kl[4 * Q], kr[4 * Q];
     uint32_t vL = 0, vR = 0, own = 0;  // bit 4 qi + j
 #pragma unroll
@@ -691,30 +750,43 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int x = x0 + j;
-            kl[4 * qi + j] = x < W ? keyL[kidx(x)] : 0u;
-            kr[4 * qi + j] = x < W ? keyR[kidx(x)] : 0u;
+            const int i = 4 * qi + j;
+            kl[i] = 0;
+            kr[i] = 0;
             if (x < W) {
-                own |= 1u << (4 * qi + j);
-                if (kl[4 * qi + j]) vL |= 1u << (4 * qi + j);
-                if (kr[4 * qi + j]) vR |= 1u << (4 * qi + j);
+                kl[i] = keyL[kidx(x)];
+                kr[i] = keyR[kidx(x)];
+                keyL[kidx(x)] = 0;
+                keyR[kidx(x)] = 0;
+                own |= 1u << i;
             }
+            if (kl[i]) vL |= 1u << i;
+            if (kr[i]) vR |= 1u << i;
         }
     }
     if (__ballot((own & ~(vL & vR)) != 0)) {
         const uint32_t lv0 = lut[0];
-        const int o0L = (int)(int16_t)(lv0 & 0xFFFFu), o0R = (int)(int16_t)(lv0 >> 16);
-        uint32_t zl = own & ~vL, zr = own & ~vR;
-        while (zl) {
-            const int i = __ffs(zl) - 1;
-            zl &= zl - 1;
-            const int s0 = 4 * ((i >> 2) * NT + t) + (i & 3) - o0L;
-            if ((unsigned)s0 < (unsigned)W && drow_l[s0] == 0) vL |= 1u << i;
-        }
-        while (zr) {
-            const int i = __ffs(zr) - 1;
-            zr &= zr - 1;
-            const int s0 = 4 * ((i >> 2) * NT + t) + (i & 3) - o0R;
-            if ((unsigned)s0 < (unsigned)W && drow_l[s0] == 0) vR |= 1u << i;
+        const int o0[2] = {(int)(int16_t)(lv0 & 0xFFFFu), (int)(int16_t)(lv0 >> 16)};
+        const uint32_t* d32 = reinterpret_cast<const uint32_t*>(drow_l);
+        const int nd = W4 >> 2;
+#pragma unroll
+        for (int qi = 0; qi < Q; ++qi) {
+            const int x0 = 4 * (qi * NT + t);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                uint32_t& vm = v ? vR : vL;
+                const uint32_t z = (own & ~vm) >> (4 * qi) & 15u;
+                if (!z) continue;
+                // the four sources x0 + j - o0 are consecutive bytes
+                const int b = x0 - o0[v];
+                const int i0 = b >> 2;
+                const uint32_t w0 = d32[min(max(i0, 0), nd - 1)], w1 = d32[min(max(i0 + 1, 0), nd - 1)];
+                const uint32_t bytes = alignbyte(w1, w0, (uint32_t)(b & 3));
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (((z >> j) & 1u) && (unsigned)(b + j) < (unsigned)W && !((bytes >> (8 * j)) & 255u))
+                        vm |= 1u << (4 * qi + j);
+            }
         }
     }
     if (f.ipc) {
@@ -735,123 +807,86 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
                 f.ipt[plane + o] = ((vR >> i) & 1u) ? 0 : 0xFFFF;
             }
         }
+        __syncthreads();  // the z-buffers and the row depth are free again
         return;
     }
-    // per chunk: ballot of the quads holding a valid pixel; the chunk's
-    // extremes go to LDS for the other chunks
+    // per chunk: ballot of the quads holding a valid pixel; the keys at the
+    // chunk's extremes go to LDS for the other chunks
     unsigned long long anyL[Q], anyR[Q];
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
-        const int x0 = 4 * (qi * NT + t);
         const uint32_t ql = (vL >> (4 * qi)) & 15u, qr = (vR >> (4 * qi)) & 15u;
         anyL[qi] = __ballot(ql != 0);
         anyR[qi] = __ballot(qr != 0);
-        const int lastL = ql ? x0 + 31 - __clz(ql) : -1, firstL = ql ? x0 + __ffs(ql) - 1 : W;
-        const int lastR = qr ? x0 + 31 - __clz(qr) : -1, firstR = qr ? x0 + __ffs(qr) - 1 : W;
-        const int a = __builtin_amdgcn_readlane(lastL, anyL[qi] ? 63 - __clzll(anyL[qi]) : 0);
-        const int b = __builtin_amdgcn_readlane(firstL, anyL[qi] ? __ffsll(anyL[qi]) - 1 : 0);
-        const int c = __builtin_amdgcn_readlane(lastR, anyR[qi] ? 63 - __clzll(anyR[qi]) : 0);
-        const int d = __builtin_amdgcn_readlane(firstR, anyR[qi] ? __ffsll(anyR[qi]) - 1 : 0);
+        const uint32_t a = __builtin_amdgcn_readlane(quad_extreme_key<true>(ql, &kl[4 * qi]), anyL[qi] ? 63 - __clzll(anyL[qi]) : 0);
+        const uint32_t b = __builtin_amdgcn_readlane(quad_extreme_key<false>(ql, &kl[4 * qi]), anyL[qi] ? __ffsll(anyL[qi]) - 1 : 0);
+        const uint32_t c = __builtin_amdgcn_readlane(quad_extreme_key<true>(qr, &kr[4 * qi]), anyR[qi] ? 63 - __clzll(anyR[qi]) : 0);
+        const uint32_t d = __builtin_amdgcn_readlane(quad_extreme_key<false>(qr, &kr[4 * qi]), anyR[qi] ? __ffsll(anyR[qi]) - 1 : 0);
         if (lane == 0) {
-            const int ch = qi * NW + wave;
-            pub[4 * ch + 0] = anyL[qi] ? a : -1;
-            pub[4 * ch + 1] = anyL[qi] ? b : W;
-            pub[4 * ch + 2] = anyR[qi] ? c : -1;
-            pub[4 * ch + 3] = anyR[qi] ? d : W;
+            uint32_t* p = pub + 8 * (qi * NW + wave);
+            p[0] = a;
+            p[1] = b;
+            p[2] = c;
+            p[3] = d;
+            p[4] = (anyL[qi] ? 1u : 0u) | (anyR[qi] ? 2u : 0u);
         }
     }
     __syncthreads();
 
-    // ---- inpainting: a hole copies the nearer valid pixel of the warped row
-    // with the smaller depth (background); equal depths go left in the left
-    // view, right in the right view; a row without valid pixels keeps the
-    // source pixel
+    // ---- hole filling from the nearest valid keys: inside the quad, in the
+    // chunk through the ballots (shuffles run on all lanes of the wave), else
+    // in the other chunks; then the anaglyph and the stores
     const unsigned long long below = (1ull << lane) - 1ull;
     const unsigned long long above = ~((2ull << lane) - 1ull);
-    uint32_t cl[4 * Q], cr[4 * Q];
-#pragma unroll
-    for (int i = 0; i < 4 * Q; ++i) {
-        cl[i] = kl[i] & 0xFFFFFFu;
-        cr[i] = kr[i] & 0xFFFFFFu;
-    }
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
+        const int x0 = 4 * (qi * NT + t);
         const uint32_t ql = (vL >> (4 * qi)) & 15u, qr = (vR >> (4 * qi)) & 15u;
         const uint32_t oq = (own >> (4 * qi)) & 15u;
-        const bool holes = (oq & ~(ql & qr)) != 0;
-        if (!__ballot(holes)) continue;  // wave-uniform
-        const int x0 = 4 * (qi * NT + t);
-        const int ch = qi * NW + wave;
-        // nearest valid x outside the quad: in the chunk through the ballots
-        // (shuffles run on all lanes of the wave), else in other chunks
-        const int lastL = ql ? x0 + 31 - __clz(ql) : -1, firstL = ql ? x0 + __ffs(ql) - 1 : W;
-        const int lastR = qr ? x0 + 31 - __clz(qr) : -1, firstR = qr ? x0 + __ffs(qr) - 1 : W;
-        const unsigned long long lb = anyL[qi] & below, rb = anyR[qi] & below;
-        const unsigned long long la = anyL[qi] & above, ra = anyR[qi] & above;
-        int exL = __shfl(lastL, lb ? 63 - __clzll(lb) : lane);
-        int exR = __shfl(lastR, rb ? 63 - __clzll(rb) : lane);
-        int efL = __shfl(firstL, la ? __ffsll(la) - 1 : lane);
-        int efR = __shfl(firstR, ra ? __ffsll(ra) - 1 : lane);
-        if (!holes) continue;
-        if (!lb) exL = -1;
-        if (!rb) exR = -1;
-        if (!la) efL = W;
-        if (!ra) efR = W;
-        for (int c = ch - 1; c >= 0 && (exL < 0 || exR < 0); --c) {
-            if (exL < 0) exL = pub[4 * c + 0];
-            if (exR < 0) exR = pub[4 * c + 2];
-        }
-        for (int c = ch + 1; c < NC && (efL >= W || efR >= W); ++c) {
-            if (efL >= W) efL = pub[4 * c + 1];
-            if (efR >= W) efR = pub[4 * c + 3];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (!((oq >> j) & 1u)) break;
-            const int i = 4 * qi + j;
-            const uint32_t lowmask = (1u << j) - 1u, highmask = ~((2u << j) - 1u) & 15u;
-            if (!((ql >> j) & 1u)) {
-                const uint32_t lo = ql & lowmask, hi = ql & highmask;
-                const int a = lo ? x0 + 31 - __clz(lo) : exL;
-                const int b = hi ? x0 + __ffs(hi) - 1 : efL;
-                uint32_t k;
-                if (a >= 0 && b < W) {
-                    const uint32_t ka = keyL[kidx(a)], kb = keyL[kidx(b)];
-                    k = (kb >> 24) < (ka >> 24) ? kb : ka;
-                } else if (a >= 0) {
-                    k = keyL[kidx(a)];
-                } else if (b < W) {
-                    k = keyL[kidx(b)];
-                } else {
-                    k = col[i];
+        uint32_t cl[4], cr[4];
+        if (__ballot((oq & ~(ql & qr)) != 0)) {
+            const unsigned long long lb = anyL[qi] & below, rb = anyR[qi] & below;
+            const unsigned long long la = anyL[qi] & above, ra = anyR[qi] & above;
+            uint32_t exL = (uint32_t)__shfl((int)quad_extreme_key<true>(ql, &kl[4 * qi]), lb ? 63 - __clzll(lb) : lane);
+            uint32_t exR = (uint32_t)__shfl((int)quad_extreme_key<true>(qr, &kr[4 * qi]), rb ? 63 - __clzll(rb) : lane);
+            uint32_t efL = (uint32_t)__shfl((int)quad_extreme_key<false>(ql, &kl[4 * qi]), la ? __ffsll(la) - 1 : lane);
+            uint32_t efR = (uint32_t)__shfl((int)quad_extreme_key<false>(qr, &kr[4 * qi]), ra ? __ffsll(ra) - 1 : lane);
+            bool hxL = lb != 0, hxR = rb != 0, hfL = la != 0, hfR = ra != 0;
+            if (oq & ~(ql & qr)) {
+                const int ch = qi * NW + wave;
+                for (int c = ch - 1; c >= 0 && !(hxL && hxR); --c) {
+                    const uint32_t fl = pub[8 * c + 4];
+                    if (!hxL && (fl & 1u)) { exL = pub[8 * c + 0]; hxL = true; }
+                    if (!hxR && (fl & 2u)) { exR = pub[8 * c + 2]; hxR = true; }
                 }
-                cl[i] = k & 0xFFFFFFu;
+                for (int c = ch + 1; c < NC && !(hfL && hfR); ++c) {
+                    const uint32_t fl = pub[8 * c + 4];
+                    if (!hfL && (fl & 1u)) { efL = pub[8 * c + 1]; hfL = true; }
+                    if (!hfR && (fl & 2u)) { efR = pub[8 * c + 3]; hfR = true; }
+                }
             }
-            if (!((qr >> j) & 1u)) {
-                const uint32_t lo = qr & lowmask, hi = qr & highmask;
-                const int a = lo ? x0 + 31 - __clz(lo) : exR;
-                const int b = hi ? x0 + __ffs(hi) - 1 : efR;
-                uint32_t k;
-                if (a >= 0 && b < W) {
-                    const uint32_t ka = keyR[kidx(a)], kb = keyR[kidx(b)];
-                    k = (ka >> 24) < (kb >> 24) ? ka : kb;
-                } else if (a >= 0) {
-                    k = keyR[kidx(a)];
-                } else if (b < W) {
-                    k = keyR[kidx(b)];
-                } else {
-                    k = col[i];
+            uint32_t needL = 0, needR = 0;
+            fill_quad<true>(ql, oq, &kl[4 * qi], exL, hxL, efL, hfL, cl, needL);
+            fill_quad<false>(qr, oq, &kr[4 * qi], exR, hxR, efR, hfR, cr, needR);
+            if (needL | needR) {
+                // a view row without any valid pixel keeps the source pixels
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (!(((needL | needR) >> j) & 1u)) continue;
+                    const uint8_t* p = f.frame + ((size_t)y * W + x0 + j) * 3;
+                    const uint32_t src = p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+                    if ((needL >> j) & 1u) cl[j] = src;
+                    if ((needR >> j) & 1u) cr[j] = src;
                 }
-                cr[i] = k & 0xFFFFFFu;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                cl[j] = kl[4 * qi + j] & 0xFFFFFFu;
+                cr[j] = kr[4 * qi + j] & 0xFFFFFFu;
             }
         }
-    }
-
-    // ---- anaglyph and stores
-#pragma unroll
-    for (int qi = 0; qi < Q; ++qi) {
-        const int x0 = 4 * (qi * NT + t);
-        if (x0 < W) store_quad_views<ALIGNED>(f, y, x0, &cl[4 * qi], &cr[4 * qi]);
+        if (x0 < W) store_quad_views<ALIGNED>(f, y, x0, cl, cr);
     }
 }
 
@@ -949,7 +984,8 @@ __device__ __forceinline__ int inpaint_pixel(const FrameDesc& f, int v, int x, i
     return 1;
 }
 
-// One image row (the single-row form used by the batch kernels).
+// One image row (the single-row form used by the batch kernels), from and
+// to any LDS contents.
 template <bool ALIGNED, int Q>
 __device__ __forceinline__ void warp_row(const FrameDesc& f, int y, int t, int NT, uint32_t* lds, bool active) {
     WarpRowIn<ALIGNED, Q> in, unused;
@@ -961,19 +997,25 @@ __device__ __forceinline__ void warp_row(const FrameDesc& f, int y, int t, int N
 #pragma unroll
         for (int i = 0; i < Q; ++i) in.dq[i] = 0;
     }
+    warp_prepare(f, active ? f.w : 0, t, NT, lds);
+    __syncthreads();
     warp_row_body<ALIGNED, Q>(f, y, t, NT, lds, active, in, -1, unused);
 }
 
-// Rows y0, y0 + step, ... of the frame, each row's loads issued during the
-// previous row's hole fill.
+// Rows y0, y0 + step, ... below y_end of the frame, the LDS state prepared
+// once, each row's loads issued during the previous row (one or two quads per
+// lane: a second row's share of four would not fit the registers).
 template <bool ALIGNED, int Q>
-__device__ __forceinline__ void warp_rows(const FrameDesc& f, int y0, int step, int t, int NT, uint32_t* lds) {
-    if (y0 >= f.h) return;
+__device__ __forceinline__ void warp_rows(const FrameDesc& f, int y0, int y_end, int step, int t, int NT,
+                                          uint32_t* lds) {
+    static_assert(Q < 4, "four quads per lane take one row at a time");
+    if (y0 >= y_end) return;
     WarpRowIn<ALIGNED, Q> cur, nxt;
     warp_load<ALIGNED, Q>(f, y0, t, NT, cur);
-    for (int y = y0; y < f.h; y += step) {
-        if (y != y0) __syncthreads();  // the previous row's last LDS reads are done
-        const int ny = y + step < f.h ? y + step : -1;
+    warp_prepare(f, f.w, t, NT, lds);
+    __syncthreads();
+    for (int y = y0; y < y_end; y += step) {
+        const int ny = y + step < y_end ? y + step : -1;
         warp_row_body<ALIGNED, Q>(f, y, t, NT, lds, true, cur, ny, nxt);
         cur = nxt;
     }

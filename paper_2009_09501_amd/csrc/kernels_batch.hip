@@ -215,7 +215,8 @@ __global__ void __launch_bounds__(256) k_mf_cbf(const FrameDesc* frames, const i
     cbf_tile<R, true>(f, local % gx, local / gx, threadIdx.x, lds, true);
 }
 
-// `rows` consecutive image rows per workgroup, one after another.
+// `rows` consecutive image rows per workgroup, each row's loads issued
+// during the previous one (four quads per lane: one row after another).
 template <int Q>
 __global__ void __launch_bounds__(1024) k_mf_warp(const FrameDesc* frames, const int* first, int n, int rows) {
     extern __shared__ uint32_t lds[];
@@ -223,11 +224,15 @@ __global__ void __launch_bounds__(1024) k_mf_warp(const FrameDesc* frames, const
     const int fi = frame_of(first, n, idx);
     const FrameDesc f = frames[fi];
     const int y0 = (idx - first[fi]) * rows;
-    for (int k = 0; k < rows; ++k) {
-        const int y = y0 + k;
-        if (y >= f.h) break;
-        if (k) __syncthreads();  // the previous row's last LDS reads are done
-        warp_row<true, Q>(f, y, threadIdx.x, blockDim.x, lds, true);
+    if constexpr (Q < 4) {
+        warp_rows<true, Q>(f, y0, min(y0 + rows, f.h), 1, threadIdx.x, blockDim.x, lds);
+    } else {
+        for (int k = 0; k < rows; ++k) {
+            const int y = y0 + k;
+            if (y >= f.h) break;
+            if (k) __syncthreads();  // the previous row's last LDS reads are done
+            warp_row<true, Q>(f, y, threadIdx.x, blockDim.x, lds, true);
+        }
     }
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "body_render.h"
 
@@ -24,7 +25,7 @@ __global__ void __launch_bounds__(256) k_cbf(FrameDesc f) {
 template <bool ALIGNED, int Q>
 __global__ void __launch_bounds__(512) k_warp(FrameDesc f) {
     extern __shared__ uint32_t lds[];
-    warp_rows<ALIGNED, Q>(f, blockIdx.x, gridDim.x, threadIdx.x, blockDim.x, lds);
+    warp_rows<ALIGNED, Q>(f, blockIdx.x, f.h, gridDim.x, threadIdx.x, blockDim.x, lds);
 }
 
 // Rows needing four quads per lane (wider than 4096 px): one row per
@@ -87,7 +88,8 @@ __global__ void __launch_bounds__(256) k_inpaint_final(FrameDesc f) {
 // ---------------------------------------------------------------------------
 // host-side launch helpers
 
-// The plain path: up to 512 lanes per row before four quads per lane.
+// The plain path: up to 512 lanes per row (two quads per lane from 2048 px)
+// before four quads per lane.
 bool warp_shape(int w, WarpShape* out) { return warp_shape_cap(w, 512, out); }
 
 bool warp_shape_cap(int w, int cap, WarpShape* out) {
@@ -123,17 +125,25 @@ static LaunchSpec cbf_r(const FrameDesc& f) {
 
 LaunchSpec spec_cbf(const FrameDesc& f) { return f.aligned ? cbf_r<true>(f) : cbf_r<false>(f); }
 
+// VGPRs per lane of k_warp<aligned, quads 1 / 2>, read at preparation (every
+// context stores the same values).
+static std::atomic<int> g_warp_vgprs[2][2] = {{128, 128}, {128, 128}};
+
 template <bool A>
 static LaunchSpec warp_q(const FrameDesc& f, const WarpShape& ws) {
     if (ws.quads == 4)
         return {reinterpret_cast<const void*>(&k_warp_wide<A>), dim3(f.h), dim3(ws.threads), ws.lds_bytes};
     const void* fn = ws.quads == 1 ? reinterpret_cast<const void*>(&k_warp<A, 1>)
                    : ws.quads == 2 ? reinterpret_cast<const void*>(&k_warp<A, 2>) : nullptr;
-    // resident workgroups per CU by LDS and lanes, times 256 CUs; every
-    // workgroup gets at least one row
+    // resident workgroups per CU by LDS, lanes and registers (512 VGPRs per
+    // SIMD lane in steps of 8, at most 8 waves per SIMD, a workgroup's waves
+    // spread over the 4 SIMDs), times 256 CUs; every workgroup gets a row
+    const int regs = (g_warp_vgprs[A ? 1 : 0][ws.quads == 1 ? 0 : 1].load(std::memory_order_relaxed) + 7) / 8 * 8;
+    const int waves_simd = std::min(8, 512 / std::max(regs, 8));
+    const int by_regs = std::max(1, waves_simd / ((ws.threads / 64 + 3) / 4));
     const int by_lds = std::max(1, (int)(kMaxLds / std::max<size_t>(ws.lds_bytes, 1)));
     const int by_lanes = std::max(1, 2048 / ws.threads);
-    const int resident = std::min(by_lds, by_lanes) * 256;
+    const int resident = std::min(std::min(by_lds, by_lanes), by_regs) * 256;
     return {fn, dim3(std::min(f.h, resident)), dim3(ws.threads), ws.lds_bytes};
 }
 
@@ -180,8 +190,21 @@ static hipError_t allow_lds() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
 }
 
+template <bool A, int Q>
+static hipError_t read_warp_vgprs() {
+    hipFuncAttributes a;
+    const hipError_t e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&k_warp<A, Q>));
+    if (e == hipSuccess && a.numRegs > 0)
+        g_warp_vgprs[A ? 1 : 0][Q == 1 ? 0 : 1].store(a.numRegs, std::memory_order_relaxed);
+    return e;
+}
+
 hipError_t prepare_render_kernels() {
     hipError_t e;
+    if ((e = read_warp_vgprs<true, 1>()) != hipSuccess) return e;
+    if ((e = read_warp_vgprs<true, 2>()) != hipSuccess) return e;
+    if ((e = read_warp_vgprs<false, 1>()) != hipSuccess) return e;
+    if ((e = read_warp_vgprs<false, 2>()) != hipSuccess) return e;
     if ((e = allow_lds<true, 1>()) != hipSuccess) return e;
     if ((e = allow_lds<true, 2>()) != hipSuccess) return e;
     if ((e = allow_lds<false, 1>()) != hipSuccess) return e;
