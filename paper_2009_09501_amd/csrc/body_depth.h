@@ -25,83 +25,95 @@ namespace pstereo {
 template <int K>
 struct BsTile {
     static constexpr int TH = 64;               // tile rows
-    static constexpr int RPT = TH / 16;         // rows per lane (16 rows apart)
+    static constexpr int RPT = 4;               // consecutive rows per lane
     static constexpr int BC = 64 / K;           // block columns per tile
     static constexpr int BR = TH / K;           // block rows per tile
     static constexpr int QB = K / 4;            // quads per block row
-    static constexpr int kLdsWords = (TH + 1) * 16 + BC * BR * 4;
+    static constexpr int LB = K / RPT;          // lane rows per block
+    static constexpr bool kInWave = LB <= 4;    // a block's lanes lie in one wave (K <= 16)
+    // luma of each lane row's first row; block sums of blocks spanning waves
+    static constexpr int kLdsWords = 16 * 16 + (kInWave ? 0 : BC * BR * 4);
 };
 
 // One 64 x 64 tile (tile_x, tile_y) on 256 lanes t = 0..255 (a multiple of
-// four whole waves): lane t takes quad t % 16 of rows t / 16 + 16 k, k < 4,
-// with all four rows' loads in flight together.  lds: BsTile<K>::kLdsWords
-// words.  Inactive lane groups (active == false) do no memory work but pass
-// the same two barriers.
+// four whole waves): lane t takes quad t % 16 of the four consecutive rows
+// from 4 (t / 16), all four rows' loads in flight together, and sums them in
+// registers; a block's lanes then combine by lane shuffles (blocks spanning
+// waves through LDS atomics as well).  lds: BsTile<K>::kLdsWords words.
+// Inactive lane groups (active == false) do no memory work but pass the same
+// barriers.
 template <int K, bool ALIGNED>
 __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile_y, int t, uint32_t* lds,
                                         bool active) {
-    constexpr int TH = BsTile<K>::TH, RPT = BsTile<K>::RPT, BC = BsTile<K>::BC, BR = BsTile<K>::BR;
-    constexpr int QB = BsTile<K>::QB;
-    uint32_t* ytile = lds;
-    uint32_t* acc = lds + (TH + 1) * 16;
+    using T = BsTile<K>;
+    constexpr int RPT = T::RPT, QB = T::QB, LB = T::LB;
+    uint32_t* yfirst = lds;     // [lane row][quad]
+    uint32_t* acc = lds + 256;  // blocks spanning waves: r, g, b, edge
     const int W = f.w, H = active ? f.h : 0;
-    const int lane = t & 63, wave = t >> 6;
-    const int qx = t & 15, tr = t >> 4;
-    const int tx0 = tile_x * 64, ty0 = tile_y * TH;
-    const int x0 = tx0 + 4 * qx;
+    const int qx = t & 15, lr = t >> 4;
+    const int tx0 = tile_x * 64, ty0 = tile_y * T::TH;
+    const int x0 = tx0 + 4 * qx, y0 = ty0 + RPT * lr;
     const int n = min(4, W - x0);
-    for (int i = t; i < BC * BR * 4; i += 256) acc[i] = 0;
-
-    uint32_t sr[RPT], sg[RPT], sb[RPT];
-    int edge[RPT];
-    uint32_t yq[RPT];  // packed luma bytes of the lane's quad, one word per row
     const uint32_t g = (uint32_t)f.g;
+    if (!T::kInWave)
+        for (int i = t; i < T::BC * T::BR * 4; i += 256) acc[i] = 0;
+
+    uint32_t sr = 0, sg = 0, sb = 0, edge = 0;
+    uint32_t yq[RPT];     // packed luma bytes of the lane's quad, one word per row
+    uint32_t ybelow = 0;  // the row below the tile (last lane row only)
     if (ALIGNED) {
-        uint3 v[RPT];
+        uint3 v[RPT + 1];
         uint32_t nx[RPT];
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int y = ty0 + tr + 16 * k;
-            v[k] = make_uint3(0, 0, 0);
-            nx[k] = 0;
+            const int y = y0 + k;
             if (y < H && x0 < W) {
                 const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
                 v[k] = *reinterpret_cast<const uint3*>(p);
                 if (x0 + 4 < W) nx[k] = *reinterpret_cast<const uint32_t*>(p + 12);
             }
         }
+        if (lr == 15 && ty0 + T::TH < H && x0 < W)
+            v[RPT] = *reinterpret_cast<const uint3*>(f.frame + ((size_t)(ty0 + T::TH) * W + x0) * 3);
+        constexpr uint32_t wlo = 77u | (150u << 8) | (29u << 16);
+        auto quad_luma = [&](uint3 q, uint32_t (&Y)[4]) {
+            Y[0] = __builtin_amdgcn_udot4(q.x, wlo, 128u, false) >> 8;
+            Y[1] = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(q.y, q.x, 3), wlo, 128u, false) >> 8;
+            Y[2] = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(q.z, q.y, 2), wlo, 128u, false) >> 8;
+            Y[3] = __builtin_amdgcn_udot4(q.z, wlo << 8, 128u, false) >> 8;
+        };
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
+            const bool in = y0 + k < H && x0 < W;
+            yq[k] = 0;
+            if (!in) continue;
             // four pixels = three dwords; sums and luma by byte dot products
-            sr[k] = __builtin_amdgcn_udot4(v[k].x, 0x01000001u, 0u, false);
-            sr[k] = __builtin_amdgcn_udot4(v[k].y, 0x00010000u, sr[k], false);
-            sr[k] = __builtin_amdgcn_udot4(v[k].z, 0x00000100u, sr[k], false);
-            sg[k] = __builtin_amdgcn_udot4(v[k].x, 0x00000100u, 0u, false);
-            sg[k] = __builtin_amdgcn_udot4(v[k].y, 0x01000001u, sg[k], false);
-            sg[k] = __builtin_amdgcn_udot4(v[k].z, 0x00010000u, sg[k], false);
-            sb[k] = __builtin_amdgcn_udot4(v[k].x, 0x00010000u, 0u, false);
-            sb[k] = __builtin_amdgcn_udot4(v[k].y, 0x00000100u, sb[k], false);
-            sb[k] = __builtin_amdgcn_udot4(v[k].z, 0x01000001u, sb[k], false);
-            constexpr uint32_t wlo = 77u | (150u << 8) | (29u << 16);
-            const uint32_t Y0 = __builtin_amdgcn_udot4(v[k].x, wlo, 128u, false) >> 8;
-            const uint32_t Y1 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(v[k].y, v[k].x, 3), wlo, 128u, false) >> 8;
-            const uint32_t Y2 = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(v[k].z, v[k].y, 2), wlo, 128u, false) >> 8;
-            const uint32_t Y3 = __builtin_amdgcn_udot4(v[k].z, wlo << 8, 128u, false) >> 8;
-            const int y = ty0 + tr + 16 * k;
-            const uint32_t Yn = x0 + 4 < W ? __builtin_amdgcn_udot4(nx[k], wlo, 128u, false) >> 8 : Y3;  // no step past the last column
-            const uint32_t hmax = max(max(__builtin_amdgcn_sad_u16(Y1, Y0, 0u), __builtin_amdgcn_sad_u16(Y2, Y1, 0u)),
-                                      max(__builtin_amdgcn_sad_u16(Y3, Y2, 0u), __builtin_amdgcn_sad_u16(Yn, Y3, 0u)));
-            const bool in = y < H && x0 < W;
-            edge[k] = in && hmax > g;
-            yq[k] = in ? (Y0 | (Y1 << 8) | (Y2 << 16) | (Y3 << 24)) : 0u;
-            ytile[(tr + 16 * k) * 16 + qx] = yq[k];
+            sr = __builtin_amdgcn_udot4(v[k].x, 0x01000001u, sr, false);
+            sr = __builtin_amdgcn_udot4(v[k].y, 0x00010000u, sr, false);
+            sr = __builtin_amdgcn_udot4(v[k].z, 0x00000100u, sr, false);
+            sg = __builtin_amdgcn_udot4(v[k].x, 0x00000100u, sg, false);
+            sg = __builtin_amdgcn_udot4(v[k].y, 0x01000001u, sg, false);
+            sg = __builtin_amdgcn_udot4(v[k].z, 0x00010000u, sg, false);
+            sb = __builtin_amdgcn_udot4(v[k].x, 0x00010000u, sb, false);
+            sb = __builtin_amdgcn_udot4(v[k].y, 0x00000100u, sb, false);
+            sb = __builtin_amdgcn_udot4(v[k].z, 0x01000001u, sb, false);
+            uint32_t Y[4];
+            quad_luma(v[k], Y);
+            const uint32_t Yn = x0 + 4 < W ? __builtin_amdgcn_udot4(nx[k], wlo, 128u, false) >> 8 : Y[3];  // no step past the last column
+            const uint32_t hmax = max(max(__builtin_amdgcn_sad_u16(Y[1], Y[0], 0u), __builtin_amdgcn_sad_u16(Y[2], Y[1], 0u)),
+                                      max(__builtin_amdgcn_sad_u16(Y[3], Y[2], 0u), __builtin_amdgcn_sad_u16(Yn, Y[3], 0u)));
+            if (hmax > g) edge = 1;
+            yq[k] = Y[0] | (Y[1] << 8) | (Y[2] << 16) | (Y[3] << 24);
+        }
+        if (lr == 15 && ty0 + T::TH < H && x0 < W) {
+            uint32_t Y[4];
+            quad_luma(v[RPT], Y);
+            ybelow = Y[0] | (Y[1] << 8) | (Y[2] << 16) | (Y[3] << 24);
         }
     } else {
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-            const int y = ty0 + tr + 16 * k;
-            sr[k] = sg[k] = sb[k] = 0;
-            edge[k] = 0;
+            const int y = y0 + k;
             yq[k] = 0;
             if (y < H && x0 < W) {
                 const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
@@ -114,75 +126,93 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     if (j < n) {
-                        sr[k] += r[j]; sg[k] += gg[j]; sb[k] += b[j];
+                        sr += r[j]; sg += gg[j]; sb += b[j];
                         yq[k] |= (uint32_t)Y[j] << (8 * j);
-                        if (x0 + j + 1 < W && iabs((j < 3 ? Y[j + 1] : ynext) - Y[j]) > f.g) edge[k] = 1;
+                        if (x0 + j + 1 < W && iabs((j < 3 ? Y[j + 1] : ynext) - Y[j]) > f.g) edge = 1;
                     }
                 }
             }
-            ytile[(tr + 16 * k) * 16 + qx] = yq[k];
         }
-    }
-    if (tr == 0) {
-        // the first row below the tile, for the vertical steps of its last row
-        const int y = ty0 + TH;
-        uint32_t v = 0;
-        if (y < H && x0 < W) {
+        if (lr == 15 && ty0 + T::TH < H && x0 < W) {
             int r[4], gg[4], b[4];
-            load_quad<ALIGNED>(f.frame + ((size_t)y * W + x0) * 3, n, r, gg, b);
+            load_quad<false>(f.frame + ((size_t)(ty0 + T::TH) * W + x0) * 3, n, r, gg, b);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) if (j < n) v |= (uint32_t)luma(r[j], gg[j], b[j]) << (8 * j);
+            for (int j = 0; j < 4; ++j) if (j < n) ybelow |= (uint32_t)luma(r[j], gg[j], b[j]) << (8 * j);
         }
-        ytile[TH * 16 + qx] = v;
     }
+    yfirst[lr * 16 + qx] = yq[0];
     __syncthreads();
+    // vertical steps: rows inside the lane's four, then the next lane row's
+    // first row (the row below the tile for the last lane row)
+    const uint32_t below_last = lr < 15 ? yfirst[(lr + 1) * 16 + qx] : ybelow;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-        const int y = ty0 + tr + 16 * k;
+        const int y = y0 + k;
         if (y + 1 < H && x0 < W) {
-            const uint32_t below = ytile[(tr + 16 * k + 1) * 16 + qx];
+            const uint32_t below = k + 1 < RPT ? yq[k + 1] : below_last;
             uint32_t vmax = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 if (j < n) vmax = max(vmax, __builtin_amdgcn_sad_u16((below >> (8 * j)) & 255u, (yq[k] >> (8 * j)) & 255u, 0u));
-            if (vmax > g) edge[k] = 1;
+            if (vmax > g) edge = 1;
         }
     }
-    // per row group k: combine the lanes of one block -- quads of a block
-    // row, and the four rows a wave covers (inside one block row: they start
-    // at a multiple of 4 and K >= 4)
-    // Two 16-bit sums per register: a wave holds at most 64 quads of a block
-    // (16 per row x 4 rows at K = 64), 64 x 4 x 255 < 2^16.
+    const int bxl = qx / QB, byl = lr / LB;  // the lane's block in the tile
+    if (T::kInWave) {
+        // two 16-bit sums per register: a block holds K * K / 16 <= 16 lanes
+        // of at most 16 pixels, 16 x 16 x 255 < 2^16
+        uint32_t rg = sr | (sg << 16), be = sb | (edge << 16);
 #pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        uint32_t rg = sr[k] | (sg[k] << 16), be = sb[k] | ((uint32_t)edge[k] << 16);
-#pragma unroll
-        for (int o = 1; o < QB && o < 16; o <<= 1) {
+        for (int o = 1; o < QB; o <<= 1) {
             rg += __shfl_xor(rg, o);
             be += __shfl_xor(be, o);
+        }
+#pragma unroll
+        for (int o = 1; o < LB; o <<= 1) {
+            rg += __shfl_xor(rg, 16 * o);
+            be += __shfl_xor(be, 16 * o);
+        }
+        const int bx = tile_x * T::BC + bxl, by = tile_y * T::BR + byl;
+        if (active && qx % QB == 0 && lr % LB == 0 && bx < f.gw && by < f.gh) {
+            const uint32_t cnt = (uint32_t)((min(bx * K + K, W) - bx * K) * (min(by * K + K, H) - by * K));
+            const uint32_t mr = ((rg & 0xFFFFu) + cnt / 2) / cnt;
+            const uint32_t mg = ((rg >> 16) + cnt / 2) / cnt;
+            const uint32_t mb = ((be & 0xFFFFu) + cnt / 2) / cnt;
+            f.stats[by * f.gw + bx] = mr | (mg << 8) | (mb << 16) | ((be >> 16) ? 1u << 24 : 0u);
+        }
+    } else {
+        // the wave's share of each block (four lane rows), then across waves
+#pragma unroll
+        for (int o = 1; o < QB; o <<= 1) {
+            sr += __shfl_xor(sr, o);
+            sg += __shfl_xor(sg, o);
+            sb += __shfl_xor(sb, o);
+            edge |= __shfl_xor(edge, o);
         }
 #pragma unroll
         for (int o = 16; o < 64; o <<= 1) {
-            rg += __shfl_xor(rg, o);
-            be += __shfl_xor(be, o);
+            sr += __shfl_xor(sr, o);
+            sg += __shfl_xor(sg, o);
+            sb += __shfl_xor(sb, o);
+            edge |= __shfl_xor(edge, o);
         }
-        if (lane < 16 && (qx % QB) == 0) {
-            const int blk = (qx / QB) + BC * ((16 * k + 4 * wave) / K);
-            atomicAdd(&acc[4 * blk + 0], rg & 0xFFFFu);
-            atomicAdd(&acc[4 * blk + 1], rg >> 16);
-            atomicAdd(&acc[4 * blk + 2], be & 0xFFFFu);
-            if (be >> 16) atomicOr(&acc[4 * blk + 3], 1u);
+        if (qx % QB == 0 && (lr & 3) == 0) {
+            const int blk = bxl + T::BC * byl;
+            atomicAdd(&acc[4 * blk + 0], sr);
+            atomicAdd(&acc[4 * blk + 1], sg);
+            atomicAdd(&acc[4 * blk + 2], sb);
+            if (edge) atomicOr(&acc[4 * blk + 3], 1u);
         }
-    }
-    __syncthreads();
-    for (int i = t; i < BC * BR; i += 256) {
-        const int bx = tile_x * BC + i % BC, by = tile_y * BR + i / BC;
-        if (active && bx < f.gw && by < f.gh) {
-            const uint32_t cnt = (uint32_t)((min(bx * K + K, W) - bx * K) * (min(by * K + K, H) - by * K));
-            const uint32_t mr = (acc[4 * i + 0] + cnt / 2) / cnt;
-            const uint32_t mg = (acc[4 * i + 1] + cnt / 2) / cnt;
-            const uint32_t mb = (acc[4 * i + 2] + cnt / 2) / cnt;
-            f.stats[by * f.gw + bx] = mr | (mg << 8) | (mb << 16) | (acc[4 * i + 3] << 24);
+        __syncthreads();
+        for (int i = t; i < T::BC * T::BR; i += 256) {
+            const int bx = tile_x * T::BC + i % T::BC, by = tile_y * T::BR + i / T::BC;
+            if (active && bx < f.gw && by < f.gh) {
+                const uint32_t cnt = (uint32_t)((min(bx * K + K, W) - bx * K) * (min(by * K + K, H) - by * K));
+                const uint32_t mr = (acc[4 * i + 0] + cnt / 2) / cnt;
+                const uint32_t mg = (acc[4 * i + 1] + cnt / 2) / cnt;
+                const uint32_t mb = (acc[4 * i + 2] + cnt / 2) / cnt;
+                f.stats[by * f.gw + bx] = mr | (mg << 8) | (mb << 16) | (acc[4 * i + 3] << 24);
+            }
         }
     }
 }
@@ -248,14 +278,6 @@ __device__ __forceinline__ void uf_unite_s(uint32_t* parent, uint32_t a, uint32_
         if (hook_prio(a) > hook_prio(b)) { const uint32_t t = a; a = b; b = t; }
         if (atomicCAS(&parent[pidx(a)], a, b) == a) return;
     }
-}
-
-// The value of v, opaque to the optimiser: per-block indices derived from it
-// are recomputed where they are used instead of being held in registers
-// across the whole kernel.
-__device__ __forceinline__ int opaque(int v) {
-    asm volatile("" : "+v"(v));
-    return v;
 }
 
 // Exact floor(n / d) for n, d < 2^16 from m = ceil(2^32 / d) (d >= 2): the

@@ -257,9 +257,33 @@ struct CbfTile {
     static constexpr int kLdsWords = kBlkOff + 2 * kBlkEntries;
 };
 
+// A lane's frame loads for one tile: three raw dwords per quad of the tile
+// and its halo (aligned frames; unaligned ones load bytes in the prologue).
+template <int R>
+struct CbfIn {
+    static constexpr int NQ = (CbfTile<R>::TR * kTileQuads + 255) / 256;
+    uint3 vq[NQ];
+};
+
+// Issue the loads of tile (tile_x, tile_y) for lane t; quads outside the
+// image (or all, when H = 0) load nothing and are not read later.
+template <int R, bool ALIGNED>
+__device__ __forceinline__ void cbf_load(const FrameDesc& f, int tile_x, int tile_y, int t, int H, CbfIn<R>& in) {
+    if (!ALIGNED) return;
+    const int W = f.w, tx0 = tile_x * kTileW, ty0 = tile_y * kTileH;
+#pragma unroll
+    for (int k = 0; k < CbfIn<R>::NQ; ++k) {
+        const int i = t + 256 * k;
+        const int tr = i / kTileQuads, tq = i - tr * kTileQuads;
+        const int yy = ty0 - R + tr, x0 = tx0 - 4 + 4 * tq;
+        if (i < CbfTile<R>::TR * kTileQuads && yy >= 0 && yy < H && x0 >= 0 && x0 < W)
+            in.vq[k] = *reinterpret_cast<const uint3*>(f.frame + ((size_t)yy * W + x0) * 3);
+    }
+}
+
 // One 64 x 32 tile (tile_x, tile_y) on 256 lanes t = 0..255 (four whole
 // waves).  lds: CbfTile<R>::kLdsWords words.  Inactive lane groups do no
-// memory work but pass the same two barriers.
+// memory work but pass the same three barriers.
 template <int R, bool ALIGNED>
 __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int tile_y, int t, uint32_t* lds,
                                          bool active) {
@@ -279,19 +303,9 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
 
     // the frame loads of all of a lane's quads of the tile and its halo go
     // out first, to arrive while the block table is staged
-    constexpr int NQ = (TR * kTileQuads + 255) / 256;
-    uint3 vq[NQ];
-    if (ALIGNED) {
-#pragma unroll
-        for (int k = 0; k < NQ; ++k) {
-            const int i = t + 256 * k;
-            const int tr = i / kTileQuads, tq = i - tr * kTileQuads;
-            const int yy = ty0 - R + tr, x0 = tx0 - 4 + 4 * tq;
-            vq[k] = make_uint3(0, 0, 0);
-            if (i < TR * kTileQuads && yy >= 0 && yy < H && x0 >= 0 && x0 < W)
-                vq[k] = *reinterpret_cast<const uint3*>(f.frame + ((size_t)yy * W + x0) * 3);
-        }
-    }
+    constexpr int NQ = CbfIn<R>::NQ;
+    CbfIn<R> in;
+    cbf_load<R, ALIGNED>(f, tile_x, tile_y, t, H, in);
 
     // the weight table (NK * 32 16-byte pieces) likewise
     constexpr int NW4 = NK * 32, NWL = (NW4 + 255) / 256;
@@ -310,7 +324,7 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
         const int nbt = bw * (by_hi - by_lo + 1);
         // after the strip-parallel grouping (unless its merge grouped the
         // whole frame itself) a block's region depth is resolved here from
-        // its strip-local label and the merge's slot table
+        // its component slot and the merge's slot table
         const bool strips = f.rstrip > 0 && f.rctl[1] == 0;
         for (int i = t; i < nbt; i += 256) {
             const int r = i / bw;
@@ -341,7 +355,7 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
             const uint8_t* p = f.frame + ((size_t)yy * W + x0) * 3;
             uint32_t col[4], D[4];
             if (ALIGNED) {
-                const uint3 v = vq[k];
+                const uint3 v = in.vq[k];
                 quad_luma2(v, y01, y23);
                 quad_colours(v, col);
             } else {

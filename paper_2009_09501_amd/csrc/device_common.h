@@ -88,6 +88,14 @@ __device__ __forceinline__ void store_quad(uint8_t* p, int n, const int (&r)[4],
 
 constexpr size_t kMaxLds = 160 * 1024;
 
+// The value of v, opaque to the optimiser: indices derived from it are
+// recomputed where they are used (or in each loop iteration) instead of being
+// held in registers across the whole kernel.
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // Workgroups are dispatched to the 8 XCDs round-robin by linear workgroup id.
 // Tile for workgroup bid of n: each XCD gets one contiguous run of tiles in
 // raster order, so neighbouring tiles -- sharing halo rows and the 128-byte

@@ -177,11 +177,11 @@ __device__ __forceinline__ int frame_of(const int* first, int n, int idx) {
     return lo;
 }
 
-constexpr int kBsLdsMax = BsTile<4>::kLdsWords;  // the largest: most blocks per tile
+constexpr int kBsLdsMax = BsTile<32>::kLdsWords;  // the largest: blocks spanning waves, most per tile
 
 __global__ void __launch_bounds__(256) k_mf_blockstats(const FrameDesc* frames, const int* first, int n) {
-    static_assert(BsTile<8>::kLdsWords <= kBsLdsMax && BsTile<16>::kLdsWords <= kBsLdsMax &&
-                  BsTile<32>::kLdsWords <= kBsLdsMax && BsTile<64>::kLdsWords <= kBsLdsMax, "blockstats LDS");
+    static_assert(BsTile<4>::kLdsWords <= kBsLdsMax && BsTile<8>::kLdsWords <= kBsLdsMax &&
+                  BsTile<16>::kLdsWords <= kBsLdsMax && BsTile<64>::kLdsWords <= kBsLdsMax, "blockstats LDS");
     __shared__ uint32_t lds[kBsLdsMax];
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
     const int fi = frame_of(first, n, idx);
