@@ -633,6 +633,19 @@ __device__ __forceinline__ bool linked(uint32_t s, uint32_t n, int tau) {
     return !((s | n) >> 24) && (int)__builtin_amdgcn_sad_u8(s, n, 0u) <= tau;
 }
 
+// Lanes with `pred` take consecutive numbers 1, 2, ... from the LDS counter
+// *ctr (one atomic per wave); 0 for the others.
+__device__ __forceinline__ uint32_t wave_claim(uint32_t* ctr, bool pred) {
+    const unsigned long long m = __ballot(pred);
+    if (!m) return 0u;
+    const int lead = __ffsll((long long)m) - 1;
+    uint32_t b = 0;
+    if ((int)(threadIdx.x & 63) == lead) b = atomicAdd(ctr, (uint32_t)__popcll(m));
+    b = __builtin_amdgcn_readlane(b, lead);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    return pred ? b + below + 1u : 0u;
+}
+
 __host__ __device__ constexpr size_t rg_strip_lds_words() { return 3 * kStripBlocks + 3 * kStripBlocks + 4; }
 
 __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uint32_t* lds) {
@@ -649,76 +662,113 @@ __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uin
     uint32_t* row = cnt + kStripBlocks;      // per root: lowest local row + 1
     uint32_t* misc = row + kStripBlocks;     // [0]: slots of this strip, [1]: its first slot,
                                              // [2]: its join candidates, [3]: their first entry
+    uint32_t* starts = cnt;                  // run-start bits, 32 blocks per word (before the counts)
     const uint32_t gwm = gw > 1 ? (uint32_t)((0x100000000ull + (uint32_t)gw - 1) / (uint32_t)gw) : 0u;
 
     for (int j = t; j < nload; j += kStripLanes) st[j] = f.stats[base + j];
     if (r0 > 0)
         for (int j = t; j < gw; j += kStripLanes) sa[j] = f.stats[base - gw + j];
-    for (int j = t; j < n; j += kStripLanes) {
-        par[j] = j;
-        cnt[j] = 0;
-        row[j] = 0;
+    for (int j = t; j < n; j += kStripLanes) par[j] = j;
+    if (t == 0) {
+        misc[0] = 0;
+        misc[2] = 0;
     }
-    if (t == 0) misc[0] = 0;
     __syncthreads();
 
-    // unions along the right and down links inside the strip
+    // horizontal runs: block j starts a run unless it is right-linked from
+    // j - 1 in the same row; the start bits of a wave's 64 consecutive blocks
+    // come from one ballot
+    int xk[2];
+    bool dk[2];  // down link inside the strip
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int j = t + k * kStripLanes;
-        if (j < n) {
-            const uint32_t s = st[j];
-            const int x = j - (int)div_u16((uint32_t)j, gwm, (uint32_t)gw) * gw;
-            if (x + 1 < gw && linked(s, st[j + 1], f.tau)) ufl_unite(par, j, j + 1, nullptr);
-            if (j + gw < n && linked(s, st[j + gw], f.tau)) ufl_unite(par, j, j + gw, nullptr);
+        const bool in = j < n;
+        const int x = in ? j - (int)div_u16((uint32_t)j, gwm, (uint32_t)gw) * gw : 0;
+        xk[k] = x;
+        const uint32_t sj = in ? st[j] : 0u;
+        dk[k] = in && j + gw < n && linked(sj, st[j + gw], f.tau);
+        const bool start = in && (x == 0 || !linked(st[j - 1], sj, f.tau));
+        const unsigned long long m = __ballot(start);
+        if ((t & 63) == 0 && j < n) {
+            starts[j >> 5] = (uint32_t)m;
+            starts[(j >> 5) + 1] = (uint32_t)(m >> 32);
         }
     }
     __syncthreads();
+    // the start of block i's run: the last start bit at or before i (every
+    // row's first block is one)
+    auto run_of = [&](int i) -> uint32_t {
+        int w = i >> 5;
+        uint32_t m = starts[w] & ((((uint32_t)1u << (i & 31)) << 1) - 1u);
+        while (!m) m = starts[--w];
+        return (uint32_t)(w * 32 + 31 - __clz(m));
+    };
 
-    // roots (= smallest block of each component); per root the non-edge
-    // count and lowest row, one atomic per wave when the wave's non-edge
-    // blocks share a root
+    // unions between runs along the down links inside the strip, one per
+    // place where the pair of runs above and below changes
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int j = t + k * kStripLanes;
+        if (!dk[k]) continue;
+        if (xk[k] > 0 && linked(st[j - 1], st[j], f.tau) && linked(st[j - 1 + gw], st[j + gw], f.tau) &&
+            linked(st[j - 1], st[j - 1 + gw], f.tau))
+            continue;
+        ufl_unite(par, run_of(j), run_of(j + gw), nullptr);
+    }
+    __syncthreads();
+
+    // roots (= smallest block of each component, its first run's start);
+    // per root the non-edge count and lowest row, one atomic per wave when
+    // the wave's non-edge blocks share a root
     uint32_t root[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int j = t + k * kStripLanes;
-        root[k] = j < n ? ufl_find(par, j) : 0u;
+        root[k] = j < n ? ufl_find(par, run_of(j)) : 0u;
     }
+    __syncthreads();  // the run bits are read; the counts take their place
+    for (int j = t; j < n; j += kStripLanes) {
+        cnt[j] = 0;
+        row[j] = 0;
+    }
+    __syncthreads();
+    // per root the non-edge count and lowest row: one pair of atomics per
+    // distinct root in a wave (its blocks are consecutive, so the highest
+    // lane holds the lowest row); slots for the non-edge roots and entries
+    // for the join candidates across the boundary above the strip -- the
+    // down links from the row above into the first row, except where block
+    // x - 1 links the same pair of components (right links in both rows and
+    // a down link) -- numbered one atomic per wave
+    uint32_t slot[2], cand[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int j = t + k * kStripLanes;
         const bool ne = j < n && !(st[j] >> 24);
         const uint32_t lrow = j < n ? div_u16((uint32_t)j, gwm, (uint32_t)gw) + 1u : 0u;
-        const unsigned long long mne = __ballot(ne);
-        if (mne) {
-            const int lead = __ffsll((long long)mne) - 1;
-            const uint32_t r_lead = __shfl(root[k], lead);
-            const unsigned long long msame = __ballot(ne && root[k] == r_lead);
-            if (msame == mne) {
-                uint32_t mr = ne ? lrow : 0u;
-#pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) mr = max(mr, (uint32_t)__shfl_xor((int)mr, o));
-                if ((t & 63) == lead) {
-                    atomicAdd(&cnt[r_lead], (uint32_t)__popcll(mne));
-                    atomicMax(&row[r_lead], mr);
-                }
-            } else if (ne) {
-                atomicAdd(&cnt[root[k]], 1u);
-                atomicMax(&row[root[k]], lrow);
+        for (unsigned long long todo = __ballot(ne); todo;) {
+            const int lead = __ffsll((long long)todo) - 1;
+            const uint32_t r = __builtin_amdgcn_readlane(root[k], lead);
+            const unsigned long long m = __ballot(ne && root[k] == r);
+            const uint32_t mr = __builtin_amdgcn_readlane(lrow, 63 - __clzll(m));
+            if ((t & 63) == lead) {
+                atomicAdd(&cnt[r], (uint32_t)__popcll(m));
+                atomicMax(&row[r], mr);
             }
+            todo &= ~m;
         }
+        slot[k] = wave_claim(&misc[0], ne && root[k] == (uint32_t)j);
+        bool c = r0 > 0 && j < gw && linked(sa[j], st[j], f.tau);
+        if (c && j > 0 && linked(sa[j - 1], st[j - 1], f.tau) && linked(sa[j - 1], sa[j], f.tau) &&
+            linked(st[j - 1], st[j], f.tau))
+            c = false;
+        cand[k] = wave_claim(&misc[2], c);
     }
     __syncthreads();
-
-    // slots for the strip's non-edge roots
-    uint32_t slot[2] = {0u, 0u};
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int j = t + k * kStripLanes;
-        if (j < n && root[k] == (uint32_t)j && !(st[j] >> 24)) slot[k] = atomicAdd(&misc[0], 1u) + 1u;
+    if (t == 0) {
+        misc[1] = atomicAdd(&f.rctl[0], misc[0]);
+        if (r0 > 0) misc[3] = atomicAdd(&f.rctl[2], misc[2]);
     }
-    __syncthreads();
-    if (t == 0) misc[1] = atomicAdd(&f.rctl[0], misc[0]);
     __syncthreads();
     const uint32_t first = misc[1];
     // each root's slot replaces its union-find entry (the finds are done)
@@ -743,25 +793,7 @@ __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uin
         f.binfo[base + j] = make_uint2(s, (s >> 24) ? 0u : par[root[k]]);
     }
 
-    // join candidates across the boundary above the strip: the down links
-    // from the row above into the first row, except where block x - 1 links
-    // the same pair of components (right links in both rows and a down link)
     if (r0 > 0) {
-        if (t == 0) misc[2] = 0;
-        __syncthreads();
-        uint32_t cand[2] = {0u, 0u};
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int x = t + k * kStripLanes;
-            if (x >= gw || !linked(sa[x], st[x], f.tau)) continue;
-            if (x > 0 && linked(sa[x - 1], st[x - 1], f.tau) && linked(sa[x - 1], sa[x], f.tau) &&
-                linked(st[x - 1], st[x], f.tau))
-                continue;
-            cand[k] = atomicAdd(&misc[2], 1u) + 1u;
-        }
-        __syncthreads();
-        if (t == 0) misc[3] = atomicAdd(&f.rctl[2], misc[2]);
-        __syncthreads();
         const uint32_t bfirst = misc[3];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -796,6 +828,24 @@ __device__ __forceinline__ void rg_merge_body(const FrameDesc& f, uint32_t* lds)
     uint32_t* cnt = lab + kRegionSlots;
     uint32_t* row = cnt + kRegionSlots;
     uint32_t* misc = row + kRegionSlots;  // [0]: background key
+    // the strips' join candidates (each a slot below and the block above,
+    // whose slot is a dependent load) are fetched while the slots load
+    const uint32_t ncand = f.rctl[2];
+    constexpr int CU = kBoundSlots / kStripLanes;
+    const bool listed = ncand <= (uint32_t)kBoundSlots;
+    uint32_t ca[CU], cb[CU];
+    if (listed) {
+        uint2 e[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (t + u * kStripLanes < (int)ncand) e[u] = f.rbnd[t + u * kStripLanes];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (t + u * kStripLanes < (int)ncand) {
+                ca[u] = f.binfo[e[u].x].y;
+                cb[u] = e[u].y;
+            }
+    }
     for (int s = t; s < ns; s += kStripLanes) {
         const uint2 e = f.rent[s];
         par[s] = s;
@@ -812,13 +862,11 @@ __device__ __forceinline__ void rg_merge_body(const FrameDesc& f, uint32_t* lds)
     const int nbnd = (gh + SR - 1) / SR - 1;
     const int total = nbnd * gw;
     const uint32_t gwm = gw > 1 ? (uint32_t)((0x100000000ull + (uint32_t)gw - 1) / (uint32_t)gw) : 0u;
-    const uint32_t ncand = f.rctl[2];
-    if (ncand <= (uint32_t)kBoundSlots) {
+    if (listed) {
         // the strips' compacted join candidates
-        for (uint32_t q = t; q < ncand; q += kStripLanes) {
-            const uint2 e = f.rbnd[q];
-            ufl_unite(par, f.binfo[e.x].y, e.y, lab);
-        }
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (t + u * kStripLanes < (int)ncand) ufl_unite(par, ca[u], cb[u], lab);
     } else
     // every boundary position, four per lane at a time, every global load of
     // the four issued before any is used
