@@ -185,8 +185,9 @@ int pstereo_profile_collect(pstereo_ctx *ctx, double ms_sum[4], int *count,
  * size and parameters (generated depth only: no PSTEREO_DEPTH_EXTERNAL, no
  * depth dumps); the graph runs on p->stream (NULL = context stream).
  * pstereo_video_frame validates the buffers like pstereo_synthesize, writes
- * their pointers into the graph's kernel arguments and launches it; it may
- * wait for the replay made four frames earlier.  Frames on one video run in
+ * their pointers into the kernel arguments of one of eight instantiated
+ * copies of the graph and launches it; it may wait for the replay made eight
+ * to eleven frames earlier.  Frames on one video run in
  * order on its stream and share the context's scratch, so a context drives
  * one video (or plain calls on the same stream) at a time.
  * pstereo_video_end waits for the stream and frees the graphs.

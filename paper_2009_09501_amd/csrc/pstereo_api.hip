@@ -519,8 +519,15 @@ int pstereo_profile_collect(pstereo_ctx* c, double ms_sum[4], int* count, double
 // frame and output pointers written into the kernel nodes' arguments.  A
 // small ring of instantiated graphs lets the host prepare frame i+1 while
 // frame i runs; an exec is only updated once its previous replay finished.
+// A ring of kRing instantiated graphs of the frame's launch sequence.  Frame
+// c replays graph c % kRing after rewriting the arguments of the nodes that
+// read the frame and output pointers (the region grouping reads only the
+// context's scratch and keeps its template arguments).  A graph is rewritten
+// only after its previous replay has finished: completion events are
+// recorded after every kEvery-th frame, alternating between two events.
 struct pstereo_video {
-    static constexpr int kRing = 4;
+    static constexpr int kRing = 8;
+    static constexpr int kEvery = 4;
     pstereo_ctx* ctx = nullptr;
     int w = 0, h = 0;
     pstereo_params params{};
@@ -528,12 +535,13 @@ struct pstereo_video {
     FrameDesc tmpl{};
     WarpShape ws{};
     pstereo::LaunchSpec ls[kMaxSpecs];
+    bool per_frame[kMaxSpecs] = {};  // node i reads the frame / output pointers
     int nk = 0;
     hipGraph_t graph[kRing] = {};
     hipGraphExec_t exec[kRing] = {};
     hipGraphNode_t node[kRing][kMaxSpecs] = {};
-    hipEvent_t done[kRing] = {};
-    bool pending[kRing] = {};
+    hipEvent_t done[2] = {};
+    long long waited = -1;  // last event group known complete
     long long count = 0;
 };
 
@@ -541,8 +549,9 @@ static void video_free(pstereo_video* v) {
     for (int k = 0; k < pstereo_video::kRing; ++k) {
         if (v->exec[k]) (void)hipGraphExecDestroy(v->exec[k]);
         if (v->graph[k]) (void)hipGraphDestroy(v->graph[k]);
-        if (v->done[k]) (void)hipEventDestroy(v->done[k]);
     }
+    for (int k = 0; k < 2; ++k)
+        if (v->done[k]) (void)hipEventDestroy(v->done[k]);
     delete v;
 }
 
@@ -591,7 +600,9 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
     v->tmpl.out_l = v->tmpl.out_r = v->tmpl.out_a = nullptr;
     v->tmpl.frame = nullptr;
     v->tmpl.aligned = (w % 4 == 0);
-    frame_specs(v->tmpl, v->ws, v->ls, v->nk);
+    int stage[kMaxSpecs];
+    frame_specs(v->tmpl, v->ws, v->ls, v->nk, &stage);
+    for (int i = 0; i < v->nk; ++i) v->per_frame[i] = stage[i] != 1;
     hipError_t e = hipSetDevice(c->device);
     for (int k = 0; k < pstereo_video::kRing && e == hipSuccess; ++k) {
         e = hipGraphCreate(&v->graph[k], 0);
@@ -602,8 +613,8 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
             e = hipGraphAddKernelNode(&v->node[k][i], v->graph[k], i ? &v->node[k][i - 1] : nullptr, i ? 1 : 0, &kp);
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&v->exec[k], v->graph[k], nullptr, nullptr, 0);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&v->done[k], hipEventDisableTiming);
     }
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&v->done[k], hipEventDisableTiming);
     if (e != hipSuccess) {
         video_free(v);
         return fail(c, PSTEREO_E_DEVICE, "graph setup: %s", hipGetErrorString(e));
@@ -634,20 +645,31 @@ int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, 
                 return fail(c, PSTEREO_E_DEVICE, "launch: %s", hipGetErrorString(e));
         return PSTEREO_OK;
     }
-    const int k = (int)(v->count % pstereo_video::kRing);
-    if (v->pending[k] && (e = hipEventSynchronize(v->done[k])) != hipSuccess)
-        return fail(c, PSTEREO_E_DEVICE, "event synchronize: %s", hipGetErrorString(e));
+    constexpr int R = pstereo_video::kRing, E = pstereo_video::kEvery;
+    const long long n = v->count;
+    const int k = (int)(n % R);
+    if (n >= R) {
+        // the previous replay of graph k (frame n - R) is covered by the event
+        // recorded after frame ((n - R) / E) * E + E - 1 < n
+        const long long g = (n - R) / E;
+        if (g > v->waited) {
+            if ((e = hipEventSynchronize(v->done[g % 2])) != hipSuccess)
+                return fail(c, PSTEREO_E_DEVICE, "event synchronize: %s", hipGetErrorString(e));
+            v->waited = g;
+        }
+    }
     FrameDesc arg = f;
     void* args[] = {&arg};
     for (int i = 0; i < v->nk; ++i) {
+        if (!v->per_frame[i]) continue;
         hipKernelNodeParams kp = node_params(v->ls[i], args);
         if ((e = hipGraphExecKernelNodeSetParams(v->exec[k], v->node[k][i], &kp)) != hipSuccess)
             return fail(c, PSTEREO_E_DEVICE, "graph node update: %s", hipGetErrorString(e));
     }
     if ((e = hipGraphLaunch(v->exec[k], v->stream)) != hipSuccess)
         return fail(c, PSTEREO_E_DEVICE, "graph launch: %s", hipGetErrorString(e));
-    (void)hipEventRecord(v->done[k], v->stream);
-    v->pending[k] = true;
+    if (n % E == E - 1 && (e = hipEventRecord(v->done[(n / E) % 2], v->stream)) != hipSuccess)
+        return fail(c, PSTEREO_E_DEVICE, "event record: %s", hipGetErrorString(e));
     v->count++;
     c->have_blocks = true;
     c->last_fd = f;

@@ -31,10 +31,11 @@ def test_video_graph_matches_plain_and_oracle(ctx, oracle_mod, w, h):
     from paper_2009_09501_amd import pstereo_params_init
     from paper_2009_09501_amd.pstereo import pstereo_video_begin, pstereo_video_end, pstereo_video_frame
     dev = torch.device("cuda:0")
-    spec = synth.VideoSpec(4, w, h, frames=12, n=40, sigma=3.0)
-    frames = [torch.from_numpy(spec.frame(t)).to(dev) for t in range(10)]
+    # 21 frames: the ring of graphs wraps twice, through both completion events
+    spec = synth.VideoSpec(4, w, h, frames=21, n=40, sigma=3.0)
+    frames = [torch.from_numpy(spec.frame(t)).to(dev) for t in range(21)]
     B = synth.default_disparity(w)
-    print(f"video {w}x{h} B={B}: 10 frames through the graph", flush=True)
+    print(f"video {w}x{h} B={B}: 21 frames through the graph", flush=True)
     outs = [[torch.empty_like(frames[0]) for _ in range(3)] for _ in frames]
     p = pstereo_params_init(max_disparity=B)
     p.stream = torch.cuda.current_stream().cuda_stream
@@ -49,8 +50,8 @@ def test_video_graph_matches_plain_and_oracle(ctx, oracle_mod, w, h):
         ref = _plain(ctx, f, max_disparity=B)
         for got, want in zip(o, ref):
             assert np.array_equal(got.cpu().numpy(), want), f"frame {i}"
-    ora = oracle_mod.synthesize(spec.frame(9), B)
-    assert np.array_equal(outs[9][2].cpu().numpy(), ora.A)
+    ora = oracle_mod.synthesize(spec.frame(20), B)
+    assert np.array_equal(outs[20][2].cpu().numpy(), ora.A)
 
 
 def test_video_rejects_external_depth(ctx):
