@@ -585,11 +585,11 @@ __device__ __forceinline__ void store_quad_views(const FrameDesc& f, int y, int 
 }
 
 // LDS of the warp of one row: both z-buffers (kidx-padded), the shift
-// table, the row's filtered depth and per chunk (Q x 64 lanes' quads) the
-// keys at its valid extremes.
+// table, the zero-key tag, the row's filtered depth, and per chunk (Q x 64
+// lanes' quads) the keys at its valid extremes.
 __host__ __device__ constexpr size_t warp_lds_bytes(int w, int threads, int q) {
     return (size_t)(2 * (((w + 3) & ~3) + ((w + 3) & ~3) / 32 + 1) * 4 + 256 * 4 + ((w + 3) & ~3) +
-                    8 * q * (threads / 64) * 4);
+                    8 * q * (threads / 64) * 4 + 4);
 }
 
 // A lane's share of one image row: the frame bytes of its Q quads (three
@@ -641,6 +641,7 @@ __device__ __forceinline__ void warp_prepare(const FrameDesc& f, int W, int t, i
     uint32_t* lut = lds + 2 * KW;
     for (int d = t; d < 256; d += NT) lut[d] = shift_entry(d, f.B, f.T);
     for (int i = t; i < 2 * KW; i += NT) lds[i] = 0;
+    if (t == 0) lut[256] = 0;  // the zero-key tag
 }
 
 // Key of the last (LAST) or first valid pixel of a quad: mask m (bit j =
@@ -697,6 +698,40 @@ __device__ __forceinline__ void fill_quad(uint32_t m, uint32_t own, const uint32
     }
 }
 
+// One view's colours of a lane's quad after the hole fill (fill_quad), for
+// the views whose wave has a hole; the nearest valid keys outside the quad
+// come from the wave's lanes (shuffles, run on all lanes) or from the other
+// chunks' published extremes (entry words pw (last) and pw + 1 (first),
+// flag bit pbit).
+template <bool LEFT_TIES>
+__device__ __forceinline__ void fill_view(uint32_t qv, uint32_t oq, const uint32_t* k, unsigned long long any,
+                                          unsigned long long below, unsigned long long above, int lane,
+                                          const uint32_t* pub, int ch, int NC, int pw, uint32_t pbit, uint32_t* c,
+                                          uint32_t& need) {
+    if (!__ballot((oq & ~qv) != 0)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = k[j] & 0xFFFFFFu;
+        return;
+    }
+    const unsigned long long lb = any & below, la = any & above;
+    uint32_t ex = (uint32_t)__shfl((int)quad_extreme_key<true>(qv, k), lb ? 63 - __clzll(lb) : lane);
+    uint32_t ef = (uint32_t)__shfl((int)quad_extreme_key<false>(qv, k), la ? __ffsll(la) - 1 : lane);
+    bool hx = lb != 0, hf = la != 0;
+    if (oq & ~qv) {
+        for (int o = ch - 1; o >= 0 && !hx; --o)
+            if (pub[8 * o + 4] & pbit) {
+                ex = pub[8 * o + pw];
+                hx = true;
+            }
+        for (int o = ch + 1; o < NC && !hf; ++o)
+            if (pub[8 * o + 4] & pbit) {
+                ef = pub[8 * o + pw + 1];
+                hf = true;
+            }
+    }
+    fill_quad<LEFT_TIES>(qv, oq, k, ex, hx, ef, hf, c, need);
+}
+
 // Image row y on NT lanes t = 0..NT-1 (whole waves) from the lane's loaded
 // share `in`; when next_y >= 0 the share of row next_y is loaded into `next`
 // while this row is resolved.  lds: warp_lds_bytes(w, NT, Q) bytes in the
@@ -714,12 +749,14 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
     uint32_t* keyL = lds;
     uint32_t* keyR = keyL + KW;
     const uint32_t* lut = keyR + KW;                                  // 256 entries
-    uint8_t* drow_l = reinterpret_cast<uint8_t*>(keyR + KW + 256);    // the row's filtered depth, W4 bytes
+    uint32_t* ztag = keyR + KW + 256;                                 // y + 1 if a source of row y has key 0
+    uint8_t* drow_l = reinterpret_cast<uint8_t*>(ztag + 1);           // the row's filtered depth, W4 bytes
     uint32_t* pub = reinterpret_cast<uint32_t*>(drow_l + W4);         // per chunk: 8 words
 
     // ---- forward warp of the row's pixels into both views; the key carries
     // the depth above the colour, so the atomic max keeps the nearer source
     // and its colour
+    bool zero_key = false;
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
         const int x0 = 4 * (qi * NT + t);
@@ -743,10 +780,12 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
             const int xl = x + (int)(int16_t)(lv & 0xFFFFu);
             const int xr = x + (int)(int16_t)(lv >> 16);
             const uint32_t key = (d << 24) | c[j];
+            zero_key |= key == 0;
             if ((unsigned)xl < (unsigned)W) atomicMax(&keyL[kidx(xl)], key);
             if ((unsigned)xr < (unsigned)W) atomicMax(&keyR[kidx(xr)], key);
         }
     }
+    if (__ballot(zero_key) && (t & 63) == 0) *ztag = (uint32_t)y + 1u;
     __syncthreads();
 
     // the next row's share is loaded while this row is resolved
@@ -754,8 +793,9 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
 
     // ---- validity, and the z-buffers back to zero: a landed source has a
     // non-zero key, except a black source of depth 0, whose key is 0; such a
-    // source is the only one that can land on a zero key, so zero keys check
-    // the depth at their depth-0 source position directly
+    // source is the only one that can land on a zero key, so in a row that
+    // has one (the tag) zero keys check the depth at their depth-0 source
+    // position directly
     uint32_t kl[4 * Q], kr[4 * Q];
     uint32_t vL = 0, vR = 0, own = 0;  // bit 4 qi + j
 #pragma unroll
@@ -778,7 +818,7 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
             if (kr[i]) vR |= 1u << i;
         }
     }
-    if (__ballot((own & ~(vL & vR)) != 0)) {
+    if (*ztag == (uint32_t)y + 1u && __ballot((own & ~(vL & vR)) != 0)) {
         const uint32_t lv0 = lut[0];
         const int o0[2] = {(int)(int16_t)(lv0 & 0xFFFFu), (int)(int16_t)(lv0 >> 16)};
         const uint32_t* d32 = reinterpret_cast<const uint32_t*>(drow_l);
@@ -857,47 +897,19 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
         const int x0 = 4 * (qi * NT + t);
         const uint32_t ql = (vL >> (4 * qi)) & 15u, qr = (vR >> (4 * qi)) & 15u;
         const uint32_t oq = (own >> (4 * qi)) & 15u;
-        uint32_t cl[4], cr[4];
-        if (__ballot((oq & ~(ql & qr)) != 0)) {
-            const unsigned long long lb = anyL[qi] & below, rb = anyR[qi] & below;
-            const unsigned long long la = anyL[qi] & above, ra = anyR[qi] & above;
-            uint32_t exL = (uint32_t)__shfl((int)quad_extreme_key<true>(ql, &kl[4 * qi]), lb ? 63 - __clzll(lb) : lane);
-            uint32_t exR = (uint32_t)__shfl((int)quad_extreme_key<true>(qr, &kr[4 * qi]), rb ? 63 - __clzll(rb) : lane);
-            uint32_t efL = (uint32_t)__shfl((int)quad_extreme_key<false>(ql, &kl[4 * qi]), la ? __ffsll(la) - 1 : lane);
-            uint32_t efR = (uint32_t)__shfl((int)quad_extreme_key<false>(qr, &kr[4 * qi]), ra ? __ffsll(ra) - 1 : lane);
-            bool hxL = lb != 0, hxR = rb != 0, hfL = la != 0, hfR = ra != 0;
-            if (oq & ~(ql & qr)) {
-                const int ch = qi * NW + wave;
-                for (int c = ch - 1; c >= 0 && !(hxL && hxR); --c) {
-                    const uint32_t fl = pub[8 * c + 4];
-                    if (!hxL && (fl & 1u)) { exL = pub[8 * c + 0]; hxL = true; }
-                    if (!hxR && (fl & 2u)) { exR = pub[8 * c + 2]; hxR = true; }
-                }
-                for (int c = ch + 1; c < NC && !(hfL && hfR); ++c) {
-                    const uint32_t fl = pub[8 * c + 4];
-                    if (!hfL && (fl & 1u)) { efL = pub[8 * c + 1]; hfL = true; }
-                    if (!hfR && (fl & 2u)) { efR = pub[8 * c + 3]; hfR = true; }
-                }
-            }
-            uint32_t needL = 0, needR = 0;
-            fill_quad<true>(ql, oq, &kl[4 * qi], exL, hxL, efL, hfL, cl, needL);
-            fill_quad<false>(qr, oq, &kr[4 * qi], exR, hxR, efR, hfR, cr, needR);
-            if (needL | needR) {
-                // a view row without any valid pixel keeps the source pixels
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (!(((needL | needR) >> j) & 1u)) continue;
-                    const uint8_t* p = f.frame + ((size_t)y * W + x0 + j) * 3;
-                    const uint32_t src = p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
-                    if ((needL >> j) & 1u) cl[j] = src;
-                    if ((needR >> j) & 1u) cr[j] = src;
-                }
-            }
-        } else {
+        uint32_t cl[4], cr[4], needL = 0, needR = 0;
+        const int ch = qi * NW + wave;
+        fill_view<true>(ql, oq, &kl[4 * qi], anyL[qi], below, above, lane, pub, ch, NC, 0, 1u, cl, needL);
+        fill_view<false>(qr, oq, &kr[4 * qi], anyR[qi], below, above, lane, pub, ch, NC, 2, 2u, cr, needR);
+        if (needL | needR) {
+            // a view row without any valid pixel keeps the source pixels
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                cl[j] = kl[4 * qi + j] & 0xFFFFFFu;
-                cr[j] = kr[4 * qi + j] & 0xFFFFFFu;
+                if (!(((needL | needR) >> j) & 1u)) continue;
+                const uint8_t* p = f.frame + ((size_t)y * W + x0 + j) * 3;
+                const uint32_t src = p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+                if ((needL >> j) & 1u) cl[j] = src;
+                if ((needR >> j) & 1u) cr[j] = src;
             }
         }
         if (x0 < W) store_quad_views<ALIGNED>(f, y, x0, cl, cr);
