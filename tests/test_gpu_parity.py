@@ -133,6 +133,26 @@ def test_external_random_depth(ctx, oracle_mod, seed):
     _check(ctx, oracle_mod, f, 40, depth=dep, case=f"external depth seed {seed}")
 
 
+@pytest.mark.parametrize("w,h", [(640, 96), (3840, 64)])
+def test_black_sources_at_depth_zero(ctx, oracle_mod, w, h):
+    """A black source at depth 0 has the same z-buffer key as an empty
+    pixel: rows with such sources (and rows without, the zero-key tag off)
+    against the oracle, with an external depth of 0 in a band and around
+    black rectangles, and one row that is all black at depth 0."""
+    rng = np.random.default_rng(w + h)
+    f = synth.gen_frame(w * 3 + h, w, h, 12, 4.0)
+    dep = np.full((h, w), 180, np.uint8)
+    dep[:, : w * 2 // 5] = 0                      # a depth-0 band
+    dep[h // 3: h // 2, :] = 0                    # and depth-0 rows
+    f[h // 8: h // 3, w // 10: w // 4] = 0        # black inside the band
+    f[h // 3: h // 2, w // 2: w // 2 + w // 8] = 0
+    ys, xs = rng.integers(0, h, 400), rng.integers(0, w, 400)
+    f[ys, xs] = 0                                 # scattered black pixels
+    f[h - 3] = 0
+    dep[h - 3] = 0                                # a black row at depth 0
+    _check(ctx, oracle_mod, f, synth.default_disparity(w), depth=dep, case=f"black depth-0 {w}x{h}")
+
+
 def test_zero_base_identity(ctx):
     f = synth.gen_frame(9, 640, 360, 12, 4.0)
     got = _run(ctx, f, max_disparity=0)
