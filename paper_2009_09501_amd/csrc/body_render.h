@@ -127,54 +127,20 @@ __device__ __forceinline__ void quad_depth_tab(const FrameDesc& f, int x0, int y
         for (int j = 0; j < 4; ++j) D[j] = own.y;
         return;
     }
+    // branch-free: per pixel the minimum of (distance << 12 | k << 8 |
+    // depth) over the candidates k in raster order (distance <= 765), so
+    // that ties go to the first; non-candidates contribute all ones
     uint32_t best[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const uint2 c = tab[(by - by_lo + k / 3 - 1) * bw + (bx - bx_lo + k % 3 - 1)];
+        const uint32_t tag = (c.x >> 24) ? 0xFFFFFFFFu : (((uint32_t)k << 8) | c.y);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) best[j] = min(best[j], (__builtin_amdgcn_sad_u8(col[j], c.x, 0u) << 12) | tag);
+    }
     const uint32_t fallback = (uint32_t)ramp(by, f.gh);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) D[j] = fallback;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int cx = bx + k % 3 - 1, cy = by + k / 3 - 1;
-        if (cx < 0 || cx >= f.gw || cy < 0 || cy >= f.gh) continue;
-        const uint2 c = tab[(cy - by_lo) * bw + (cx - bx_lo)];
-        if (c.x >> 24) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t dd = __builtin_amdgcn_sad_u8(col[j], c.x, 0u);
-            if (dd < best[j]) { best[j] = dd; D[j] = c.y; }
-        }
-    }
-}
-
-__device__ __forceinline__ void quad_depth(const FrameDesc& f, int x0, int yy, const uint32_t (&col)[4],
-                                           uint32_t (&D)[4]) {
-    const int bx = x0 / f.K, by = yy / f.K;
-    const uint2 own = f.binfo[by * f.gw + bx];
-    if (!(own.x >> 24)) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) D[j] = own.y;
-        return;
-    }
-    uint2 c[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int cx = min(max(bx + k % 3 - 1, 0), f.gw - 1);
-        const int cy = min(max(by + k / 3 - 1, 0), f.gh - 1);
-        c[k] = f.binfo[cy * f.gw + cx];
-    }
-    uint32_t best[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-    const uint32_t fallback = (uint32_t)ramp(by, f.gh);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) D[j] = fallback;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const int cx = bx + k % 3 - 1, cy = by + k / 3 - 1;
-        if (cx < 0 || cx >= f.gw || cy < 0 || cy >= f.gh || (c[k].x >> 24)) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t dd = __builtin_amdgcn_sad_u8(col[j], c[k].x, 0u);
-            if (dd < best[j]) { best[j] = dd; D[j] = c[k].y; }
-        }
-    }
+    for (int j = 0; j < 4; ++j) D[j] = best[j] == 0xFFFFFFFFu ? fallback : (best[j] & 255u);
 }
 
 // ---------------------------------------------------------------------------
@@ -316,9 +282,11 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
 
     // the tile's block table (halo and one ring of neighbours, clipped to the
     // grid) into LDS, so the raw depth needs no global lookups
+    // (clipped to the grid plus one ring outside it, whose entries are
+    // marked as edge blocks)
     const int ks = __builtin_ctz((unsigned)f.K);
-    const int bx_lo = max(0, ((tx0 - 4) >> ks) - 1), bx_hi = min(f.gw - 1, ((tx0 + 4 * kTileQuads - 5) >> ks) + 1);
-    const int by_lo = max(0, ((ty0 - R) >> ks) - 1), by_hi = min(f.gh - 1, ((ty0 + kTileH - 1 + R) >> ks) + 1);
+    const int bx_lo = max(-1, ((tx0 - 4) >> ks) - 1), bx_hi = min(f.gw, ((tx0 + 4 * kTileQuads - 5) >> ks) + 1);
+    const int by_lo = max(-1, ((ty0 - R) >> ks) - 1), by_hi = min(f.gh, ((ty0 + kTileH - 1 + R) >> ks) + 1);
     const int bw = bx_hi - bx_lo + 1;
     if (!f.depth_in && H > 0) {
         const int nbt = bw * (by_hi - by_lo + 1);
@@ -328,9 +296,12 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
         const bool strips = f.rstrip > 0 && f.rctl[1] == 0;
         for (int i = t; i < nbt; i += 256) {
             const int r = i / bw;
-            const int by = by_lo + r, b = by * f.gw + bx_lo + (i - r * bw);
-            uint2 e = f.binfo[b];
-            if (strips) e.y = block_depth_from_slots(f, by, e);
+            const int by = by_lo + r, bx = bx_lo + (i - r * bw);
+            uint2 e = make_uint2(1u << 24, 0u);
+            if (by >= 0 && by < f.gh && bx >= 0 && bx < f.gw) {
+                e = f.binfo[by * f.gw + bx];
+                if (strips) e.y = block_depth_from_slots(f, by, e);
+            }
             btab[i] = e;
         }
     }
