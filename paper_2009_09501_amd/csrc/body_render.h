@@ -391,20 +391,35 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
         const int x0 = tx0 + 4 * qx, y = ty0 + ty;
         bool needs = false;
         if (x0 < W && y < H) {
-            // exact shortcut: all in-window depths equal -> the normalised
-            // weighted sum is that depth (columns x0-R .. x0+3+R, valid rows)
-            const uint32_t c = tD[(ty + R) * kRowWords + 2 * qx + 2] & 0xFFFFu;
-            uint32_t bad = 0;
-            const uint32_t splat = c | (c << 16);
+            // exact shortcut: all in-window depths (columns x0-R .. x0+3+R,
+            // rows inside the image) equal -> the normalised weighted sum is
+            // that depth.  With blocks of 8 px or more the window's pixels
+            // inside the image lie in at most 2 x 2 blocks: when those are
+            // non-edge blocks of one region depth the window is uniform
+            // (four table reads); else the depths are compared pixel by pixel
+            uint32_t c = 0, bad = 1;
+            if (!f.depth_in && ks >= 3) {
+                const int bxa = max(x0 - R, 0) >> ks, bxb = min(x0 + 3 + R, W - 1) >> ks;
+                const int bya = max(y - R, 0) >> ks, byb = min(y + R, H - 1) >> ks;
+                const uint2 e00 = btab[(bya - by_lo) * bw + (bxa - bx_lo)], e01 = btab[(bya - by_lo) * bw + (bxb - bx_lo)];
+                const uint2 e10 = btab[(byb - by_lo) * bw + (bxa - bx_lo)], e11 = btab[(byb - by_lo) * bw + (bxb - bx_lo)];
+                c = e00.y;
+                bad = ((e00.x | e01.x | e10.x | e11.x) >> 24) | (e01.y ^ c) | (e10.y ^ c) | (e11.y ^ c);
+            }
+            if (bad) {
+                c = tD[(ty + R) * kRowWords + 2 * qx + 2] & 0xFFFFu;
+                bad = 0;
+                const uint32_t splat = c | (c << 16);
 #pragma unroll
-            for (int i = 0; i < S; ++i) {
-                const int yy = y + i - R;
-                if (yy < 0 || yy >= H) continue;
-                const int base = (ty + i) * kRowWords + 2 * qx;
+                for (int i = 0; i < S; ++i) {
+                    const int yy = y + i - R;
+                    if (yy < 0 || yy >= H) continue;
+                    const int base = (ty + i) * kRowWords + 2 * qx;
 #pragma unroll
-                for (int k = (4 - R) >> 1; k <= (7 + R) >> 1; ++k) {
-                    const uint32_t mask = ((2 * k >= 4 - R) ? 0xFFFFu : 0u) | ((2 * k + 1 <= 7 + R) ? 0xFFFF0000u : 0u);
-                    bad |= (tD[base + k] ^ splat) & mask;
+                    for (int k = (4 - R) >> 1; k <= (7 + R) >> 1; ++k) {
+                        const uint32_t mask = ((2 * k >= 4 - R) ? 0xFFFFu : 0u) | ((2 * k + 1 <= 7 + R) ? 0xFFFF0000u : 0u);
+                        bad |= (tD[base + k] ^ splat) & mask;
+                    }
                 }
             }
             if (!bad) {
