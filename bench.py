@@ -377,14 +377,26 @@ def main() -> int:
         ctx.synthesize(frames[i % len(frames)], out=outs, stream=stream, **params)
     torch.cuda.synchronize()
     pstereo_profile_collect(ctx.handle)  # clear
-    # the cost of an event record itself, from back-to-back event pairs on
-    # the same stream; subtracted from the event-bracketed stage durations
+    # what an event pair adds to the kernel it brackets, subtracted from the
+    # event-bracketed stage durations: a pair around one tiny kernel, less
+    # that kernel's share of a long back-to-back run of it (one pair around
+    # 256 launches)
+    tiny = torch.zeros(1, dtype=torch.int32, device=dev)
+    for _ in range(16):
+        tiny.fill_(1)
     pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(64)]
     for a, b in pairs:
         a.record(stream)
+        tiny.fill_(1)
         b.record(stream)
+    run0, run1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    run0.record(stream)
+    for _ in range(256):
+        tiny.fill_(1)
+    run1.record(stream)
     torch.cuda.synchronize()
-    ev_overhead_ms = statistics.median(a.elapsed_time(b) for a, b in pairs)
+    ev_overhead_ms = max(statistics.median(a.elapsed_time(b) for a, b in pairs) - run0.elapsed_time(run1) / 256,
+                         0.0)
 
     # per-stage HIP events on every `sample`-th timed step: each event record
     # adds a few microseconds of stream time, so recording them on every step
