@@ -588,20 +588,23 @@ __host__ __device__ constexpr size_t regions_lds_bytes_c(int nb) {
 
 // ---------------------------------------------------------------------------
 // Strip-parallel region grouping.  The same components and labels as
-// regions_body, computed in three launches:
+// regions_body, computed in two launches (plus a per-block pass on request):
 //   strips: one workgroup per strip of rstrip block rows (at most
 //     kStripBlocks blocks, two per lane) finds the strip-local components by
-//     union-find in LDS (a root is hooked under the smaller root, so every
-//     root is its component's smallest block), writes each block's
-//     strip-local label, and enters every non-edge component into a slot
-//     table: {label, block count} and its lowest block row + 1;
+//     union-find in LDS over horizontal runs of linked blocks (a root is
+//     hooked under the smaller root, so every root is its component's
+//     smallest block), enters every non-edge component into a slot table --
+//     {label, block count} and its lowest block row + 1 -- writes each
+//     block's {statistics, slot}, and lists the join candidates across the
+//     boundary above it;
 //   merge: one workgroup joins slots across strip boundaries (union-find over
 //     slots, again rooted at the smallest label), sums counts and takes the
 //     lowest row per merged component, picks the background and writes each
-//     slot's final label and depth.  With more than kRegionSlots slots it runs
-//     regions_body instead, for the whole frame;
-//   final: one lane per block turns its strip-local label into the final
-//     label and depth.
+//     slot's final label and depth.  With more than kRegionSlots slots it
+//     runs regions_body instead, for the whole frame;
+//   final (only for the per-block dump): one lane per block turns its slot
+//     into the final label and depth.  The depth filter resolves the depths
+//     it needs from the slot table itself.
 
 constexpr int kStripLanes = 1024;
 constexpr int kStripBlocks = 2048;
@@ -930,7 +933,7 @@ __device__ __forceinline__ void rg_merge_body(const FrameDesc& f, uint32_t* lds)
     }
 }
 
-// One block per lane: final label and depth from the strip-local label.
+// One block per lane: final label and depth from the block's slot.
 __device__ __forceinline__ void rg_final_block(const FrameDesc& f, int b) {
     const int gw = f.gw, gh = f.gh;
     if (b >= gw * gh || f.rctl[1]) return;

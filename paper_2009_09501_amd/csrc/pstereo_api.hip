@@ -459,7 +459,7 @@ int pstereo_debug_blocks(pstereo_ctx* c, uint32_t* stats, int32_t* labels, uint8
     (void)hipSetDevice(c->device);
     hipError_t e;
     if (!c->blocks_final) {
-        // turn the strip-local labels into final labels and depths
+        // turn the blocks' slots into final labels and depths
         if ((e = pstereo::launch(pstereo::spec_rg_final(c->last_fd), c->last_fd, c->last_stream)) != hipSuccess)
             return fail(c, PSTEREO_E_DEVICE, "block resolution launch: %s", hipGetErrorString(e));
         c->blocks_final = true;
