@@ -227,11 +227,17 @@ __global__ void __launch_bounds__(1024) k_mf_warp(const FrameDesc* frames, const
     if constexpr (Q < 4) {
         warp_rows<true, Q>(f, y0, min(y0 + rows, f.h), 1, threadIdx.x, blockDim.x, lds);
     } else {
+        // the LDS state prepared once (each row restores it); lane offsets
+        // recomputed per row rather than held across rows
+        warp_prepare(f, f.w, threadIdx.x, blockDim.x, lds);
+        __syncthreads();
+        WarpRowIn<true, Q> in, unused;
         for (int k = 0; k < rows; ++k) {
             const int y = y0 + k;
             if (y >= f.h) break;
-            if (k) __syncthreads();  // the previous row's last LDS reads are done
-            warp_row<true, Q>(f, y, threadIdx.x, blockDim.x, lds, true);
+            const int t = opaque((int)threadIdx.x);
+            warp_load<true, Q>(f, y, t, blockDim.x, in);
+            warp_row_body<true, Q>(f, y, t, blockDim.x, lds, true, in, -1, unused);
         }
     }
 }
