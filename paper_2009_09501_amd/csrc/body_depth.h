@@ -250,11 +250,6 @@ __device__ __forceinline__ uint32_t hook_prio(uint32_t x) {
     return x;
 }
 
-__device__ __forceinline__ int mean_l1(uint32_t s, uint32_t n) {
-    return iabs((int)(s & 255) - (int)(n & 255)) + iabs((int)((s >> 8) & 255) - (int)((n >> 8) & 255)) +
-           iabs((int)((s >> 16) & 255) - (int)((n >> 16) & 255));
-}
-
 // LDS index of block b in the parent array: one pad word every 32 blocks, so
 // the 64 lanes of a wave, each at its own run of 32 blocks, hit 64 distinct
 // banks instead of one.

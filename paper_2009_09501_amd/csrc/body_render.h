@@ -53,8 +53,6 @@ __host__ __device__ constexpr CbfWeightTable make_cbf_weights() {
 }
 __device__ const CbfWeightTable kCbfWeights = make_cbf_weights();
 
-__device__ __forceinline__ uint32_t byte_of(uint32_t w, int i) { return (w >> (8 * i)) & 255u; }
-
 // Depth -> (left offset, right offset) of the Fig. 3 rule with the rounding
 // reading: P = round(B*m/255), m = D when D > T (crossed) else 255 - D
 // (uncrossed); the left view moves by ceil(P/2), the right view by floor(P/2),

@@ -70,22 +70,6 @@ __device__ __forceinline__ void load_quad(const uint8_t* p, int n, int (&r)[4], 
     }
 }
 
-template <bool ALIGNED>
-__device__ __forceinline__ void store_quad(uint8_t* p, int n, const int (&r)[4], const int (&g)[4], const int (&b)[4]) {
-    if constexpr (ALIGNED) {
-        uint3 v;
-        v.x = r[0] | (g[0] << 8) | (b[0] << 16) | (r[1] << 24);
-        v.y = g[1] | (b[1] << 8) | (r[2] << 16) | (g[2] << 24);
-        v.z = b[2] | (r[3] << 8) | (g[3] << 16) | (b[3] << 24);
-        *reinterpret_cast<uint3*>(p) = v;
-    } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (j < n) { p[3 * j] = r[j]; p[3 * j + 1] = g[j]; p[3 * j + 2] = b[j]; }
-        }
-    }
-}
-
 constexpr size_t kMaxLds = 160 * 1024;
 
 // The value of v, opaque to the optimiser: indices derived from it are
