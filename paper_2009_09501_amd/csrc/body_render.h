@@ -740,12 +740,15 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
     // ---- forward warp of the row's pixels into both views; the key carries
     // the depth above the colour, so the atomic max keeps the nearer source
     // and its colour
+    // a target outside the row lands on a padding word (x in [W, W4]: the
+    // word of x = W4 is a spare one past the row), which nothing reads, so
+    // the atomics need no branch
     bool zero_key = false;
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
         const int x0 = 4 * (qi * NT + t);
         if (x0 >= W) continue;
-        const int n = min(4, W - x0);
+        const int n = ALIGNED ? 4 : min(4, W - x0);
         uint32_t c[4];
         if (ALIGNED) {
             quad_colours(make_uint3(in.c[3 * qi], in.c[3 * qi + 1], in.c[3 * qi + 2]), c);
@@ -757,16 +760,16 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
         *reinterpret_cast<uint32_t*>(drow_l + x0) = dq;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            if (j >= n) continue;
+            if (!ALIGNED && j >= n) continue;
             const int x = x0 + j;
             const uint32_t d = (dq >> (8 * j)) & 255u;
             const uint32_t lv = lut[d];
-            const int xl = x + (int)(int16_t)(lv & 0xFFFFu);
-            const int xr = x + (int)(int16_t)(lv >> 16);
+            const int xl = (int)min((unsigned)(x + (int)(int16_t)(lv & 0xFFFFu)), (unsigned)W4);
+            const int xr = (int)min((unsigned)(x + (int)(int16_t)(lv >> 16)), (unsigned)W4);
             const uint32_t key = (d << 24) | c[j];
             zero_key |= key == 0;
-            if ((unsigned)xl < (unsigned)W) atomicMax(&keyL[kidx(xl)], key);
-            if ((unsigned)xr < (unsigned)W) atomicMax(&keyR[kidx(xr)], key);
+            atomicMax(&keyL[kidx(xl)], key);
+            atomicMax(&keyR[kidx(xr)], key);
         }
     }
     if (__ballot(zero_key) && (t & 63) == 0) *ztag = (uint32_t)y + 1u;
@@ -785,13 +788,15 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
         const int x0 = 4 * (qi * NT + t);
+        // aligned rows hold whole quads only
+        const bool quad_in = x0 < W;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int x = x0 + j;
             const int i = 4 * qi + j;
             kl[i] = 0;
             kr[i] = 0;
-            if (x < W) {
+            if (ALIGNED ? quad_in : x < W) {
                 kl[i] = keyL[kidx(x)];
                 kr[i] = keyR[kidx(x)];
                 keyL[kidx(x)] = 0;
