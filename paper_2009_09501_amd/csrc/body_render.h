@@ -125,20 +125,23 @@ __device__ __forceinline__ void quad_depth_tab(const FrameDesc& f, int x0, int y
         for (int j = 0; j < 4; ++j) D[j] = own.y;
         return;
     }
-    // branch-free: per pixel the minimum of (distance << 12 | k << 8 |
+    // branch-free: per pixel the minimum of (distance << 16) + (k << 8 |
     // depth) over the candidates k in raster order (distance <= 765), so
-    // that ties go to the first; non-candidates contribute all ones
+    // that ties go to the first -- one v_sad_hi_u8 per candidate; a
+    // non-candidate adds kNone, which no candidate key reaches and no
+    // distance carries past 2^32
+    constexpr uint32_t kNone = 0xFC000000u;
     uint32_t best[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const uint2 c = tab[(by - by_lo + k / 3 - 1) * bw + (bx - bx_lo + k % 3 - 1)];
-        const uint32_t tag = (c.x >> 24) ? 0xFFFFFFFFu : (((uint32_t)k << 8) | c.y);
+        const uint32_t tag = (c.x >> 24) ? kNone : (((uint32_t)k << 8) | c.y);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) best[j] = min(best[j], (__builtin_amdgcn_sad_u8(col[j], c.x, 0u) << 12) | tag);
+        for (int j = 0; j < 4; ++j) best[j] = min(best[j], __builtin_amdgcn_sad_hi_u8(col[j], c.x, tag));
     }
     const uint32_t fallback = (uint32_t)ramp(by, f.gh);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) D[j] = best[j] == 0xFFFFFFFFu ? fallback : (best[j] & 255u);
+    for (int j = 0; j < 4; ++j) D[j] = best[j] >= kNone ? fallback : (best[j] & 255u);
 }
 
 // ---------------------------------------------------------------------------
