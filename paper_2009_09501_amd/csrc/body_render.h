@@ -490,6 +490,15 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
 // over all LDS banks.
 __device__ __forceinline__ int kidx(int x) { return x + (x >> 5); }
 
+// kidx(x) held as one value, so that the word address is formed from it in
+// one shift-add instead of the two shifted terms the optimiser distributes
+// it into.
+__device__ __forceinline__ int kidx_held(int x) {
+    int k = kidx(x);
+    asm("" : "+v"(k));
+    return k;
+}
+
 // Per-byte mean of two packed colours, rounded half up, with no carries
 // between bytes: (a | b) - ((a ^ b) >> 1) per byte.
 __device__ __forceinline__ uint32_t avg_bytes(uint32_t a, uint32_t b) {
@@ -774,8 +783,8 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
             const int xr = (int)min((unsigned)(x + (int)(int16_t)(lv >> 16)), (unsigned)W4);
             const uint32_t key = (d << 24) | c[j];
             zero_key |= key == 0;
-            atomicMax(&keyL[kidx(xl)], key);
-            atomicMax(&keyR[kidx(xr)], key);
+            atomicMax(&keyL[kidx_held(xl)], key);
+            atomicMax(&keyR[kidx_held(xr)], key);
         }
     }
     if (__ballot(zero_key) && (t & 63) == 0) *ztag = (uint32_t)y + 1u;
