@@ -490,6 +490,14 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
 // over all LDS banks.
 __device__ __forceinline__ int kidx(int x) { return x + (x >> 5); }
 
+// 1 if k != 0, else 0, as one v_min_u32 (the optimiser would turn min(k, 1)
+// back into a compare and a select through VCC).
+__device__ __forceinline__ uint32_t nonzero_bit(uint32_t k) {
+    uint32_t r;
+    asm("v_min_u32 %0, %1, 1" : "=v"(r) : "v"(k));
+    return r;
+}
+
 // kidx(x) held as one value, so that the word address is formed from it in
 // one shift-add instead of the two shifted terms the optimiser distributes
 // it into.
@@ -818,9 +826,13 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
                 keyR[kidx(x)] = 0;
                 own |= 1u << i;
             }
-            if (kl[i]) vL |= 1u << i;
-            if (kr[i]) vR |= 1u << i;
         }
+    }
+    // the valid bits once every read is out
+#pragma unroll
+    for (int i = 0; i < 4 * Q; ++i) {
+        vL |= nonzero_bit(kl[i]) << i;
+        vR |= nonzero_bit(kr[i]) << i;
     }
     if (*ztag == (uint32_t)y + 1u && __ballot((own & ~(vL & vR)) != 0)) {
         const uint32_t lv0 = lut[0];
