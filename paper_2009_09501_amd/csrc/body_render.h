@@ -690,17 +690,17 @@ __device__ __forceinline__ void fill_quad(uint32_t m, uint32_t own, const uint32
         if (has) rh |= 1u << j;
         if ((m >> j) & 1u) { run = k[j]; has = true; }
     }
+    // branch-free per pixel: an invalid pixel's key is 0, which is also its
+    // colour when neither side has a valid pixel
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        uint32_t v = k[j];
-        if (!((m >> j) & 1u)) {
-            const bool a = (lh >> j) & 1u, b = (rh >> j) & 1u;
-            const uint32_t ka = lk[j], kb = rk[j];
-            if (a && b) v = LEFT_TIES ? ((kb >> 24) < (ka >> 24) ? kb : ka) : ((ka >> 24) < (kb >> 24) ? ka : kb);
-            else if (a) v = ka;
-            else if (b) v = kb;
-            else if ((own >> j) & 1u) need |= 1u << j;
-        }
+        const bool valid = (m >> j) & 1u;
+        const bool a = (lh >> j) & 1u, b = (rh >> j) & 1u;
+        const uint32_t ka = lk[j], kb = rk[j];
+        const bool nearer_b = LEFT_TIES ? (kb >> 24) < (ka >> 24) : (kb >> 24) <= (ka >> 24);
+        const uint32_t fill = b && (!a || nearer_b) ? kb : (a ? ka : 0u);
+        const uint32_t v = valid ? k[j] : fill;
+        if (!valid && !a && !b && ((own >> j) & 1u)) need |= 1u << j;
         c[j] = v & 0xFFFFFFu;
     }
 }
