@@ -540,30 +540,40 @@ __device__ __forceinline__ void store_quad_views(const FrameDesc& f, int y, int 
     const int W = f.w;
     const int n = min(4, W - x0);
     const size_t off = ((size_t)y * W + x0) * 3;
+    // unaligned rows: byte stores of the quad's pixels inside the row
     auto store4 = [&](uint8_t* out, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
         if (!out) return;
-        if (ALIGNED) {
-            uint3 v;
-            v.x = perm(c1, c0, 0x04020100u);
-            v.y = perm(c2, c1, 0x05040201u);
-            v.z = perm(c3, c2, 0x06050402u);
-            *reinterpret_cast<uint3*>(out + off) = v;
-        } else {
-            const uint32_t c[4] = {c0, c1, c2, c3};
+        const uint32_t c[4] = {c0, c1, c2, c3};
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (j < n) {
-                    out[off + 3 * j] = (uint8_t)c[j];
-                    out[off + 3 * j + 1] = (uint8_t)(c[j] >> 8);
-                    out[off + 3 * j + 2] = (uint8_t)(c[j] >> 16);
-                }
+        for (int j = 0; j < 4; ++j) {
+            if (j < n) {
+                out[off + 3 * j] = (uint8_t)c[j];
+                out[off + 3 * j + 1] = (uint8_t)(c[j] >> 8);
+                out[off + 3 * j + 2] = (uint8_t)(c[j] >> 16);
             }
         }
     };
-    store4(f.out_l, cl[0], cl[1], cl[2], cl[3]);
-    store4(f.out_r, cr[0], cr[1], cr[2], cr[3]);
-    store4(f.out_a, (cl[0] & 0xFFu) | (cr[0] & 0xFFFF00u), (cl[1] & 0xFFu) | (cr[1] & 0xFFFF00u),
-           (cl[2] & 0xFFu) | (cr[2] & 0xFFFF00u), (cl[3] & 0xFFu) | (cr[3] & 0xFFFF00u));
+    if (ALIGNED) {
+        // both views packed once; in the three dwords of a quad the red bytes
+        // sit at fixed places, so the anaglyph is one bit-field insert per
+        // dword
+        const uint3 lp = make_uint3(perm(cl[1], cl[0], 0x04020100u), perm(cl[2], cl[1], 0x05040201u),
+                                    perm(cl[3], cl[2], 0x06050402u));
+        const uint3 rp = make_uint3(perm(cr[1], cr[0], 0x04020100u), perm(cr[2], cr[1], 0x05040201u),
+                                    perm(cr[3], cr[2], 0x06050402u));
+        if (f.out_l) *reinterpret_cast<uint3*>(f.out_l + off) = lp;
+        if (f.out_r) *reinterpret_cast<uint3*>(f.out_r + off) = rp;
+        if (f.out_a) {
+            constexpr uint32_t m0 = 0xFF0000FFu, m1 = 0x00FF0000u, m2 = 0x0000FF00u;
+            *reinterpret_cast<uint3*>(f.out_a + off) =
+                make_uint3((lp.x & m0) | (rp.x & ~m0), (lp.y & m1) | (rp.y & ~m1), (lp.z & m2) | (rp.z & ~m2));
+        }
+    } else {
+        store4(f.out_l, cl[0], cl[1], cl[2], cl[3]);
+        store4(f.out_r, cr[0], cr[1], cr[2], cr[3]);
+        store4(f.out_a, (cl[0] & 0xFFu) | (cr[0] & 0xFFFF00u), (cl[1] & 0xFFu) | (cr[1] & 0xFFFF00u),
+               (cl[2] & 0xFFu) | (cr[2] & 0xFFFF00u), (cl[3] & 0xFFu) | (cr[3] & 0xFFFF00u));
+    }
     if (f.out_h) {
         const int hw = W >> 1;
         const uint32_t l0 = avg_bytes(cl[0], cl[1]), l1 = avg_bytes(cl[2], cl[3]);
