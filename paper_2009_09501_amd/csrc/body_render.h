@@ -650,8 +650,10 @@ __device__ __forceinline__ void warp_load(const FrameDesc& f, int y, int t, int 
 }
 
 // The warp's standing LDS state for rows of width W: the shift table, and
-// both z-buffers zero (each row's validity pass zeroes what its scatter
-// wrote, so the state holds from row to row).  A barrier must follow before
+// both z-buffers zero.  Each row's validity pass zeroes the words of x < W;
+// the padding words past the row, where out-of-row targets land, are never
+// read at this width, so the state holds from row to row of one frame (rows
+// of another width need a fresh preparation).  A barrier must follow before
 // the first row.
 __device__ __forceinline__ void warp_prepare(const FrameDesc& f, int W, int t, int NT, uint32_t* lds) {
     const int KW = kidx((W + 3) & ~3) + 1;
