@@ -53,12 +53,14 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
     const int qx = t & 15, lr = t >> 4;
     const int tx0 = tile_x * 64, ty0 = tile_y * T::TH;
     const int x0 = tx0 + 4 * qx, y0 = ty0 + RPT * lr;
-    const int n = min(4, W - x0);
+    const int n = ALIGNED ? 4 : min(4, W - x0);  // aligned frames hold whole quads
     const uint32_t g = (uint32_t)f.g;
     if (!T::kInWave)
         for (int i = t; i < T::BC * T::BR * 4; i += 256) acc[i] = 0;
 
-    uint32_t sr = 0, sg = 0, sb = 0, edge = 0;
+    // edge: the block has a luma step above g; emax: the largest step seen
+    // by the aligned path (compared with g once at the end)
+    uint32_t sr = 0, sg = 0, sb = 0, edge = 0, emax = 0;
     uint32_t yq[RPT];     // packed luma bytes of the lane's quad, one word per row
     uint32_t ybelow = 0;  // the row below the tile (last lane row only)
     if (ALIGNED) {
@@ -102,7 +104,7 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
             const uint32_t Yn = x0 + 4 < W ? __builtin_amdgcn_udot4(nx[k], wlo, 128u, false) >> 8 : Y[3];  // no step past the last column
             const uint32_t hmax = max(max(__builtin_amdgcn_sad_u16(Y[1], Y[0], 0u), __builtin_amdgcn_sad_u16(Y[2], Y[1], 0u)),
                                       max(__builtin_amdgcn_sad_u16(Y[3], Y[2], 0u), __builtin_amdgcn_sad_u16(Yn, Y[3], 0u)));
-            if (hmax > g) edge = 1;
+            emax = max(emax, hmax);
             yq[k] = Y[0] | (Y[1] << 8) | (Y[2] << 16) | (Y[3] << 24);
         }
         if (lr == 15 && ty0 + T::TH < H && x0 < W) {
@@ -150,13 +152,12 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
         const int y = y0 + k;
         if (y + 1 < H && x0 < W) {
             const uint32_t below = k + 1 < RPT ? yq[k + 1] : below_last;
-            uint32_t vmax = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (j < n) vmax = max(vmax, __builtin_amdgcn_sad_u16((below >> (8 * j)) & 255u, (yq[k] >> (8 * j)) & 255u, 0u));
-            if (vmax > g) edge = 1;
+                if (j < n) emax = max(emax, __builtin_amdgcn_sad_u16((below >> (8 * j)) & 255u, (yq[k] >> (8 * j)) & 255u, 0u));
         }
     }
+    if (emax > g) edge = 1;
     const int bxl = qx / QB, byl = lr / LB;  // the lane's block in the tile
     if (T::kInWave) {
         // two 16-bit sums per register: a block holds K * K / 16 <= 16 lanes
