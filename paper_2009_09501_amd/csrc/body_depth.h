@@ -66,11 +66,15 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
     if (ALIGNED) {
         uint3 v[RPT + 1];
         uint32_t nx[RPT];
+        // the lane's quad in its first row; the next rows one uniform row
+        // stride apart
+        const uint8_t* p0 = f.frame + ((size_t)y0 * W + x0) * 3;
+        const size_t stride = (size_t)W * 3;
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
             const int y = y0 + k;
             if (y < H && x0 < W) {
-                const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
+                const uint8_t* p = p0 + k * stride;
                 v[k] = *reinterpret_cast<const uint3*>(p);
                 if (x0 + 4 < W) nx[k] = *reinterpret_cast<const uint32_t*>(p + 12);
             }

@@ -624,6 +624,9 @@ __device__ __forceinline__ void warp_load(const FrameDesc& f, int y, int t, int 
     constexpr int P = WarpRowIn<ALIGNED, Q>::kPerQuad;
     const int W = f.w;
     const uint8_t* drow = f.df + (size_t)y * W;
+    // the lane's first quad of the row; its next quads a uniform 12 NT bytes
+    // apart
+    const uint8_t* q0 = f.frame + ((size_t)y * W + 4 * t) * 3;
 #pragma unroll
     for (int qi = 0; qi < Q; ++qi) {
         const int x0 = 4 * (qi * NT + t);
@@ -632,7 +635,7 @@ __device__ __forceinline__ void warp_load(const FrameDesc& f, int y, int t, int 
         in.dq[qi] = 0;
         if (x0 >= W) continue;
         if (ALIGNED) {
-            const uint3 v = *reinterpret_cast<const uint3*>(f.frame + ((size_t)y * W + x0) * 3);
+            const uint3 v = *reinterpret_cast<const uint3*>(q0 + (size_t)qi * 12 * NT);
             in.c[P * qi] = v.x;
             in.c[P * qi + 1] = v.y;
             in.c[P * qi + 2] = v.z;
