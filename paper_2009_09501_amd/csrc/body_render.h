@@ -679,6 +679,20 @@ __device__ __forceinline__ uint32_t quad_extreme_key(uint32_t m, const uint32_t*
     return r;
 }
 
+// The key of the last (LAST) or first valid pixel of a wave's chunk, read
+// back from the view's z-buffer: any = ballot of the lanes whose quad holds a
+// valid pixel, m = the lane's quad mask, c0 = the chunk's first pixel; 0 when
+// the chunk has none.  Uniform: one lane's mask, one broadcast LDS read.
+template <bool LAST>
+__device__ __forceinline__ uint32_t chunk_extreme_key(unsigned long long any, uint32_t m, const uint32_t* key,
+                                                      int c0) {
+    if (!any) return 0u;
+    const int src = LAST ? 63 - __clzll(any) : __ffsll((long long)any) - 1;
+    const uint32_t ms = __builtin_amdgcn_readlane(m, src);
+    const int j = LAST ? 31 - __clz(ms) : __ffs(ms) - 1;
+    return key[kidx(c0 + 4 * src + j)];
+}
+
 // Hole fill of one view's quad: pixel j with valid bit clear takes the
 // nearer valid pixel on either side of the row, the smaller depth winning
 // and ties going left (LEFT_TIES, the left view) or right; with a valid
@@ -764,7 +778,8 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
                                               const WarpRowIn<ALIGNED, Q>& in, int next_y,
                                               WarpRowIn<ALIGNED, Q>& next) {
     const int W = active ? f.w : 0;
-    const int lane = t & 63, wave = t >> 6, NW = NT >> 6;
+    // wave: the same for all lanes of a wave (whole waves), held uniform
+    const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6), NW = NT >> 6;
     const int NC = Q * NW;  // chunks per row
     const int W4 = (W + 3) & ~3;
     const int KW = kidx(W4) + 1;
@@ -837,8 +852,6 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
             if (ALIGNED ? quad_in : x < W) {
                 kl[i] = keyL[kidx(x)];
                 kr[i] = keyR[kidx(x)];
-                keyL[kidx(x)] = 0;
-                keyR[kidx(x)] = 0;
                 own |= 1u << i;
             }
         }
@@ -849,6 +862,23 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
         vL |= nonzero_bit(kl[i]) << i;
         vR |= nonzero_bit(kr[i]) << i;
     }
+    // the lane's z-buffer words back to zero (after the chunk's extreme keys
+    // are read back below: the words of a chunk are this wave's alone, and
+    // its LDS accesses complete in order)
+    auto clear_own = [&]() {
+#pragma unroll
+        for (int qi = 0; qi < Q; ++qi) {
+            const int x0 = 4 * (qi * NT + t);
+            const bool quad_in = x0 < W;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (ALIGNED ? quad_in : x0 + j < W) {
+                    keyL[kidx(x0 + j)] = 0;
+                    keyR[kidx(x0 + j)] = 0;
+                }
+            }
+        }
+    };
     if (*ztag == (uint32_t)y + 1u && __ballot((own & ~(vL & vR)) != 0)) {
         const uint32_t lv0 = lut[0];
         const int o0[2] = {(int)(int16_t)(lv0 & 0xFFFFu), (int)(int16_t)(lv0 >> 16)};
@@ -892,6 +922,7 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
                 f.ipt[plane + o] = ((vR >> i) & 1u) ? 0 : 0xFFFF;
             }
         }
+        clear_own();
         __syncthreads();  // the z-buffers and the row depth are free again
         return;
     }
@@ -903,10 +934,11 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
         const uint32_t ql = (vL >> (4 * qi)) & 15u, qr = (vR >> (4 * qi)) & 15u;
         anyL[qi] = __ballot(ql != 0);
         anyR[qi] = __ballot(qr != 0);
-        const uint32_t a = __builtin_amdgcn_readlane(quad_extreme_key<true>(ql, &kl[4 * qi]), anyL[qi] ? 63 - __clzll(anyL[qi]) : 0);
-        const uint32_t b = __builtin_amdgcn_readlane(quad_extreme_key<false>(ql, &kl[4 * qi]), anyL[qi] ? __ffsll(anyL[qi]) - 1 : 0);
-        const uint32_t c = __builtin_amdgcn_readlane(quad_extreme_key<true>(qr, &kr[4 * qi]), anyR[qi] ? 63 - __clzll(anyR[qi]) : 0);
-        const uint32_t d = __builtin_amdgcn_readlane(quad_extreme_key<false>(qr, &kr[4 * qi]), anyR[qi] ? __ffsll(anyR[qi]) - 1 : 0);
+        const int c0 = 4 * (qi * NT + 64 * wave);  // the chunk's first pixel
+        const uint32_t a = chunk_extreme_key<true>(anyL[qi], ql, keyL, c0);
+        const uint32_t b = chunk_extreme_key<false>(anyL[qi], ql, keyL, c0);
+        const uint32_t c = chunk_extreme_key<true>(anyR[qi], qr, keyR, c0);
+        const uint32_t d = chunk_extreme_key<false>(anyR[qi], qr, keyR, c0);
         if (lane == 0) {
             uint32_t* p = pub + 8 * (qi * NW + wave);
             p[0] = a;
@@ -916,6 +948,7 @@ __device__ __forceinline__ void warp_row_body(const FrameDesc& f, int y, int t, 
             p[4] = (anyL[qi] ? 1u : 0u) | (anyR[qi] ? 2u : 0u);
         }
     }
+    clear_own();
     __syncthreads();
 
     // ---- hole filling from the nearest valid keys: inside the quad, in the
