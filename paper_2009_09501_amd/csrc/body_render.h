@@ -142,7 +142,12 @@ __device__ __forceinline__ void quad_depth_tab(const FrameDesc& f, int x0, int y
 #pragma unroll
         for (int j = 0; j < 4; ++j) best[j] = min(best[j], __builtin_amdgcn_sad_hi_u8(col[j], c.x, tag));
     }
-    const uint32_t fallback = (uint32_t)ramp(by, f.gh);
+    // the ramp of the block row only where a pixel found no candidate (rare)
+    bool none = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) none |= best[j] >= kNone;
+    uint32_t fallback = 0;
+    if (none) fallback = (uint32_t)ramp(by, f.gh);
 #pragma unroll
     for (int j = 0; j < 4; ++j) D[j] = best[j] >= kNone ? fallback : (best[j] & 255u);
 }
