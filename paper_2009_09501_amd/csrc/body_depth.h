@@ -35,6 +35,17 @@ struct BsTile {
     static constexpr int kLdsWords = 16 * 16 + (kInWave ? 0 : BC * BR * 4);
 };
 
+// Rounded mean sum / cnt of a block of cnt pixels, (sum + cnt / 2) / cnt: a
+// shift for a whole K x K block (cnt = K * K, a power of two), the division
+// only for blocks cut by the frame's right or bottom edge.
+template <int K>
+__device__ __forceinline__ uint32_t block_mean(uint32_t sum, uint32_t cnt) {
+    constexpr uint32_t kFull = (uint32_t)(K * K);
+    constexpr int kShift = __builtin_ctz(kFull);
+    if (cnt == kFull) return (sum + kFull / 2) >> kShift;
+    return (sum + cnt / 2) / cnt;
+}
+
 // One 64 x 64 tile (tile_x, tile_y) on 256 lanes t = 0..255 (a multiple of
 // four whole waves): lane t takes quad t % 16 of the four consecutive rows
 // from 4 (t / 16), all four rows' loads in flight together, and sums them in
@@ -180,9 +191,9 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
         const int bx = tile_x * T::BC + bxl, by = tile_y * T::BR + byl;
         if (active && qx % QB == 0 && lr % LB == 0 && bx < f.gw && by < f.gh) {
             const uint32_t cnt = (uint32_t)((min(bx * K + K, W) - bx * K) * (min(by * K + K, H) - by * K));
-            const uint32_t mr = ((rg & 0xFFFFu) + cnt / 2) / cnt;
-            const uint32_t mg = ((rg >> 16) + cnt / 2) / cnt;
-            const uint32_t mb = ((be & 0xFFFFu) + cnt / 2) / cnt;
+            const uint32_t mr = block_mean<K>((rg & 0xFFFFu), cnt);
+            const uint32_t mg = block_mean<K>((rg >> 16), cnt);
+            const uint32_t mb = block_mean<K>((be & 0xFFFFu), cnt);
             f.stats[by * f.gw + bx] = mr | (mg << 8) | (mb << 16) | ((be >> 16) ? 1u << 24 : 0u);
         }
     } else {
@@ -213,9 +224,9 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
             const int bx = tile_x * T::BC + i % T::BC, by = tile_y * T::BR + i / T::BC;
             if (active && bx < f.gw && by < f.gh) {
                 const uint32_t cnt = (uint32_t)((min(bx * K + K, W) - bx * K) * (min(by * K + K, H) - by * K));
-                const uint32_t mr = (acc[4 * i + 0] + cnt / 2) / cnt;
-                const uint32_t mg = (acc[4 * i + 1] + cnt / 2) / cnt;
-                const uint32_t mb = (acc[4 * i + 2] + cnt / 2) / cnt;
+                const uint32_t mr = block_mean<K>(acc[4 * i + 0], cnt);
+                const uint32_t mg = block_mean<K>(acc[4 * i + 1], cnt);
+                const uint32_t mb = block_mean<K>(acc[4 * i + 2], cnt);
                 f.stats[by * f.gw + bx] = mr | (mg << 8) | (mb << 16) | (acc[4 * i + 3] << 24);
             }
         }
