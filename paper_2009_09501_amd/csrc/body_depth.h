@@ -711,12 +711,26 @@ __device__ __forceinline__ void rg_strip_body(const FrameDesc& f, int strip, uin
     }
     __syncthreads();
     // the start of block i's run: the last start bit at or before i (every
-    // row's first block is one)
+    // row's first block is one).  Each wave keeps, in its own slice of the
+    // row array (unused until the counts), the last start at or before the
+    // end of every 32-block word (a max-scan over the words, n <= 2048), so a
+    // lookup reads at most two words
+    uint32_t* lastw = row + 64 * (t >> 6);
+    {
+        const int w = t & 63;
+        const uint32_t word = w < ((n + 31) >> 5) ? starts[w] : 0u;
+        int v = word ? w * 32 + 31 - __clz(word) : -1;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(v, o);
+            if (w >= o) v = max(v, u);
+        }
+        lastw[w] = (uint32_t)v;
+    }
     auto run_of = [&](int i) -> uint32_t {
-        int w = i >> 5;
-        uint32_t m = starts[w] & ((((uint32_t)1u << (i & 31)) << 1) - 1u);
-        while (!m) m = starts[--w];
-        return (uint32_t)(w * 32 + 31 - __clz(m));
+        const int w = i >> 5;
+        const uint32_t m = starts[w] & ((((uint32_t)1u << (i & 31)) << 1) - 1u);
+        return m ? (uint32_t)(w * 32 + 31 - __clz(m)) : lastw[w - 1];
     };
 
     // unions between runs along the down links inside the strip, one per
