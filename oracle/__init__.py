@@ -20,7 +20,7 @@ import numpy as np
 
 from .build import LIB_PATH, build_oracle
 
-__all__ = ["OracleResult", "synthesize", "auto_block", "disparity_lut",
+__all__ = ["OracleResult", "synthesize", "synthesize_views", "synthesize_views_mt", "auto_block", "disparity_lut",
            "weight_tables", "luma", "hsbs", "gather", "synthesize_gather", "inpaint_blocks",
            "synthesize_inpaint", "load", "build_oracle"]
 
@@ -46,6 +46,11 @@ def load():
         _u8p, _u8p, _u8p, _u8p,
         _u8p, _u32p, _i32p, _u8p, _u8p, _u8p,
         _i32p, _i32p, _i32p, _i32p]
+    lib.oracle_synthesize_mt.restype = ctypes.c_int
+    lib.oracle_synthesize_mt.argtypes = [
+        _u8p, ctypes.c_int, ctypes.c_int,
+        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+        _u8p, _u8p, _u8p, ctypes.c_int]
     lib.oracle_auto_block.restype = ctypes.c_int
     lib.oracle_auto_block.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.oracle_disparity_lut.restype = None
@@ -150,6 +155,23 @@ def synthesize_views(frame: np.ndarray, B: int, **kw):
         _p(None, _i32p), _p(None, _i32p), _p(None, _i32p), _p(None, _i32p))
     if rc != 0:
         raise ValueError(f"oracle_synthesize failed with code {rc}")
+    return L, R, A
+
+
+def synthesize_views_mt(frame: np.ndarray, B: int, nthreads: int, **kw):
+    """(L, R, A) with the row-independent stages split over ``nthreads``
+    threads (the CPU baseline's row-parallel mode); equal to
+    synthesize_views for any thread count."""
+    lib = load()
+    frame = np.ascontiguousarray(frame, dtype=np.uint8)
+    h, w, _ = frame.shape
+    K = kw.get("K", 0) or lib.oracle_auto_block(w, h)
+    L, R, A = (np.empty((h, w, 3), np.uint8) for _ in range(3))
+    rc = lib.oracle_synthesize_mt(
+        _p(frame, _u8p), w, h, B, kw.get("T", 150), K, kw.get("g", 24),
+        kw.get("tau", 24), kw.get("r", 2), _p(L, _u8p), _p(R, _u8p), _p(A, _u8p), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle_synthesize_mt failed with code {rc}")
     return L, R, A
 
 

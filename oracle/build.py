@@ -1,4 +1,5 @@
-"""Build step of the CPU oracle: gcc -O2, plain C, no SIMD intrinsics."""
+"""Build step of the CPU oracle: gcc -O2, plain C, no SIMD intrinsics (pthreads
+only for the row-parallel timing mode)."""
 from __future__ import annotations
 
 import os
@@ -12,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 def build_oracle(verbose: bool = False) -> str:
     """Compile ``oracle.c`` into ``liboracle.so`` beside it; returns the path."""
     tmp = LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra",
            "-o", tmp, SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

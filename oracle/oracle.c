@@ -22,6 +22,7 @@
  * cross-bilateral weight tables from exp() in double precision.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -106,15 +107,227 @@ void oracle_disparity_lut(int B, int T, int32_t *P_out, int32_t *oL_out, int32_t
     }
 }
 
+/* ------------------------------------------------- row-range stages */
+/* The row-independent stages below each take a half-open range of image rows
+ * [y0, y1); the driver runs them over all rows, either in one call or split
+ * into row bands on several threads (the CPU baseline's row-parallel mode).
+ * A band's result does not depend on how the rows are split. */
+
+/* O1: luma of every pixel of rows y0..y1-1. */
+static void orc_luma_rows(const uint8_t *frame, int w, int y0, int y1, uint8_t *Y) {
+    for (int64_t i = (int64_t)y0 * w; i < (int64_t)y1 * w; i++)
+        Y[i] = (uint8_t)orc_luma(frame[3 * i], frame[3 * i + 1], frame[3 * i + 2]);
+}
+
+#define RAMP(row) (gh > 1 ? (255 * (row) + (gh - 1) / 2) / (gh - 1) : 0)
+
+/* O8: pixel depth.  Non-edge block: its region depth.  Edge block: the
+ * region depth of the non-edge block among the 3x3 neighbours whose mean
+ * colour is nearest (L1) to the pixel, first strict minimum in raster order;
+ * with no candidate, the ramp of the block row. */
+static void orc_depth_rows(const uint8_t *frame, int w, int K, int gw, int gh, const uint32_t *stats,
+                           const uint8_t *dblk, int y0, int y1, uint8_t *D0) {
+    for (int y = y0; y < y1; y++) {
+        for (int x = 0; x < w; x++) {
+            int64_t i = (int64_t)y * w + x;
+            int bx = x / K, by = y / K, b = by * gw + bx;
+            if (!(stats[b] >> 24)) { D0[i] = dblk[b]; continue; }
+            int best = -1, bestd = 0;
+            for (int dy = -1; dy <= 1; dy++) {
+                for (int dx = -1; dx <= 1; dx++) {
+                    int cx = bx + dx, cy = by + dy;
+                    if (cx < 0 || cx >= gw || cy < 0 || cy >= gh) continue;
+                    uint32_t sc = stats[cy * gw + cx];
+                    if (sc >> 24) continue;
+                    int d = 0;
+                    for (int c = 0; c < 3; c++)
+                        d += abs((int)frame[3 * i + c] - (int)((sc >> (8 * c)) & 255));
+                    if (best < 0 || d < bestd) { best = cy * gw + cx; bestd = d; }
+                }
+            }
+            D0[i] = best >= 0 ? dblk[best] : (uint8_t)RAMP(by);
+        }
+    }
+}
+
+/* O9: cross-bilateral filter of the depth map guided by luma: window
+ * (2r+1)^2 clipped to the image, weight ws[dx^2+dy^2] * wr[|Y(q)-Y(p)|],
+ * normalised sum rounded half up. */
+static void orc_cbf_rows(const uint8_t *Y, const uint8_t *D0, int w, int h, int r, int y0, int y1,
+                         uint8_t *Df) {
+    for (int y = y0; y < y1; y++) {
+        for (int x = 0; x < w; x++) {
+            int64_t i = (int64_t)y * w + x;
+            uint64_t acc = 0, wsum = 0;
+            for (int dy = -r; dy <= r; dy++) {
+                for (int dx = -r; dx <= r; dx++) {
+                    int qx = x + dx, qy = y + dy;
+                    if (qx < 0 || qx >= w || qy < 0 || qy >= h) continue;
+                    int64_t q = (int64_t)qy * w + qx;
+                    uint64_t wt = (uint64_t)orc_ws[dx * dx + dy * dy] * (uint64_t)orc_wr[abs((int)Y[q] - (int)Y[i])];
+                    acc += wt * D0[q];
+                    wsum += wt;
+                }
+            }
+            Df[i] = (uint8_t)((acc + wsum / 2) / wsum);
+        }
+    }
+}
+
+/* O11 + O12 for one view over rows y0..y1-1; key and pick are w-entry
+ * work rows of the caller. */
+static void orc_view_rows(const uint8_t *frame, const uint8_t *Df, int w, int view, const int32_t *off,
+                          int y0, int y1, uint32_t *key, int32_t *pick, uint8_t *V, int32_t *dw,
+                          int32_t *ds) {
+    for (int y = y0; y < y1; y++) {
+        const int64_t row = (int64_t)y * w;
+        /* O11: forward warp of every source pixel of the row to
+         * x + offset(depth); at a collision the nearer source (larger
+         * depth) wins, then the larger source x.  This is the left / right
+         * frame reconstruction (Section 4, Fig. 3 code) written as a
+         * z-buffered scatter instead of a gather at the destination's
+         * depth. */
+        for (int x = 0; x < w; x++) key[x] = 0;
+        for (int x = 0; x < w; x++) {
+            int d = Df[row + x];
+            int xd = x + off[d];
+            if (xd < 0 || xd >= w) continue;
+            uint32_t k = (1u << 24) | ((uint32_t)d << 16) | (uint32_t)x;
+            if (k > key[xd]) key[xd] = k;
+        }
+        /* O12: inpainting of holes (Section 3: post-processed frames;
+         * Section 4: GPU inpainting).  A hole copies the nearer valid
+         * pixel of the warped row on its left or right: the one with the
+         * smaller depth (background); equal depths go left in the left
+         * view and right in the right view; a row with no valid pixel
+         * copies the source row, as the Fig. 3 code does for an
+         * out-of-range shift.  Fill colours come from the warped row
+         * before filling. */
+        for (int xd = 0; xd < w; xd++) {
+            if (key[xd]) { pick[xd] = (int32_t)(key[xd] & 0xFFFF); continue; }
+            int xl = -1, xr = -1;
+            for (int j = xd - 1; j >= 0; j--) if (key[j]) { xl = j; break; }
+            for (int j = xd + 1; j < w; j++) if (key[j]) { xr = j; break; }
+            int chosen;
+            if (xl >= 0 && xr >= 0) {
+                int dl = (key[xl] >> 16) & 255, dr = (key[xr] >> 16) & 255;
+                if (dl < dr) chosen = xl;
+                else if (dr < dl) chosen = xr;
+                else chosen = view == 0 ? xl : xr;
+                pick[xd] = (int32_t)(key[chosen] & 0xFFFF);
+            } else if (xl >= 0) {
+                pick[xd] = (int32_t)(key[xl] & 0xFFFF);
+            } else if (xr >= 0) {
+                pick[xd] = (int32_t)(key[xr] & 0xFFFF);
+            } else {
+                pick[xd] = xd;
+            }
+        }
+        for (int xd = 0; xd < w; xd++) {
+            int64_t src = row + pick[xd];
+            for (int c = 0; c < 3; c++) V[3 * (row + xd) + c] = frame[3 * src + c];
+            if (dw) dw[row + xd] = key[xd] ? (int32_t)(key[xd] & 0xFFFF) : -1;
+            if (ds) ds[row + xd] = pick[xd];
+        }
+    }
+}
+
+/* O13: red-cyan anaglyph of rows y0..y1-1: red from the left view, green
+ * and blue from the right view (Fig. 3 code: res from the left and right
+ * reconstructions); the views copied out beside it. */
+static void orc_compose_rows(const uint8_t *Lv, const uint8_t *Rv, int w, int y0, int y1, uint8_t *out_L,
+                             uint8_t *out_R, uint8_t *out_A) {
+    for (int64_t i = (int64_t)y0 * w; i < (int64_t)y1 * w; i++) {
+        if (out_L) for (int c = 0; c < 3; c++) out_L[3 * i + c] = Lv[3 * i + c];
+        if (out_R) for (int c = 0; c < 3; c++) out_R[3 * i + c] = Rv[3 * i + c];
+        if (out_A) {
+            out_A[3 * i + 0] = Lv[3 * i + 0];
+            out_A[3 * i + 1] = Rv[3 * i + 1];
+            out_A[3 * i + 2] = Rv[3 * i + 2];
+        }
+    }
+}
+#undef RAMP
+
+/* One row-parallel stage: which stage, its arguments, and the band of rows of
+ * one thread. */
+typedef struct {
+    int stage;  /* 1 luma, 8 pixel depth, 9 filter, 11 views + anaglyph */
+    const uint8_t *frame;
+    int w, h, K, gw, gh, r;
+    const uint32_t *stats;
+    const uint8_t *dblk;
+    uint8_t *Y, *D0, *Df, *Lv, *Rv;
+    const int32_t *offL, *offR;
+    int32_t *dwL, *dwR, *dsL, *dsR;
+    uint8_t *out_L, *out_R, *out_A;
+    uint32_t *key;
+    int32_t *pick;
+    int y0, y1;
+} orc_band;
+
+static void *orc_band_run(void *arg) {
+    orc_band *b = (orc_band *)arg;
+    switch (b->stage) {
+    case 1: orc_luma_rows(b->frame, b->w, b->y0, b->y1, b->Y); break;
+    case 8: orc_depth_rows(b->frame, b->w, b->K, b->gw, b->gh, b->stats, b->dblk, b->y0, b->y1, b->D0); break;
+    case 9: orc_cbf_rows(b->Y, b->D0, b->w, b->h, b->r, b->y0, b->y1, b->Df); break;
+    case 11:
+        orc_view_rows(b->frame, b->Df, b->w, 0, b->offL, b->y0, b->y1, b->key, b->pick, b->Lv, b->dwL, b->dsL);
+        orc_view_rows(b->frame, b->Df, b->w, 1, b->offR, b->y0, b->y1, b->key, b->pick, b->Rv, b->dwR, b->dsR);
+        orc_compose_rows(b->Lv, b->Rv, b->w, b->y0, b->y1, b->out_L, b->out_R, b->out_A);
+        break;
+    }
+    return NULL;
+}
+
+/* Run one stage over all rows: in the calling thread (nthreads <= 1), or in
+ * nthreads contiguous row bands, each on its own thread.  Returns 0, or
+ * ORC_E_NOMEM if a thread or its work rows could not be created. */
+static int orc_rows(orc_band proto, int nthreads) {
+    if (nthreads > proto.h) nthreads = proto.h;
+    if (nthreads <= 1) {
+        proto.y0 = 0;
+        proto.y1 = proto.h;
+        orc_band_run(&proto);
+        return ORC_OK;
+    }
+    orc_band *bands = calloc((size_t)nthreads, sizeof(orc_band));
+    pthread_t *tid = calloc((size_t)nthreads, sizeof(pthread_t));
+    int *started = calloc((size_t)nthreads, sizeof(int));
+    int rc = (bands && tid && started) ? ORC_OK : ORC_E_NOMEM;
+    for (int t = 0; rc == ORC_OK && t < nthreads; t++) {
+        bands[t] = proto;
+        bands[t].y0 = (int)((int64_t)proto.h * t / nthreads);
+        bands[t].y1 = (int)((int64_t)proto.h * (t + 1) / nthreads);
+        bands[t].key = NULL;
+        bands[t].pick = NULL;
+        if (proto.stage == 11) {
+            bands[t].key = malloc(sizeof(uint32_t) * proto.w);
+            bands[t].pick = malloc(sizeof(int32_t) * proto.w);
+            if (!bands[t].key || !bands[t].pick) { rc = ORC_E_NOMEM; break; }
+        }
+        if (pthread_create(&tid[t], NULL, orc_band_run, &bands[t]) != 0) { rc = ORC_E_NOMEM; break; }
+        started[t] = 1;
+    }
+    for (int t = 0; t < nthreads; t++)
+        if (started && started[t]) pthread_join(tid[t], NULL);
+    for (int t = 0; bands && t < nthreads; t++) { free(bands[t].key); free(bands[t].pick); }
+    free(bands);
+    free(tid);
+    free(started);
+    return rc;
+}
+
 /* -------------------------------------------------------------- driver */
-int oracle_synthesize(const uint8_t *frame, int w, int h,
-                      int B, int T, int K, int g, int tau, int r,
-                      const uint8_t *depth_in,
-                      uint8_t *out_L, uint8_t *out_R, uint8_t *out_A,
-                      uint8_t *dump_Y, uint32_t *dump_stats, int32_t *dump_labels,
-                      uint8_t *dump_dblk, uint8_t *dump_D0, uint8_t *dump_Df,
-                      int32_t *dump_warpL, int32_t *dump_warpR,
-                      int32_t *dump_srcL, int32_t *dump_srcR) {
+static int orc_synthesize(const uint8_t *frame, int w, int h,
+                          int B, int T, int K, int g, int tau, int r,
+                          const uint8_t *depth_in,
+                          uint8_t *out_L, uint8_t *out_R, uint8_t *out_A,
+                          uint8_t *dump_Y, uint32_t *dump_stats, int32_t *dump_labels,
+                          uint8_t *dump_dblk, uint8_t *dump_D0, uint8_t *dump_Df,
+                          int32_t *dump_warpL, int32_t *dump_warpR,
+                          int32_t *dump_srcL, int32_t *dump_srcR, int nthreads) {
     if (!frame || w < 1 || h < 1 || w > 65535 || h > 65535) return ORC_E_INVALID;
     if (B < 0 || B > 255 || T < -1 || T > 255 || r < 0 || r > ORC_MAX_RADIUS) return ORC_E_INVALID;
     if (g < 0 || g > 255 || tau < 0 || tau > 765) return ORC_E_INVALID;
@@ -139,9 +352,26 @@ int oracle_synthesize(const uint8_t *frame, int w, int h,
     int rc = ORC_OK;
     if (!ok) { rc = ORC_E_NOMEM; goto done; }
 
+    orc_band band;
+    memset(&band, 0, sizeof band);
+    band.frame = frame;
+    band.w = w;
+    band.h = h;
+    band.K = K;
+    band.gw = gw;
+    band.gh = gh;
+    band.r = r;
+    band.stats = stats;
+    band.dblk = dblk;
+    band.Y = Y;
+    band.D0 = D0;
+    band.Df = Df;
+    band.Lv = Lv;
+    band.Rv = Rv;
+
     /* O1: luma of every pixel. */
-    for (int64_t i = 0; i < npx; i++)
-        Y[i] = (uint8_t)orc_luma(frame[3 * i], frame[3 * i + 1], frame[3 * i + 2]);
+    band.stage = 1;
+    if ((rc = orc_rows(band, nthreads)) != ORC_OK) goto done;
 
     /* ramp h(row): top of the frame far (0), bottom near (255); larger depth
      * value = nearer, as the Fig. 3 code sends D > 150 to the crossed shift. */
@@ -240,129 +470,35 @@ int oracle_synthesize(const uint8_t *frame, int w, int h,
             else dblk[b] = (uint8_t)RAMP(rmax[lab[b]]);
         }
 
-        /* O8: pixel depth.  Non-edge block: its region depth.  Edge block:
-         * the region depth of the non-edge block among the 3x3 neighbours
-         * whose mean colour is nearest (L1) to the pixel, first strict minimum
-         * in raster order; with no candidate, the ramp of the block row. */
-        for (int y = 0; y < h; y++) {
-            for (int x = 0; x < w; x++) {
-                int64_t i = (int64_t)y * w + x;
-                int bx = x / K, by = y / K, b = by * gw + bx;
-                if (!(stats[b] >> 24)) { D0[i] = dblk[b]; continue; }
-                int best = -1, bestd = 0;
-                for (int dy = -1; dy <= 1; dy++) {
-                    for (int dx = -1; dx <= 1; dx++) {
-                        int cx = bx + dx, cy = by + dy;
-                        if (cx < 0 || cx >= gw || cy < 0 || cy >= gh) continue;
-                        uint32_t sc = stats[cy * gw + cx];
-                        if (sc >> 24) continue;
-                        int d = 0;
-                        for (int c = 0; c < 3; c++)
-                            d += abs((int)frame[3 * i + c] - (int)((sc >> (8 * c)) & 255));
-                        if (best < 0 || d < bestd) { best = cy * gw + cx; bestd = d; }
-                    }
-                }
-                D0[i] = best >= 0 ? dblk[best] : (uint8_t)RAMP(by);
-            }
-        }
+        /* O8: pixel depth (orc_depth_rows). */
+        band.stage = 8;
+        if ((rc = orc_rows(band, nthreads)) != ORC_OK) goto done;
     }
 #undef RAMP
 
-    /* O9: cross-bilateral filter of the depth map guided by luma: window
-     * (2r+1)^2 clipped to the image, weight ws[dx^2+dy^2] * wr[|Y(q)-Y(p)|],
-     * normalised sum rounded half up. */
-    for (int y = 0; y < h; y++) {
-        for (int x = 0; x < w; x++) {
-            int64_t i = (int64_t)y * w + x;
-            uint64_t acc = 0, wsum = 0;
-            for (int dy = -r; dy <= r; dy++) {
-                for (int dx = -r; dx <= r; dx++) {
-                    int qx = x + dx, qy = y + dy;
-                    if (qx < 0 || qx >= w || qy < 0 || qy >= h) continue;
-                    int64_t q = (int64_t)qy * w + qx;
-                    uint64_t wt = (uint64_t)orc_ws[dx * dx + dy * dy] * (uint64_t)orc_wr[abs((int)Y[q] - (int)Y[i])];
-                    acc += wt * D0[q];
-                    wsum += wt;
-                }
-            }
-            Df[i] = (uint8_t)((acc + wsum / 2) / wsum);
-        }
-    }
+    /* O9: cross-bilateral filter (orc_cbf_rows). */
+    band.stage = 9;
+    if ((rc = orc_rows(band, nthreads)) != ORC_OK) goto done;
 
     /* O10: depth -> per-view offsets. */
     int32_t lutP[256], lutL[256], lutR[256];
     oracle_disparity_lut(B, T, lutP, lutL, lutR);
 
-    /* O11 + O12, per view and per row. */
-    for (int view = 0; view < 2; view++) {
-        const int32_t *off = view == 0 ? lutL : lutR;
-        uint8_t *V = view == 0 ? Lv : Rv;
-        int32_t *dw = view == 0 ? dump_warpL : dump_warpR;
-        int32_t *ds = view == 0 ? dump_srcL : dump_srcR;
-        for (int y = 0; y < h; y++) {
-            const int64_t row = (int64_t)y * w;
-            /* O11: forward warp of every source pixel of the row to
-             * x + offset(depth); at a collision the nearer source (larger
-             * depth) wins, then the larger source x.  This is the left / right
-             * frame reconstruction (Section 4, Fig. 3 code) written as a
-             * z-buffered scatter instead of a gather at the destination's
-             * depth. */
-            for (int x = 0; x < w; x++) key[x] = 0;
-            for (int x = 0; x < w; x++) {
-                int d = Df[row + x];
-                int xd = x + off[d];
-                if (xd < 0 || xd >= w) continue;
-                uint32_t k = (1u << 24) | ((uint32_t)d << 16) | (uint32_t)x;
-                if (k > key[xd]) key[xd] = k;
-            }
-            /* O12: inpainting of holes (Section 3: post-processed frames;
-             * Section 4: GPU inpainting).  A hole copies the nearer valid
-             * pixel of the warped row on its left or right: the one with the
-             * smaller depth (background); equal depths go left in the left
-             * view and right in the right view; a row with no valid pixel
-             * copies the source row, as the Fig. 3 code does for an
-             * out-of-range shift.  Fill colours come from the warped row
-             * before filling. */
-            for (int xd = 0; xd < w; xd++) {
-                if (key[xd]) { pick[xd] = (int32_t)(key[xd] & 0xFFFF); continue; }
-                int xl = -1, xr = -1;
-                for (int j = xd - 1; j >= 0; j--) if (key[j]) { xl = j; break; }
-                for (int j = xd + 1; j < w; j++) if (key[j]) { xr = j; break; }
-                int chosen;
-                if (xl >= 0 && xr >= 0) {
-                    int dl = (key[xl] >> 16) & 255, dr = (key[xr] >> 16) & 255;
-                    if (dl < dr) chosen = xl;
-                    else if (dr < dl) chosen = xr;
-                    else chosen = view == 0 ? xl : xr;
-                    pick[xd] = (int32_t)(key[chosen] & 0xFFFF);
-                } else if (xl >= 0) {
-                    pick[xd] = (int32_t)(key[xl] & 0xFFFF);
-                } else if (xr >= 0) {
-                    pick[xd] = (int32_t)(key[xr] & 0xFFFF);
-                } else {
-                    pick[xd] = xd;
-                }
-            }
-            for (int xd = 0; xd < w; xd++) {
-                int64_t src = row + pick[xd];
-                for (int c = 0; c < 3; c++) V[3 * (row + xd) + c] = frame[3 * src + c];
-                if (dw) dw[row + xd] = key[xd] ? (int32_t)(key[xd] & 0xFFFF) : -1;
-                if (ds) ds[row + xd] = pick[xd];
-            }
-        }
-    }
-
-    /* O13: red-cyan anaglyph: red from the left view, green and blue from the
-     * right view (Fig. 3 code: res from the left and right reconstructions). */
-    for (int64_t i = 0; i < npx; i++) {
-        if (out_L) for (int c = 0; c < 3; c++) out_L[3 * i + c] = Lv[3 * i + c];
-        if (out_R) for (int c = 0; c < 3; c++) out_R[3 * i + c] = Rv[3 * i + c];
-        if (out_A) {
-            out_A[3 * i + 0] = Lv[3 * i + 0];
-            out_A[3 * i + 1] = Rv[3 * i + 1];
-            out_A[3 * i + 2] = Rv[3 * i + 2];
-        }
-    }
+    /* O11 + O12 per view, then O13, row by row (orc_view_rows,
+     * orc_compose_rows). */
+    band.stage = 11;
+    band.offL = lutL;
+    band.offR = lutR;
+    band.dwL = dump_warpL;
+    band.dwR = dump_warpR;
+    band.dsL = dump_srcL;
+    band.dsR = dump_srcR;
+    band.out_L = out_L;
+    band.out_R = out_R;
+    band.out_A = out_A;
+    band.key = key;
+    band.pick = pick;
+    if ((rc = orc_rows(band, nthreads)) != ORC_OK) goto done;
 
     if (dump_Y) memcpy(dump_Y, Y, npx);
     if (dump_D0) memcpy(dump_D0, D0, npx);
@@ -376,6 +512,28 @@ done:
     free(linkR); free(linkD); free(cnt); free(rmax); free(key); free(pick);
     free(Lv); free(Rv);
     return rc;
+}
+
+int oracle_synthesize(const uint8_t *frame, int w, int h,
+                      int B, int T, int K, int g, int tau, int r,
+                      const uint8_t *depth_in,
+                      uint8_t *out_L, uint8_t *out_R, uint8_t *out_A,
+                      uint8_t *dump_Y, uint32_t *dump_stats, int32_t *dump_labels,
+                      uint8_t *dump_dblk, uint8_t *dump_D0, uint8_t *dump_Df,
+                      int32_t *dump_warpL, int32_t *dump_warpR,
+                      int32_t *dump_srcL, int32_t *dump_srcR) {
+    return orc_synthesize(frame, w, h, B, T, K, g, tau, r, depth_in, out_L, out_R, out_A, dump_Y, dump_stats,
+                          dump_labels, dump_dblk, dump_D0, dump_Df, dump_warpL, dump_warpR, dump_srcL, dump_srcR, 1);
+}
+
+/* The same pipeline with its row-independent stages (O1, O8, O9, O11-O13)
+ * split into nthreads row bands on as many threads; the block stages O2-O7
+ * stay on the calling thread.  Outputs only (the CPU baseline's row-parallel
+ * mode); they equal oracle_synthesize's for any nthreads. */
+int oracle_synthesize_mt(const uint8_t *frame, int w, int h, int B, int T, int K, int g, int tau, int r,
+                         uint8_t *out_L, uint8_t *out_R, uint8_t *out_A, int nthreads) {
+    return orc_synthesize(frame, w, h, B, T, K, g, tau, r, NULL, out_L, out_R, out_A, NULL, NULL, NULL, NULL, NULL,
+                          NULL, NULL, NULL, NULL, NULL, nthreads < 1 ? 1 : nthreads);
 }
 
 /* ---------------------------------------------------------- HSBS output */

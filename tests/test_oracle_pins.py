@@ -541,3 +541,15 @@ def test_inpaint_blocks_closed_forms(oracle_mod):
     assert sweeps == 1
     top = [f[0, 1], f[1, 1]]
     assert v[0, 2].tolist() == [int((int(top[0][k]) + int(top[1][k]) + 1) // 2) for k in range(3)]
+
+
+@pytest.mark.parametrize("w,h,K,threads", [(333, 191, 0, 3), (640, 360, 0, 8), (97, 64, 2, 5), (24, 9, 4, 16)])
+def test_row_parallel_equals_single_thread(oracle_mod, w, h, K, threads):
+    """The CPU baseline's row-parallel mode splits only row-independent
+    stages: its outputs equal the single-thread oracle's for any band split."""
+    frame = synth.gen_frame(31 + w, w, h, 12, 4.0)
+    B = synth.default_disparity(w)
+    one = oracle_mod.synthesize_views(frame, B, K=K)
+    many = oracle_mod.synthesize_views_mt(frame, B, threads, K=K)
+    for a, b in zip(one, many):
+        assert np.array_equal(a, b)
