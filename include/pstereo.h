@@ -21,9 +21,11 @@
  *  - The caller owns every image buffer; the context owns all scratch memory,
  *    allocated once in pstereo_create.  No call after create allocates device
  *    memory, so the launch sequence can be captured into a HIP graph.
- *  - Calls enqueue work on params->stream (a hipStream_t, NULL = the context's
- *    own stream) and return; outputs are valid once that stream has reached
- *    the work (synchronise it, or set PSTEREO_SYNC).
+ *  - Calls enqueue work on params->stream (a hipStream_t; NULL = the HIP null
+ *    stream, the legacy default stream, which is also torch's default stream)
+ *    and return; outputs are valid once that stream has reached the work
+ *    (synchronise it, or set PSTEREO_SYNC).  The work is ordered after what
+ *    was enqueued on that stream before the call, like any kernel on it.
  *  - Every call returns a status code; nothing is thrown across the ABI.
  *    Errors are not sticky.  The message of the last failure is kept per
  *    context (pstereo_last_error).  A context is not thread-safe: use one per
@@ -51,7 +53,8 @@ extern "C" {
 /* Flags. */
 #define PSTEREO_DEPTH_EXTERNAL 0x1u /* depth_in replaces the generated depth map */
 #define PSTEREO_SYNC 0x2u           /* block until the outputs are complete */
-#define PSTEREO_PROFILE 0x4u        /* record per-kernel HIP events (pstereo_profile_collect) */
+#define PSTEREO_PROFILE 0x4u        /* record each kernel's start and stop times in HIP events
+                                       (pstereo_profile_collect) */
 #define PSTEREO_WARP_GATHER 0x8u    /* reconstruct the views as the Fig. 3 code does (Section 4):
                                        each destination pixel gathers the source pixel its
                                        own filtered depth points back to, its own source
@@ -63,12 +66,26 @@ extern "C" {
                                        (Section 4) instead of the row fill: Jacobi sweeps over
                                        the whole frame, a hole with >= 2 undamaged 8-neighbours
                                        taking their mean (rounded half up), until a sweep fills
-                                       nothing (at most 4096 sweeps); pixels never filled keep
-                                       their own source pixel.  Plain calls only.  The first
+                                       nothing; pixels never filled keep their own source pixel.
+                                       A frame still filling pixels at sweep 4096 is not composed:
+                                       the call returns PSTEREO_E_UNSUPPORTED and the outputs are
+                                       left unwritten.  Plain calls only.  The first
                                        such call allocates 12 * max_w * max_h bytes of scratch,
                                        and every such call waits for its sweeps (the host checks
                                        convergence), so it is neither asynchronous nor
                                        graph-capturable */
+
+#define PSTEREO_PIPELINE 0x20u      /* pipelined plain calls: this call's depth-map stages (block
+                                       statistics, region grouping) run on a second stream the
+                                       context owns, so that they overlap the depth filter and
+                                       warp of the context's previous pipelined call.  The caller
+                                       promises that everything writing this call's frame was
+                                       enqueued on params->stream (or had finished) before that
+                                       previous pipelined call was made; the filter and warp still
+                                       follow everything on params->stream.  Calls on the same
+                                       context alternate two sets of block tables.  Ignored with
+                                       PSTEREO_DEPTH_EXTERNAL or PSTEREO_INPAINT_BLOCKS; not for
+                                       stream capture */
 
 /* Largest number of depth blocks per frame (region grouping runs in one
  * workgroup's LDS). */
@@ -86,7 +103,7 @@ typedef struct pstereo_params {
     int32_t depth_threshold;  /* T: depths above T shift crossed (in front of the
                                  screen), others uncrossed; 150 in the paper;
                                  -1..255, -1 = linear mode (depth 0 at the screen) */
-    int32_t block_size;       /* K: depth block edge in px, one of 4, 8, 16, 32, 64;
+    int32_t block_size;       /* K: depth block edge in px, one of 2, 4, 8, 16, 32, 64;
                                  0 = smallest of 8, 16, 32, 64 giving at most
                                  PSTEREO_MAX_BLOCKS blocks */
     int32_t edge_thresh;      /* g: a block is an edge block when some forward luma
@@ -102,7 +119,7 @@ typedef struct pstereo_params {
                                  PSTEREO_DEPTH_EXTERNAL is set; filtered like it */
     uint8_t *out_depth;       /* optional device uint8 [h][w]: filtered depth */
     uint8_t *out_depth_raw;   /* optional device uint8 [h][w]: depth before filtering */
-    void *stream;             /* hipStream_t to enqueue on; NULL = context stream */
+    void *stream;             /* hipStream_t to enqueue on; NULL = the HIP null stream */
     uint8_t *out_hsbs;        /* optional device RGB24 [h][w][3]: half side-by-side
                                  frame (Section 5 names it beside the anaglyph):
                                  left half = left view squeezed to floor(w/2)
@@ -121,8 +138,8 @@ typedef struct pstereo_ctx pstereo_ctx;
 int pstereo_params_init(pstereo_params *p);
 
 /* Create a context on HIP device `device` for frames up to max_w x max_h
- * (1 <= max_w <= 65535, 1 <= max_h <= 65535).  Allocates the context's stream
- * and all scratch memory.  On success *out receives the context.  Errors:
+ * (1 <= max_w <= 65535, 1 <= max_h <= 65535).  Allocates all scratch memory
+ * (the context owns no stream: work goes on the caller's).  On success *out receives the context.  Errors:
  * PSTEREO_E_INVALID (bad device or sizes, out == NULL), PSTEREO_E_NOMEM,
  * PSTEREO_E_DEVICE. */
 int pstereo_create(pstereo_ctx **out, int device, int max_w, int max_h);
@@ -141,8 +158,9 @@ int pstereo_synthesize(pstereo_ctx *ctx, const uint8_t *frame, int w, int h,
                        const pstereo_params *p, uint8_t *out_left,
                        uint8_t *out_right, uint8_t *out_anaglyph);
 
-/* Release the context, its stream and its scratch memory.  NULL is a no-op.
- * Waits for the context's outstanding work first. */
+/* Release the context and its scratch memory.  NULL is a no-op.  Waits for
+ * the device first (the context's work may sit on any of the caller's
+ * streams). */
 int pstereo_destroy(pstereo_ctx *ctx);
 
 /* Message of the last failed call on ctx ("" if none); ctx may be NULL for
@@ -166,14 +184,18 @@ int pstereo_debug_blocks(pstereo_ctx *ctx, uint32_t *stats, int32_t *labels,
                          uint8_t *dblk, int cap, int *gw, int *gh);
 
 /*
- * Kernel timing.  Each pstereo_synthesize with PSTEREO_PROFILE records HIP
- * events on its stream at the ends of its four stages (block statistics,
- * region grouping, depth filter, warp; a stage may be several kernels).  This call waits for the recorded events,
- * writes the summed kernel durations in milliseconds to ms_sum[0..3] and the number
- * of profiled calls to *count, and clears the record.  If per_call_ms is not
- * NULL it receives, in call order, up to cap per-call durations (first event
- * to last event of the call, ms).  At most 4096 calls are kept between
- * collections; older ones are dropped and not counted.
+ * Kernel timing.  Each pstereo_synthesize with PSTEREO_PROFILE launches its
+ * kernels with a start and a stop HIP event each, which take the times of the
+ * kernel's own dispatch (no marker packets between the kernels).  The events
+ * are created by the first profiled call on the context.  This call waits
+ * for the recorded events, writes the summed durations in milliseconds of the
+ * four stages (block statistics, region grouping, depth filter, warp; a stage
+ * runs from its first kernel's start to its last kernel's stop) to
+ * ms_sum[0..3] and the number of profiled calls to *count, and clears the
+ * record.  If per_call_ms is not NULL it receives, in call order, up to cap
+ * per-call durations (first kernel's start to last kernel's stop, ms).  At
+ * most 4096 calls are kept between collections; older ones are dropped and
+ * not counted.  Block-inpainting sweeps are not timed.
  */
 int pstereo_profile_collect(pstereo_ctx *ctx, double ms_sum[4], int *count,
                             double *per_call_ms, int cap);
@@ -201,12 +223,11 @@ int pstereo_video_frame(pstereo_video *v, const uint8_t *frame, uint8_t *out_lef
 int pstereo_video_end(pstereo_video *v);
 
 /*
- * Batched form: many frames of uneven size through ONE persistent, fused
- * kernel launch.  Each of its workgroups (one per compute unit) claims
- * tasks in a dependency order (per frame: block statistics, region grouping,
- * depth filter, warp) from a device counter, so the region grouping of one
- * frame overlaps the streaming work of the others.  Every frame's output is
- * byte-identical to pstereo_synthesize with the same parameters.
+ * Batched form: many frames of uneven size per launch, in one of two forms
+ * (PSTEREO_BATCH_STAGED, the default: one kernel per stage over all frames;
+ * PSTEREO_BATCH_FUSED: one persistent kernel whose workgroups claim tasks in
+ * a dependency order -- see the tuning section below).  Every frame's output
+ * is byte-identical to pstereo_synthesize with the same parameters.
  *
  * pstereo_batch_create: a batch object on ctx's device for up to max_jobs
  *   frames of max_pixels pixels in total; allocates all per-frame scratch
@@ -218,9 +239,9 @@ int pstereo_video_end(pstereo_video *v);
  *   multiple of 4 and at most 16384, 4-byte aligned device buffers, outputs
  *   disjoint from every frame and from each other (PSTEREO_E_ALIAS).
  * pstereo_batch_launch: enqueues the prepared batch on `stream` (a
- *   hipStream_t; NULL = the prepare stream): a counter-reset kernel and the
- *   persistent kernel; no copies and no allocation, so it can be captured
- *   into a HIP graph and replayed.  A prepared batch can be launched any
+ *   hipStream_t; NULL = the prepare stream): the staged kernels, or a
+ *   counter-reset kernel and the persistent kernel; no copies and no
+ *   allocation, so it can be captured into a HIP graph and replayed.  A prepared batch can be launched any
  *   number of times; launches of one batch object must not overlap.
  *   Each dependency wait inside the persistent kernel is bounded (1 s of
  *   wall-clock time); should one run out, every workgroup leaves early, the
@@ -245,6 +266,24 @@ int pstereo_batch_launch(pstereo_batch *b, void *stream);
 int pstereo_batch_run(pstereo_batch *b, const pstereo_job *jobs, int n, const pstereo_params *p);
 int pstereo_batch_destroy(pstereo_batch *b);
 const char *pstereo_batch_last_error(const pstereo_batch *b);
+
+/*
+ * pstereo_synthesize_batch: the views of n frames (sizes may differ) in one
+ * batched launch on p->stream (NULL = the HIP null stream), with a batch
+ * object the context keeps.  Same requirements and results as
+ * pstereo_batch_run (per-job max_disparity; p's other fields shared); the
+ * form is the staged one with 512-lane row-warp workgroups of 4 rows.  The
+ * first call, and any call with more jobs (above 64) or pixels (above one 4K
+ * frame) than the context's batch object holds, synchronises the device and
+ * allocates that object's scratch; later calls allocate nothing.  The call
+ * uploads its job tables from pinned staging on the stream, so it is not
+ * meant for graph capture (use pstereo_batch_prepare + pstereo_batch_launch).
+ * With PSTEREO_SYNC it waits for the stream.  Errors as for
+ * pstereo_batch_run; the message is kept on the context.  The paper converts
+ * frames one at a time (Section 5); running many frames per launch is this
+ * library's form for throughput.
+ */
+int pstereo_synthesize_batch(pstereo_ctx *ctx, const pstereo_job *jobs, int n, const pstereo_params *p);
 
 /*
  * Batch forms and their tuning.

@@ -233,6 +233,42 @@ __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile
     }
 }
 
+// Block statistics for blocks of 2 x 2 px (frames of at most 2^17 pixels,
+// so this path is never the bulk of the work): the same 64 x 64 px tiles on
+// 256 lanes; lane t takes block column t % 32 of the tile's 32 x 32 blocks in
+// block rows t / 32 + 8 k, k = 0..3, reading pixels bytewise and the luma
+// steps to the right and below directly.  No barriers.
+__device__ __forceinline__ void bs_tile_k2(const FrameDesc& f, int tile_x, int tile_y, int t, bool active) {
+    if (!active) return;
+    const int W = f.w, H = f.h;
+    const int bx = tile_x * 32 + (t & 31);
+    if (bx >= f.gw) return;
+    for (int k = 0; k < 4; ++k) {
+        const int by = tile_y * 32 + (t >> 5) + 8 * k;
+        if (by >= f.gh) break;
+        uint32_t sr = 0, sg = 0, sb = 0, cnt = 0, edge = 0;
+        for (int dy = 0; dy < 2; ++dy) {
+            for (int dx = 0; dx < 2; ++dx) {
+                const int x = 2 * bx + dx, y = 2 * by + dy;
+                if (x >= W || y >= H) continue;
+                const uint8_t* p = f.frame + ((size_t)y * W + x) * 3;
+                sr += p[0];
+                sg += p[1];
+                sb += p[2];
+                ++cnt;
+                const int Y = luma(p[0], p[1], p[2]);
+                if (x + 1 < W && iabs(luma(p[3], p[4], p[5]) - Y) > f.g) edge = 1;
+                if (y + 1 < H) {
+                    const uint8_t* q = p + (size_t)W * 3;
+                    if (iabs(luma(q[0], q[1], q[2]) - Y) > f.g) edge = 1;
+                }
+            }
+        }
+        f.stats[by * f.gw + bx] = ((sr + cnt / 2) / cnt) | (((sg + cnt / 2) / cnt) << 8) |
+                                  (((sb + cnt / 2) / cnt) << 16) | (edge << 24);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // region grouping, one workgroup of 1024 lanes per frame.
 //

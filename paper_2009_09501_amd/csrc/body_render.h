@@ -152,6 +152,47 @@ __device__ __forceinline__ void quad_depth_tab(const FrameDesc& f, int x0, int y
     for (int j = 0; j < 4; ++j) D[j] = best[j] >= kNone ? fallback : (best[j] & 255u);
 }
 
+// Raw depth of the four pixels of a quad for blocks of 2 px (the quad spans
+// two block columns): the same rule as quad_depth_tab, per pixel, from the
+// block table in global memory (frames of 2 px blocks hold at most 2^17
+// pixels, so this path is never the bulk of the work).  strips: block depths
+// are resolved through the merge's slot table.
+__device__ __forceinline__ uint2 block_entry_global(const FrameDesc& f, int bx, int by, bool strips) {
+    if (bx < 0 || bx >= f.gw || by < 0 || by >= f.gh) return make_uint2(1u << 24, 0u);
+    uint2 e = f.binfo[by * f.gw + bx];
+    if (strips) e.y = block_depth_from_slots(f, by, e);
+    return e;
+}
+
+__device__ __forceinline__ void quad_depth_k2(const FrameDesc& f, int x0, int yy, bool strips,
+                                              const uint32_t (&col)[4], uint32_t (&D)[4]) {
+    const int by = yy >> 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int bx = (x0 + j) >> 1;
+        const uint2 own = block_entry_global(f, bx, by, strips);
+        if (!(own.x >> 24)) {
+            D[j] = own.y;
+            continue;
+        }
+        // first strict minimum of the L1 colour distance over the non-edge
+        // blocks of the 3 x 3 neighbourhood, in raster order
+        int best = -1;
+        uint32_t bestd = 0, bestdep = 0;
+        for (int k = 0; k < 9; ++k) {
+            const uint2 c = block_entry_global(f, bx + k % 3 - 1, by + k / 3 - 1, strips);
+            if (c.x >> 24) continue;
+            const uint32_t d = __builtin_amdgcn_sad_u8(col[j], c.x, 0u);
+            if (best < 0 || d < bestd) {
+                best = k;
+                bestd = d;
+                bestdep = c.y;
+            }
+        }
+        D[j] = best >= 0 ? bestdep : (uint32_t)ramp(by, f.gh);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // k_cbf: 64 x 32 pixel tiles, 256 lanes; lane = one quad in each of two tile
 // rows (ty and ty + 16).  LDS holds, for the tile and a 4 px / R row halo,
@@ -258,8 +299,9 @@ __device__ __forceinline__ void cbf_load(const FrameDesc& f, int tile_x, int til
 
 // One 64 x 32 tile (tile_x, tile_y) on 256 lanes t = 0..255 (four whole
 // waves).  lds: CbfTile<R>::kLdsWords words.  Inactive lane groups do no
-// memory work but pass the same three barriers.
-template <int R, bool ALIGNED>
+// memory work but pass the same three barriers.  K2: blocks of 2 px (raw
+// depth looked up per pixel in global memory, no block table in LDS).
+template <int R, bool ALIGNED, bool K2 = false>
 __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int tile_y, int t, uint32_t* lds,
                                          bool active) {
     constexpr int S = 2 * R + 1;
@@ -297,7 +339,7 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
     const int bx_lo = max(-1, ((tx0 - 4) >> ks) - 1), bx_hi = min(f.gw, ((tx0 + 4 * kTileQuads - 5) >> ks) + 1);
     const int by_lo = max(-1, ((ty0 - R) >> ks) - 1), by_hi = min(f.gh, ((ty0 + kTileH - 1 + R) >> ks) + 1);
     const int bw = bx_hi - bx_lo + 1;
-    if (!f.depth_in && H > 0) {
+    if (!K2 && !f.depth_in && H > 0) {
         const int nbt = bw * (by_hi - by_lo + 1);
         // after the strip-parallel grouping (unless its merge grouped the
         // whole frame itself) a block's region depth is resolved here from
@@ -357,6 +399,8 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
                 const uint8_t* dp = f.depth_in + (size_t)yy * W + x0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) D[j] = j < n ? dp[j] : 0u;
+            } else if (K2) {
+                quad_depth_k2(f, x0, yy, f.rstrip > 0 && f.rctl[1] == 0, col, D);
             } else {
                 quad_depth_tab(f, x0, yy, ks, btab, bx_lo, by_lo, bw, col, D);
             }
@@ -407,7 +451,7 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
             // non-edge blocks of one region depth the window is uniform
             // (four table reads); else the depths are compared pixel by pixel
             uint32_t c = 0, bad = 1;
-            if (!f.depth_in && ks >= 3) {
+            if (!K2 && !f.depth_in && ks >= 3) {
                 const int bxa = max(x0 - R, 0) >> ks, bxb = min(x0 + 3 + R, W - 1) >> ks;
                 const int bya = max(y - R, 0) >> ks, byb = min(y + R, H - 1) >> ks;
                 const uint2 e00 = btab[(bya - by_lo) * bw + (bxa - bx_lo)], e01 = btab[(bya - by_lo) * bw + (bxb - bx_lo)];

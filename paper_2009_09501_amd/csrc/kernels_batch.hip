@@ -65,6 +65,7 @@ __device__ __noinline__ void task_blockstats(const FrameDesc* fp, int k, int ite
     const bool active = item < items;
     const int tx = active ? item % gx : 0, ty = active ? item / gx : 0;
     switch (f.K) {
+        case 2: bs_tile_k2(f, tx, ty, t, active); break;
         case 4: bs_tile<4, true>(f, tx, ty, t, lds + g * BsTile<4>::kLdsWords, active); break;
         case 8: bs_tile<8, true>(f, tx, ty, t, lds + g * BsTile<8>::kLdsWords, active); break;
         case 16: bs_tile<16, true>(f, tx, ty, t, lds + g * BsTile<16>::kLdsWords, active); break;
@@ -86,7 +87,8 @@ __device__ __noinline__ void task_cbf(const FrameDesc* fp, int k, int items, int
     const int item = 4 * k + g;
     const bool active = item < items;
     const int tx = active ? item % gx : 0, ty = active ? item / gx : 0;
-    cbf_tile<R, true>(f, tx, ty, t, lds + g * CbfTile<R>::kLdsWords, active);
+    if (f.K == 2) cbf_tile<R, true, true>(f, tx, ty, t, lds + g * CbfTile<R>::kLdsWords, active);
+    else cbf_tile<R, true>(f, tx, ty, t, lds + g * CbfTile<R>::kLdsWords, active);
 }
 
 __device__ __noinline__ void task_warp(const FrameDesc* fp, int k, uint32_t* lds) {
@@ -190,6 +192,7 @@ __global__ void __launch_bounds__(256) k_mf_blockstats(const FrameDesc* frames, 
     const int gx = (f.w + 63) / 64;
     const int tx = local % gx, ty = local / gx;
     switch (f.K) {
+        case 2: bs_tile_k2(f, tx, ty, threadIdx.x, true); break;
         case 4: bs_tile<4, true>(f, tx, ty, threadIdx.x, lds, true); break;
         case 8: bs_tile<8, true>(f, tx, ty, threadIdx.x, lds, true); break;
         case 16: bs_tile<16, true>(f, tx, ty, threadIdx.x, lds, true); break;
@@ -204,7 +207,8 @@ __global__ void __launch_bounds__(kRegionThreads) k_mf_regions(const FrameDesc* 
     regions_body(f, lds);
 }
 
-template <int R>
+// K2: every frame of the batch has blocks of 2 px (the block size is shared).
+template <int R, bool K2>
 __global__ void __launch_bounds__(256) k_mf_cbf(const FrameDesc* frames, const int* first, int n) {
     __shared__ uint32_t lds[CbfTile<R>::kLdsWords];
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
@@ -212,7 +216,7 @@ __global__ void __launch_bounds__(256) k_mf_cbf(const FrameDesc* frames, const i
     const FrameDesc f = frames[fi];
     const int local = idx - first[fi];
     const int gx = (f.w + kTileW - 1) / kTileW;
-    cbf_tile<R, true>(f, local % gx, local / gx, threadIdx.x, lds, true);
+    cbf_tile<R, true, K2>(f, local % gx, local / gx, threadIdx.x, lds, true);
 }
 
 // `rows` consecutive image rows per workgroup, each row's loads issued
@@ -251,11 +255,17 @@ hipError_t launch_staged(const FrameDesc* d_frames, const int* d_first, const St
     const int* first_cbf = d_first + (n + 1);
     hipLaunchKernelGGL(k_mf_blockstats, dim3(pl.tiles_bs), dim3(256), 0, s, d_frames, first_bs, n);
     hipLaunchKernelGGL(k_mf_regions, dim3(n), dim3(kRegionThreads), pl.regions_lds, s, d_frames);
+    const void* cbf_fn;
     switch (pl.r) {
-        case 0: hipLaunchKernelGGL(k_mf_cbf<0>, dim3(pl.tiles_cbf), dim3(256), 0, s, d_frames, first_cbf, n); break;
-        case 1: hipLaunchKernelGGL(k_mf_cbf<1>, dim3(pl.tiles_cbf), dim3(256), 0, s, d_frames, first_cbf, n); break;
-        case 2: hipLaunchKernelGGL(k_mf_cbf<2>, dim3(pl.tiles_cbf), dim3(256), 0, s, d_frames, first_cbf, n); break;
-        default: hipLaunchKernelGGL(k_mf_cbf<3>, dim3(pl.tiles_cbf), dim3(256), 0, s, d_frames, first_cbf, n); break;
+        case 0: cbf_fn = pl.k2 ? (const void*)&k_mf_cbf<0, true> : (const void*)&k_mf_cbf<0, false>; break;
+        case 1: cbf_fn = pl.k2 ? (const void*)&k_mf_cbf<1, true> : (const void*)&k_mf_cbf<1, false>; break;
+        case 2: cbf_fn = pl.k2 ? (const void*)&k_mf_cbf<2, true> : (const void*)&k_mf_cbf<2, false>; break;
+        default: cbf_fn = pl.k2 ? (const void*)&k_mf_cbf<3, true> : (const void*)&k_mf_cbf<3, false>; break;
+    }
+    {
+        void* args[] = {const_cast<FrameDesc**>(&d_frames), const_cast<int**>(&first_cbf), const_cast<int*>(&n)};
+        hipError_t e = hipLaunchKernel(cbf_fn, dim3(pl.tiles_cbf), dim3(256), args, 0, s);
+        if (e != hipSuccess) return e;
     }
     for (int c = 0; c < pl.nclass; ++c) {
         const int* fw = d_first + (size_t)(2 + c) * (n + 1);

@@ -17,6 +17,10 @@ __global__ void __launch_bounds__(256) k_blockstats(FrameDesc f) {
     bs_tile<K, ALIGNED>(f, tile - ty * gx, ty, threadIdx.x, lds, true);
 }
 
+__global__ void __launch_bounds__(256) k_blockstats_k2(FrameDesc f) {
+    bs_tile_k2(f, blockIdx.x, blockIdx.y, threadIdx.x, true);
+}
+
 __global__ void __launch_bounds__(kRegionThreads) k_regions(FrameDesc f) {
     extern __shared__ uint32_t lds[];
     regions_body(f, lds);
@@ -47,6 +51,9 @@ static LaunchSpec bs_spec(const FrameDesc& f) {
 template <bool A>
 static LaunchSpec bs_k(const FrameDesc& f) {
     switch (f.K) {
+        case 2:
+            return {reinterpret_cast<const void*>(&k_blockstats_k2), dim3((f.w + 63) / 64, (f.h + 63) / 64), dim3(256),
+                    0};
         case 4: return bs_spec<4, A>(f);
         case 8: return bs_spec<8, A>(f);
         case 16: return bs_spec<16, A>(f);

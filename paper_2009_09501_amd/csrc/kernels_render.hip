@@ -10,13 +10,13 @@
 
 namespace pstereo {
 
-template <int R, bool ALIGNED>
+template <int R, bool ALIGNED, bool K2>
 __global__ void __launch_bounds__(256) k_cbf(FrameDesc f) {
     __shared__ uint32_t lds[CbfTile<R>::kLdsWords];
     const int gx = gridDim.x;
     const int tile = xcd_tile(blockIdx.y * gx + blockIdx.x, gx * gridDim.y);
     const int ty = tile / gx;
-    cbf_tile<R, ALIGNED>(f, tile - ty * gx, ty, threadIdx.x, lds, true);
+    cbf_tile<R, ALIGNED, K2>(f, tile - ty * gx, ty, threadIdx.x, lds, true);
 }
 
 // Rows blockIdx.x, blockIdx.x + gridDim.x, ...: a grid of at most a few
@@ -108,8 +108,11 @@ bool warp_shape_cap(int w, int cap, WarpShape* out) {
 
 template <int R, bool A>
 static LaunchSpec cbf_spec(const FrameDesc& f) {
-    return {reinterpret_cast<const void*>(&k_cbf<R, A>), dim3((f.w + kTileW - 1) / kTileW, (f.h + kTileH - 1) / kTileH),
-            dim3(256), 0};
+    // blocks of 2 px take their raw depth per pixel from global memory (an
+    // external depth map needs no block lookups at all)
+    const void* fn = (f.K == 2 && !f.depth_in) ? reinterpret_cast<const void*>(&k_cbf<R, A, true>)
+                                                 : reinterpret_cast<const void*>(&k_cbf<R, A, false>);
+    return {fn, dim3((f.w + kTileW - 1) / kTileW, (f.h + kTileH - 1) / kTileH), dim3(256), 0};
 }
 
 template <bool A>

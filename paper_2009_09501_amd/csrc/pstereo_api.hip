@@ -17,31 +17,75 @@ using pstereo::WarpShape;
 
 namespace {
 
+// Profiling ring: per profiled call, a start and a stop event per kernel.
 constexpr int kProfSets = 4096;
-constexpr int kProfEvents = 5;  // before blockstats, after blockstats, after regions, after cbf, after warp
+constexpr int kMaxKernels = 6;
+constexpr int kProfEvents = 2 * kMaxKernels;
 
 thread_local std::string g_create_error;
+
+// The per-frame tables of the depth-map stages (block statistics, region
+// grouping) that the filter reads: one set per frame in flight.
+struct BlockScratch {
+    uint8_t* mem = nullptr;  // one allocation, carved below
+    uint32_t* stats = nullptr;
+    uint2* binfo = nullptr;
+    int32_t* labels = nullptr;
+    uint2* rent = nullptr;
+    uint32_t* rrow = nullptr;
+    uint32_t* rfin = nullptr;
+    uint2* rbnd = nullptr;
+    uint32_t* rctl = nullptr;
+};
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// Allocate and carve one set; the control words start at zero (the merge
+// kernel leaves them zero after each frame).
+hipError_t block_scratch_alloc(BlockScratch& b) {
+    const size_t nb = PSTEREO_MAX_BLOCKS, ns = pstereo::kRegionSlots, nd = pstereo::kBoundSlots;
+    const size_t sz[8] = {nb * 4, nb * 8, nb * 4, ns * 8, ns * 4, ns * 4, nd * 8, 4 * 4};
+    size_t off[8], tot = 0;
+    for (int i = 0; i < 8; ++i) {
+        off[i] = tot;
+        tot += align256(sz[i]);
+    }
+    hipError_t e = hipMalloc(&b.mem, tot);
+    if (e != hipSuccess) return e;
+    b.stats = reinterpret_cast<uint32_t*>(b.mem + off[0]);
+    b.binfo = reinterpret_cast<uint2*>(b.mem + off[1]);
+    b.labels = reinterpret_cast<int32_t*>(b.mem + off[2]);
+    b.rent = reinterpret_cast<uint2*>(b.mem + off[3]);
+    b.rrow = reinterpret_cast<uint32_t*>(b.mem + off[4]);
+    b.rfin = reinterpret_cast<uint32_t*>(b.mem + off[5]);
+    b.rbnd = reinterpret_cast<uint2*>(b.mem + off[6]);
+    b.rctl = reinterpret_cast<uint32_t*>(b.mem + off[7]);
+    return hipMemset(b.rctl, 0, 4 * sizeof(uint32_t));
+}
 
 }  // namespace
 
 struct pstereo_ctx {
     int device = 0;
     int max_w = 0, max_h = 0;
-    hipStream_t stream = nullptr;
-    uint32_t* d_stats = nullptr;
-    uint2* d_binfo = nullptr;
-    int32_t* d_labels = nullptr;
+    // block tables: set 0 for every call; pipelined calls alternate sets 0
+    // and 1 so that one frame's depth-map stages can run while the previous
+    // frame's filter still reads its set
+    BlockScratch blk[2];
     uint8_t* d_df = nullptr;  // filtered depth, max_w * max_h bytes
-    uint2* d_rent = nullptr;
-    uint32_t* d_rrow = nullptr;
-    uint32_t* d_rfin = nullptr;
-    uint2* d_rbnd = nullptr;
-    uint32_t* d_rctl = nullptr;
+    // pipelined calls (PSTEREO_PIPELINE): the depth-map stages go on `side`
+    hipStream_t side = nullptr;
+    hipEvent_t ev_before = nullptr;  // the caller's stream before the last pipelined call
+    hipEvent_t ev_depth = nullptr;   // the depth-map stages of the last pipelined call done
+    bool pipe_valid = false;         // ev_before holds the previous pipelined call's mark
+    hipStream_t pipe_stream = nullptr;
+    long long pipe_n = 0;
     // block-iterative inpainting scratch, allocated on first use
     uint32_t* d_ipc = nullptr;
     uint16_t* d_ipt = nullptr;
     uint32_t* d_ipn = nullptr;
     uint32_t* h_ipn = nullptr;  // pinned read-back of one sweep counter
+    pstereo_batch* batch = nullptr;  // pstereo_synthesize_batch's batch object, made on first use
     std::string err;
     // last generated-depth call, for pstereo_debug_blocks
     bool have_blocks = false;
@@ -49,15 +93,17 @@ struct pstereo_ctx {
     hipStream_t last_stream = nullptr;
     FrameDesc last_fd{};         // descriptor of the last generated-depth frame
     bool blocks_final = false;   // its per-block labels and depths are final
-    // profiling ring
+    // profiling ring: events of kProfSets calls; per call the kernel count
+    // and each kernel's stage
     std::vector<hipEvent_t> prof_ev;
-    std::vector<uint8_t> prof_has_depth;
+    std::vector<int8_t> prof_stage;  // [kProfSets][kMaxKernels], -1 past the last kernel
     long long prof_head = 0;
 };
 
 namespace pstereo {
 int ctx_device(const pstereo_ctx* c) { return c->device; }
-hipStream_t ctx_stream(const pstereo_ctx* c) { return c->stream; }
+pstereo_batch** ctx_batch(pstereo_ctx* c) { return &c->batch; }
+void ctx_set_error(pstereo_ctx* c, const char* msg) { c->err = msg ? msg : ""; }
 }  // namespace pstereo
 
 namespace {
@@ -99,7 +145,7 @@ bool overlap(const Range& a, const Range& b) {
     return a.p && b.p && a.p < b.p + b.n && b.p < a.p + a.n;
 }
 
-bool legal_block(int K) { return K == 4 || K == 8 || K == 16 || K == 32 || K == 64; }
+bool legal_block(int K) { return K == 2 || K == 4 || K == 8 || K == 16 || K == 32 || K == 64; }
 
 int auto_block(int w, int h) {
     static const int cand[4] = {8, 16, 32, 64};
@@ -146,25 +192,23 @@ int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = pstereo::prepare_depth_kernels();
     if (e == hipSuccess) e = pstereo::prepare_render_kernels();
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete c;
         return fail(nullptr, PSTEREO_E_DEVICE, "device setup failed: %s", hipGetErrorString(e));
     }
-    const size_t nb = PSTEREO_MAX_BLOCKS;
-    if (hipMalloc(&c->d_stats, nb * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&c->d_binfo, nb * sizeof(uint2)) != hipSuccess ||
-        hipMalloc(&c->d_labels, nb * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&c->d_df, (size_t)max_w * max_h) != hipSuccess ||
-        hipMalloc(&c->d_rent, pstereo::kRegionSlots * sizeof(uint2)) != hipSuccess ||
-        hipMalloc(&c->d_rrow, pstereo::kRegionSlots * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&c->d_rfin, pstereo::kRegionSlots * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&c->d_rbnd, pstereo::kBoundSlots * sizeof(uint2)) != hipSuccess ||
-        hipMalloc(&c->d_rctl, 4 * sizeof(uint32_t)) != hipSuccess ||
-        hipMemset(c->d_rctl, 0, 4 * sizeof(uint32_t)) != hipSuccess) {
+    if (block_scratch_alloc(c->blk[0]) != hipSuccess || block_scratch_alloc(c->blk[1]) != hipSuccess ||
+        hipMalloc(&c->d_df, (size_t)max_w * max_h) != hipSuccess) {
         (void)hipGetLastError();
         pstereo_destroy(c);
         return fail(nullptr, PSTEREO_E_NOMEM, "scratch allocation failed");
+    }
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_before, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_depth, hipEventDisableTiming) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        pstereo_destroy(c);
+        return fail(nullptr, PSTEREO_E_DEVICE, "stream or event creation failed");
     }
     *out = c;
     return PSTEREO_OK;
@@ -173,22 +217,20 @@ int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
 int pstereo_destroy(pstereo_ctx* c) {
     if (!c) return PSTEREO_OK;
     (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    // the context's work may sit on any stream of the caller's: wait for the
+    // device before its scratch goes
+    (void)hipDeviceSynchronize();
+    if (c->batch) (void)pstereo_batch_destroy(c->batch);
     for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
-    (void)hipFree(c->d_stats);
-    (void)hipFree(c->d_binfo);
-    (void)hipFree(c->d_labels);
+    for (BlockScratch& b : c->blk) (void)hipFree(b.mem);
     (void)hipFree(c->d_df);
-    (void)hipFree(c->d_rent);
-    (void)hipFree(c->d_rrow);
-    (void)hipFree(c->d_rfin);
-    (void)hipFree(c->d_rbnd);
-    (void)hipFree(c->d_rctl);
+    if (c->ev_before) (void)hipEventDestroy(c->ev_before);
+    if (c->ev_depth) (void)hipEventDestroy(c->ev_depth);
+    if (c->side) (void)hipStreamDestroy(c->side);
     (void)hipFree(c->d_ipc);
     (void)hipFree(c->d_ipt);
     (void)hipFree(c->d_ipn);
     if (c->h_ipn) (void)hipHostFree(c->h_ipn);
-    if (c->stream) (void)hipStreamDestroy(c->stream);
     (void)hipGetLastError();
     delete c;
     return PSTEREO_OK;
@@ -228,7 +270,7 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
     const bool ext = (p.flags & PSTEREO_DEPTH_EXTERNAL) != 0;
     if (ext && !p.depth_in) return fail(c, PSTEREO_E_INVALID, "PSTEREO_DEPTH_EXTERNAL without depth_in");
     const int K = p.block_size ? p.block_size : auto_block(w, h);
-    if (!legal_block(K)) return fail(c, PSTEREO_E_INVALID, "block_size %d not in {4,8,16,32,64}", p.block_size);
+    if (!legal_block(K)) return fail(c, PSTEREO_E_INVALID, "block_size %d not in {2,4,8,16,32,64}", p.block_size);
     const int gw = (w + K - 1) / K, gh = (h + K - 1) / K;
     if (!ext && (long long)gw * gh > PSTEREO_MAX_BLOCKS)
         return fail(c, PSTEREO_E_INVALID, "%dx%d blocks of %d px exceed %d", gw, gh, K, PSTEREO_MAX_BLOCKS);
@@ -273,15 +315,16 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
     f.out_df = p.out_depth;
     f.out_d0 = p.out_depth_raw;
     f.out_h = p.out_hsbs;
-    f.stats = c->d_stats;
-    f.binfo = c->d_binfo;
-    f.labels = c->d_labels;
+    const BlockScratch& bs = c->blk[0];
+    f.stats = bs.stats;
+    f.binfo = bs.binfo;
+    f.labels = bs.labels;
     f.df = c->d_df;
-    f.rent = c->d_rent;
-    f.rrow = c->d_rrow;
-    f.rfin = c->d_rfin;
-    f.rbnd = c->d_rbnd;
-    f.rctl = c->d_rctl;
+    f.rent = bs.rent;
+    f.rrow = bs.rrow;
+    f.rfin = bs.rfin;
+    f.rbnd = bs.rbnd;
+    f.rctl = bs.rctl;
     f.rstrip = pstereo::strip_rows(gw);
     f.w = w;
     f.h = h;
@@ -297,7 +340,7 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
     f.aligned = (w % 4 == 0) && (al % 4 == 0);
     f.gather = gather ? 1 : 0;
     *fd = f;
-    *stream = p.stream ? (hipStream_t)p.stream : c->stream;
+    *stream = (hipStream_t)p.stream;  // NULL: the HIP null stream
     *flags = p.flags;
     return PSTEREO_OK;
 }
@@ -305,6 +348,7 @@ int build_desc(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo
 // The launch sequence of one frame (block statistics and region grouping
 // only with a generated depth map).
 constexpr int kMaxSpecs = 6;
+static_assert(kMaxSpecs <= kMaxKernels, "profiling ring holds every kernel of a call");
 
 // stage[i]: which of the four profiled stages kernel i belongs to (block
 // statistics, region grouping, depth filter, warp)
@@ -379,46 +423,92 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
 
     const bool prof = (flags & PSTEREO_PROFILE) != 0;
     hipEvent_t* ev = nullptr;
+    int8_t* ev_stage = nullptr;
     if (prof) {
         if (c->prof_ev.empty()) {
-            c->prof_ev.resize((size_t)kProfSets * kProfEvents, nullptr);
-            c->prof_has_depth.resize(kProfSets, 0);
-            for (auto& x : c->prof_ev)
-                if ((e = hipEventCreate(&x)) != hipSuccess)
+            // created once, on the first profiled call
+            std::vector<hipEvent_t> evs((size_t)kProfSets * kProfEvents, nullptr);
+            for (auto& x : evs) {
+                if ((e = hipEventCreate(&x)) != hipSuccess) {
+                    for (hipEvent_t y : evs)
+                        if (y) (void)hipEventDestroy(y);
                     return fail(c, PSTEREO_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+                }
+            }
+            c->prof_ev.swap(evs);
+            c->prof_stage.assign((size_t)kProfSets * kMaxKernels, -1);
         }
         const int slot = (int)(c->prof_head % kProfSets);
         ev = &c->prof_ev[(size_t)slot * kProfEvents];
-        c->prof_has_depth[slot] = !ext;
+        ev_stage = &c->prof_stage[(size_t)slot * kMaxKernels];
         c->prof_head++;
+    }
+
+    // Pipelined call: the depth-map stages (block statistics, region
+    // grouping) run on the context's side stream into block-table set
+    // pipe_n % 2, after the work the caller's stream held before the
+    // previous pipelined call (the caller promises the frame was complete
+    // then); the filter and warp follow on the caller's stream once they are
+    // done.  So this frame's depth map is built while the previous frame's
+    // filter and warp run, and the set it writes was last read by the filter
+    // two frames back, which that mark already covers.
+    const bool pipe = (flags & PSTEREO_PIPELINE) && !ext && !inpaint;
+    if (pipe) {
+        const BlockScratch& bs = c->blk[c->pipe_n % 2];
+        f.stats = bs.stats;
+        f.binfo = bs.binfo;
+        f.labels = bs.labels;
+        f.rent = bs.rent;
+        f.rrow = bs.rrow;
+        f.rfin = bs.rfin;
+        f.rbnd = bs.rbnd;
+        f.rctl = bs.rctl;
+        const bool first = !c->pipe_valid || c->pipe_stream != s;
+        c->pipe_valid = false;  // until this call's launches are all enqueued
+        if ((first && (e = hipEventRecord(c->ev_before, s)) != hipSuccess) ||
+            (e = hipStreamWaitEvent(c->side, c->ev_before, 0)) != hipSuccess ||
+            (e = hipEventRecord(c->ev_before, s)) != hipSuccess)
+            return fail(c, PSTEREO_E_DEVICE, "pipeline ordering: %s", hipGetErrorString(e));
+    } else {
+        c->pipe_valid = false;
     }
 
     pstereo::LaunchSpec ls[kMaxSpecs];
     int stage[kMaxSpecs];
     int n;
     frame_specs(f, ws, ls, n, &stage);
-    // event k is recorded at the end of stage k-1; frames without the depth kernels
-    // repeat the first event so the depth slots read zero
-    if (prof) (void)hipEventRecord(ev[0], s);
-    if (ext && prof) {
-        (void)hipEventRecord(ev[1], s);
-        (void)hipEventRecord(ev[2], s);
-    }
     static const char* names[4] = {"block statistics", "region grouping", "depth filter", "warp"};
     for (int i = 0; i < n; ++i) {
-        if ((e = pstereo::launch(ls[i], f, s)) != hipSuccess)
+        hipStream_t si = s;
+        if (pipe && stage[i] <= 1) si = c->side;
+        if (pipe && stage[i] == 2 &&
+            ((e = hipEventRecord(c->ev_depth, c->side)) != hipSuccess ||
+             (e = hipStreamWaitEvent(s, c->ev_depth, 0)) != hipSuccess)) {
+            if (prof) ev_stage[0] = -1;
+            return fail(c, PSTEREO_E_DEVICE, "pipeline ordering: %s", hipGetErrorString(e));
+        }
+        // a profiled call takes each kernel's own start and stop times
+        e = prof ? pstereo::launch_timed(ls[i], f, si, ev[2 * i], ev[2 * i + 1]) : pstereo::launch(ls[i], f, si);
+        if (e != hipSuccess) {
+            if (prof) ev_stage[0] = -1;  // nothing of this call is collected
             return fail(c, PSTEREO_E_DEVICE, "%s launch: %s", names[stage[i]], hipGetErrorString(e));
-        // one event at the end of each stage (the inpainting sweeps belong
-        // to the warp stage)
-        if (prof && (i + 1 == n || stage[i + 1] != stage[i]) && !(inpaint && stage[i] == 3))
-            (void)hipEventRecord(ev[stage[i] + 1], s);
+        }
     }
+    if (pipe) {
+        c->pipe_valid = true;
+        c->pipe_stream = s;
+        c->pipe_n++;
+    }
+    if (prof)
+        for (int i = 0; i < kMaxKernels; ++i) ev_stage[i] = (int8_t)(i < n ? stage[i] : -1);
     if (inpaint) {
         // sweeps in chunks of 8 until one fills nothing (each sweep returns at
-        // once after a sweep that filled nothing)
+        // once after a sweep that filled nothing); a frame still filling
+        // pixels at the last allowed sweep is reported, not composed
         if ((e = pstereo::launch_inpaint_reset(f, s)) != hipSuccess)
             return fail(c, PSTEREO_E_DEVICE, "inpainting launch: %s", hipGetErrorString(e));
-        for (int sw = 1; sw <= pstereo::kMaxSweeps; sw += 8) {
+        bool converged = false;
+        for (int sw = 1; sw <= pstereo::kMaxSweeps && !converged; sw += 8) {
             const int last = std::min(sw + 7, pstereo::kMaxSweeps);
             for (int k = sw; k <= last; ++k)
                 if ((e = pstereo::launch_inpaint_sweep(f, k, s)) != hipSuccess)
@@ -426,11 +516,14 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
             if ((e = hipMemcpyAsync(c->h_ipn, f.ipn + last, sizeof(uint32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
                 (e = hipStreamSynchronize(s)) != hipSuccess)
                 return fail(c, PSTEREO_E_DEVICE, "inpainting convergence check: %s", hipGetErrorString(e));
-            if (*c->h_ipn == 0) break;
+            converged = *c->h_ipn == 0;
         }
+        if (!converged)
+            return fail(c, PSTEREO_E_UNSUPPORTED,
+                        "block inpainting still filled pixels at its last allowed sweep (%d); outputs not written",
+                        pstereo::kMaxSweeps);
         if ((e = pstereo::launch_inpaint_final(f, s)) != hipSuccess)
             return fail(c, PSTEREO_E_DEVICE, "inpainting composition: %s", hipGetErrorString(e));
-        if (prof) (void)hipEventRecord(ev[4], s);
     }
     if (!ext) {
         c->have_blocks = true;
@@ -457,6 +550,7 @@ int pstereo_debug_blocks(pstereo_ctx* c, uint32_t* stats, int32_t* labels, uint8
     if (gh) *gh = c->last_gh;
     if (cap < nb) return fail(c, PSTEREO_E_INVALID, "capacity %d < %d blocks", cap, nb);
     (void)hipSetDevice(c->device);
+    c->pipe_valid = false;  // the next pipelined call waits for this one
     hipError_t e;
     if (!c->blocks_final) {
         // turn the blocks' slots into final labels and depths
@@ -467,9 +561,9 @@ int pstereo_debug_blocks(pstereo_ctx* c, uint32_t* stats, int32_t* labels, uint8
     e = hipStreamSynchronize(c->last_stream);
     if (e != hipSuccess) return fail(c, PSTEREO_E_DEVICE, "stream synchronize: %s", hipGetErrorString(e));
     std::vector<uint2> bi(nb);
-    if ((e = hipMemcpy(bi.data(), c->d_binfo, nb * sizeof(uint2), hipMemcpyDeviceToHost)) != hipSuccess)
+    if ((e = hipMemcpy(bi.data(), c->last_fd.binfo, nb * sizeof(uint2), hipMemcpyDeviceToHost)) != hipSuccess)
         return fail(c, PSTEREO_E_DEVICE, "copy: %s", hipGetErrorString(e));
-    if (labels && (e = hipMemcpy(labels, c->d_labels, nb * sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+    if (labels && (e = hipMemcpy(labels, c->last_fd.labels, nb * sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)
         return fail(c, PSTEREO_E_DEVICE, "copy: %s", hipGetErrorString(e));
     for (int i = 0; i < nb; ++i) {
         if (stats) stats[i] = bi[i].x;
@@ -489,22 +583,24 @@ int pstereo_profile_collect(pstereo_ctx* c, double ms_sum[4], int* count, double
     for (long long k = c->prof_head - n; k < c->prof_head; ++k) {
         const int slot = (int)(k % kProfSets);
         hipEvent_t* ev = &c->prof_ev[(size_t)slot * kProfEvents];
-        hipError_t e = hipEventSynchronize(ev[4]);
+        const int8_t* st = &c->prof_stage[(size_t)slot * kMaxKernels];
+        int nk = 0;
+        while (nk < kMaxKernels && st[nk] >= 0) ++nk;
+        if (nk == 0) continue;  // a call whose launch failed
+        hipError_t e = hipEventSynchronize(ev[2 * nk - 1]);
         if (e != hipSuccess) return fail(c, PSTEREO_E_DEVICE, "event synchronize: %s", hipGetErrorString(e));
-        float a = 0.f, b = 0.f, d = 0.f, q = 0.f;
-        if (c->prof_has_depth[slot]) {
-            (void)hipEventElapsedTime(&a, ev[0], ev[1]);
-            (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+        // a stage runs from its first kernel's start to its last kernel's stop
+        for (int i = 0; i < nk;) {
+            int j = i;
+            while (j + 1 < nk && st[j + 1] == st[i]) ++j;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[2 * i], ev[2 * j + 1]);
+            ms_sum[st[i]] += ms;
+            i = j + 1;
         }
-        (void)hipEventElapsedTime(&d, ev[2], ev[3]);
-        (void)hipEventElapsedTime(&q, ev[3], ev[4]);
-        ms_sum[0] += a;
-        ms_sum[1] += b;
-        ms_sum[2] += d;
-        ms_sum[3] += q;
         if (per_call_ms && *count < cap) {
             float tot = 0.f;
-            (void)hipEventElapsedTime(&tot, ev[0], ev[4]);
+            (void)hipEventElapsedTime(&tot, ev[0], ev[2 * nk - 1]);
             per_call_ms[*count] = tot;
         }
         ++*count;
@@ -591,6 +687,7 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
     v->params = pp;
     uint32_t flags;
     // template descriptor: aligned placeholders stand in for the frame buffers
+    // (the graphs run on p->stream, NULL = the HIP null stream)
     uint8_t* ph = c->d_df;
     int rc = build_desc(c, ph, w, h, &pp, ph + 4, ph + 8, ph + 12, &v->tmpl, &v->ws, &v->stream, &flags, false);
     if (rc != PSTEREO_OK) {
@@ -671,6 +768,7 @@ int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, 
     if (n % E == E - 1 && (e = hipEventRecord(v->done[(n / E) % 2], v->stream)) != hipSuccess)
         return fail(c, PSTEREO_E_DEVICE, "event record: %s", hipGetErrorString(e));
     v->count++;
+    c->pipe_valid = false;
     c->have_blocks = true;
     c->last_fd = f;
     c->blocks_final = f.rstrip == 0;

@@ -36,6 +36,7 @@ struct StagedPlan {
     int tiles_bs = 0, tiles_cbf = 0;
     size_t regions_lds = 0;
     int r = 2;
+    bool k2 = false;    // blocks of 2 px (shared by every frame of the batch)
     int warp_rows = 1;  // image rows per warp workgroup
     int nclass = 0;
     int cls_threads[kMaxWarpClasses];

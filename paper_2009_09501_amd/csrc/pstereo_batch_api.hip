@@ -198,9 +198,9 @@ int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, con
     if (p.cbf_radius < 0 || p.cbf_radius > 3) return bfail(b, PSTEREO_E_INVALID, "cbf_radius out of range");
     if (p.edge_thresh < 0 || p.edge_thresh > 255) return bfail(b, PSTEREO_E_INVALID, "edge_thresh out of range");
     if (p.link_thresh < 0 || p.link_thresh > 765) return bfail(b, PSTEREO_E_INVALID, "link_thresh out of range");
-    if (p.block_size && p.block_size != 4 && p.block_size != 8 && p.block_size != 16 && p.block_size != 32 &&
-        p.block_size != 64)
-        return bfail(b, PSTEREO_E_INVALID, "block_size %d not in {4,8,16,32,64}", p.block_size);
+    if (p.block_size && p.block_size != 2 && p.block_size != 4 && p.block_size != 8 && p.block_size != 16 &&
+        p.block_size != 32 && p.block_size != 64)
+        return bfail(b, PSTEREO_E_INVALID, "block_size %d not in {2,4,8,16,32,64}", p.block_size);
     (void)hipSetDevice(b->device);
     // the staging buffers may still feed the previous prepare's copies
     if (b->staged_pending) {
@@ -283,7 +283,7 @@ int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, con
     }
     b->n = n;
     b->r = p.cbf_radius;
-    b->stream = p.stream ? (hipStream_t)p.stream : pstereo::ctx_stream(b->ctx);
+    b->stream = (hipStream_t)p.stream;  // NULL: the HIP null stream
     hipStream_t st = b->stream;
     hipError_t e;
     if (b->tune.mode == PSTEREO_BATCH_FUSED) {
@@ -317,6 +317,7 @@ int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, con
         pl = pstereo::StagedPlan();
         pl.n = n;
         pl.r = p.cbf_radius;
+        pl.k2 = p.block_size == 2;
         pl.warp_rows = b->tune.warp_rows;
         int* fb = b->h_first;
         int* fc = b->h_first + (n + 1);
@@ -509,6 +510,49 @@ int pstereo_batch_autotune(pstereo_batch* b, const pstereo_job* jobs, int n, con
     rc = pstereo_batch_prepare(b, jobs, n, p);
     if (best) *best = best_c;
     if (best_ms) *best_ms = best_t;
+    return rc;
+}
+
+int pstereo_synthesize_batch(pstereo_ctx* ctx, const pstereo_job* jobs, int n, const pstereo_params* p) {
+    if (!ctx) return PSTEREO_E_INVALID;
+    pstereo::ctx_set_error(ctx, "");
+    if (!jobs || n < 1 || n > 4096) {
+        pstereo::ctx_set_error(ctx, "job count outside 1..4096 or jobs is NULL");
+        return PSTEREO_E_INVALID;
+    }
+    int64_t px = 0;
+    for (int i = 0; i < n; ++i) {
+        if (jobs[i].w < 1 || jobs[i].h < 1) {
+            pstereo::ctx_set_error(ctx, "a job has a non-positive size");
+            return PSTEREO_E_INVALID;
+        }
+        px += (int64_t)jobs[i].w * jobs[i].h;
+    }
+    pstereo_batch** slot = pstereo::ctx_batch(ctx);
+    pstereo_batch* b = *slot;
+    if (!b || b->max_jobs < n || b->max_pixels < px) {
+        // (re)made for at least this many jobs and pixels; the old object's
+        // scratch may still be read by launches in flight on any stream
+        if (b) {
+            (void)hipSetDevice(b->device);
+            (void)hipDeviceSynchronize();
+            batch_free(b);
+            *slot = nullptr;
+        }
+        const int jobs_cap = std::max(n, 64);
+        const int64_t px_cap = std::max<int64_t>(px, (int64_t)3840 * 2160);
+        const int rc = pstereo::batch_create_internal(ctx, jobs_cap, px_cap, true, &b);
+        if (rc != PSTEREO_OK) {
+            pstereo::ctx_set_error(ctx, "batch scratch allocation failed");
+            return rc;
+        }
+        // the staged form with 512-lane row workgroups of 4 rows, the tuning
+        // the autotuner picks for the uneven 720p..8K mix
+        b->tune = {PSTEREO_BATCH_STAGED, 512, 4, 0};
+        *slot = b;
+    }
+    const int rc = pstereo_batch_run(b, jobs, n, p);
+    if (rc != PSTEREO_OK) pstereo::ctx_set_error(ctx, b->err.c_str());
     return rc;
 }
 

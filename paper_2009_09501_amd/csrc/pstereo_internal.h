@@ -1,6 +1,7 @@
 // Internal interface between the C ABI layer and the gfx950 kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -92,12 +93,23 @@ inline hipError_t launch(const LaunchSpec& ls, const FrameDesc& f, hipStream_t s
     void* args[] = {&arg};
     return hipLaunchKernel(ls.func, ls.grid, ls.block, args, ls.lds, s);
 }
+// The same with the kernel's own start and stop times recorded into two
+// events (timestamps of the dispatch itself, no marker packets around it).
+inline hipError_t launch_timed(const LaunchSpec& ls, const FrameDesc& f, hipStream_t s, hipEvent_t start,
+                               hipEvent_t stop) {
+    if (!ls.func) return hipErrorInvalidValue;
+    FrameDesc arg = f;
+    void* args[] = {&arg};
+    return hipExtLaunchKernel(ls.func, ls.grid, ls.block, args, ls.lds, s, start, stop, 0);
+}
 size_t regions_lds_bytes(int nb);
 hipError_t prepare_depth_kernels();
 hipError_t prepare_render_kernels();
 
-// Accessors of the opaque context for the other C ABI files.
+// Accessors of the opaque context for the other C ABI files: its device, the
+// batch object it keeps for pstereo_synthesize_batch, and its last-error text.
 int ctx_device(const pstereo_ctx* c);
-hipStream_t ctx_stream(const pstereo_ctx* c);
+pstereo_batch** ctx_batch(pstereo_ctx* c);
+void ctx_set_error(pstereo_ctx* c, const char* msg);
 
 }  // namespace pstereo

@@ -28,6 +28,7 @@ PSTEREO_SYNC = 0x2
 PSTEREO_PROFILE = 0x4
 PSTEREO_WARP_GATHER = 0x8
 PSTEREO_INPAINT_BLOCKS = 0x10
+PSTEREO_PIPELINE = 0x20
 
 PSTEREO_MAX_BLOCKS = 32768
 
@@ -47,7 +48,7 @@ EXPORTED = [
     "pstereo_last_error", "pstereo_debug_blocks", "pstereo_profile_collect",
     "pstereo_video_begin", "pstereo_video_frame", "pstereo_video_end",
     "pstereo_batch_create", "pstereo_batch_prepare", "pstereo_batch_launch", "pstereo_batch_run",
-    "pstereo_batch_destroy", "pstereo_batch_last_error",
+    "pstereo_batch_destroy", "pstereo_batch_last_error", "pstereo_synthesize_batch",
     "pstereo_batch_set_tuning", "pstereo_batch_get_tuning", "pstereo_batch_autotune",
     "pstereo_server_create", "pstereo_server_open_stream", "pstereo_server_close_stream",
     "pstereo_server_submit", "pstereo_server_poll", "pstereo_server_drain", "pstereo_server_info",
@@ -166,6 +167,8 @@ def load_library():
     lib.pstereo_batch_destroy.restype = ci
     lib.pstereo_batch_last_error.argtypes = [vp]
     lib.pstereo_batch_last_error.restype = ctypes.c_char_p
+    lib.pstereo_synthesize_batch.argtypes = [vp, J, ci, P]
+    lib.pstereo_synthesize_batch.restype = ci
     T = ctypes.POINTER(PstereoBatchTuning)
     lib.pstereo_batch_set_tuning.argtypes = [vp, T]
     lib.pstereo_batch_set_tuning.restype = ci
@@ -330,6 +333,13 @@ def pstereo_batch_run(b: int, jobs, n: int, params: Optional[PstereoParams], che
 
 def pstereo_batch_destroy(b: int) -> int:
     return load_library().pstereo_batch_destroy(b)
+
+
+def pstereo_synthesize_batch(ctx: int, jobs, n: int, params: Optional[PstereoParams], check: bool = True) -> int:
+    """Views of ``n`` jobs (a ``make_jobs`` array) in one batched launch with
+    the context's own batch object."""
+    rc = load_library().pstereo_synthesize_batch(ctx, jobs, n, ctypes.byref(params) if params is not None else None)
+    return _check(rc, ctx) if check else rc
 
 
 def pstereo_batch_last_error(b: int) -> str:
