@@ -1,10 +1,11 @@
-"""GPU tests of the launch forms beyond the single call: hipGraph video replay
-(and, as they land, batched and served frames).  Every form must give exactly
-the bytes of the plain per-frame call, which the parity tests tie to the
-oracle."""
+"""GPU tests of the launch forms beyond the single call: hipGraph video
+replay, batched frames (staged and fused forms, the autotuner, the context's
+own batch call).  Every output is compared with the oracle directly, and with
+the plain per-frame call."""
 import numpy as np
 import pytest
 
+import refs
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -50,8 +51,51 @@ def test_video_graph_matches_plain_and_oracle(ctx, oracle_mod, w, h):
         ref = _plain(ctx, f, max_disparity=B)
         for got, want in zip(o, ref):
             assert np.array_equal(got.cpu().numpy(), want), f"frame {i}"
-    ora = oracle_mod.synthesize(spec.frame(20), B)
-    assert np.array_equal(outs[20][2].cpu().numpy(), ora.A)
+        refs.assert_views(o, refs.views(("video", 4, w, h, i), spec.frame(i), B), f"video {w}x{h} frame {i}")
+
+
+def test_video_4k_clip_frames_vs_oracle(ctx):
+    """The 4K clip's replay over 300 frames: frames 0, 149 and 299 of the
+    moving-ellipse clip against the oracle, the frames in between from a bank
+    of four (the graph ring wraps 37 times); every output compared on the
+    device with the plain call's output for the same input."""
+    from paper_2009_09501_amd import pstereo_params_init
+    from paper_2009_09501_amd.pstereo import pstereo_video_begin, pstereo_video_end, pstereo_video_frame
+    dev = torch.device("cuda:0")
+    W, H = 3840, 2160
+    B = synth.default_disparity(W)
+    spec = synth.VideoSpec(4, W, H, frames=300, n=40, sigma=3.0)
+    special = {t: spec.frame(t) for t in (0, 149, 299)}
+    bank_t = [37, 75, 187, 262]
+    dframes = {t: torch.from_numpy(spec.frame(t)).to(dev) for t in bank_t}
+    dframes.update({t: torch.from_numpy(f).to(dev) for t, f in special.items()})
+    seq = [t if t in special else bank_t[t % 4] for t in range(300)]
+    plain = {}
+    for t, f in dframes.items():
+        plain[t] = ctx.synthesize(f, max_disparity=B)
+    torch.cuda.synchronize()
+    p = pstereo_params_init(max_disparity=B)
+    p.stream = torch.cuda.current_stream().cuda_stream
+    v = pstereo_video_begin(ctx.handle, W, H, p)
+    kept = {}
+    try:
+        chunk = 50
+        for c0 in range(0, 300, chunk):
+            outs = [[torch.empty_like(dframes[0]) for _ in range(3)] for _ in range(chunk)]
+            for k in range(chunk):
+                pstereo_video_frame(v, dframes[seq[c0 + k]], *outs[k], ctx=ctx.handle)
+            torch.cuda.synchronize()
+            for k in range(chunk):
+                t = c0 + k
+                for o, pl in zip(outs[k], plain[seq[t]]):
+                    assert torch.equal(o, pl), f"video frame {t} differs from the plain call"
+                if t in special:
+                    kept[t] = [o.cpu() for o in outs[k]]
+            print(f"video 4K frames {c0}..{c0 + chunk - 1} equal the plain call", flush=True)
+    finally:
+        pstereo_video_end(v)
+    for t, f in special.items():
+        refs.assert_views(kept[t], refs.views(("video", 4, W, H, t), f, B), f"4K video frame {t}")
 
 
 def test_video_rejects_external_depth(ctx):
@@ -67,6 +111,11 @@ def _batch_frames(sizes, seed0):
     dev = torch.device("cuda:0")
     host = [synth.gen_frame(seed0 + i, w, h, 20, 4.0) for i, (w, h) in enumerate(sizes)]
     return host, [torch.from_numpy(f).to(dev) for f in host]
+
+
+def _batch_oracle(host, sizes, seed0, **kw):
+    return [refs.views(("batch", seed0 + i, w, h), f, synth.default_disparity(w), **kw)
+            for i, (f, (w, h)) in enumerate(zip(host, sizes))]
 
 
 BATCH_SIZES = [(1920, 1080), (640, 360), (1280, 720), (3840, 2160), (648, 364), (1024, 768), (2560, 1440),
@@ -99,13 +148,36 @@ def test_batch_matches_plain_and_oracle(ctx, oracle_mod, tuning):
         torch.cuda.synchronize()
     finally:
         pstereo_batch_destroy(b)
+    ora = _batch_oracle(host, BATCH_SIZES, 700)
     for i, (f, o) in enumerate(zip(frames, outs)):
+        refs.assert_views(o, ora[i], f"batch ({tuning}) frame {i} {BATCH_SIZES[i]}")
         ref = _plain(ctx, f, max_disparity=synth.default_disparity(f.shape[1]))
         for k, (got, want) in enumerate(zip(o, ref)):
             g = got.cpu().numpy()
             assert np.array_equal(g, want), f"frame {i} {BATCH_SIZES[i]} output {k}: {(g != want).any(-1).sum()} px"
-    ora = oracle_mod.synthesize(host[1], synth.default_disparity(640))
-    assert np.array_equal(outs[1][0].cpu().numpy(), ora.L)
+
+
+@pytest.mark.parametrize("K", [2, 0])
+def test_synthesize_batch_call(ctx, K):
+    """pstereo_synthesize_batch (the context's own batch object, grown on
+    demand) against the oracle, twice: a small batch, then a larger one that
+    makes the context grow its object; K = 2 runs every frame with blocks of
+    2 px (small frames: at most 32768 blocks), K = 0 the automatic size."""
+    from paper_2009_09501_amd import pstereo_params_init
+    from paper_2009_09501_amd.pstereo import PSTEREO_SYNC, make_jobs, pstereo_synthesize_batch
+    if K == 2:
+        rounds = [[(320, 240), (64, 48)], [(360, 360), (128, 96), (200, 100)]]
+    else:
+        rounds = [[(640, 360), (1280, 720)], [(1920, 1080), (640, 360), (3840, 2160), (2560, 1440)]]
+    for r, sizes in enumerate(rounds):
+        seed0 = 1500 + 20 * r + K
+        host, frames = _batch_frames(sizes, seed0)
+        outs = [[torch.zeros_like(f) for _ in range(3)] for f in frames]
+        p = pstereo_params_init(block_size=K, flags=PSTEREO_SYNC)
+        print(f"synthesize_batch K={K} round {r}: {sizes}", flush=True)
+        pstereo_synthesize_batch(ctx.handle, make_jobs(frames, outs), len(frames), p)
+        for i, (o, want) in enumerate(zip(outs, _batch_oracle(host, sizes, seed0, K=K))):
+            refs.assert_views(o, want, f"synthesize_batch K={K} round {r} frame {i} {sizes[i]}")
 
 
 @pytest.mark.parametrize("tuning", ["staged", "fused"])
@@ -114,9 +186,9 @@ def test_batch_relaunch_and_graph_replay(ctx, tuning):
     from paper_2009_09501_amd.pstereo import (make_jobs, pstereo_batch_create, pstereo_batch_destroy,
                                               pstereo_batch_launch, pstereo_batch_prepare, pstereo_batch_set_tuning)
     sizes = [(1280, 720), (640, 360), (1920, 1080)]
-    _, frames = _batch_frames(sizes, 900)
+    host, frames = _batch_frames(sizes, 900)
     outs = [[torch.zeros_like(f) for _ in range(3)] for f in frames]
-    refs = [_plain(ctx, f, max_disparity=synth.default_disparity(f.shape[1])) for f in frames]
+    ora = _batch_oracle(host, sizes, 900)
     b = pstereo_batch_create(ctx.handle, 4, sum(w * h for w, h in sizes))
     s = torch.cuda.Stream()
     try:
@@ -132,9 +204,8 @@ def test_batch_relaunch_and_graph_replay(ctx, tuning):
             torch.cuda.synchronize()
             pstereo_batch_launch(b, s)
             s.synchronize()
-            for o, r in zip(outs, refs):
-                for got, want in zip(o, r):
-                    assert np.array_equal(got.cpu().numpy(), want), f"relaunch {rep}"
+            for i, (o, r) in enumerate(zip(outs, ora)):
+                refs.assert_views(o, r, f"relaunch {rep} frame {i}")
         # captured into a HIP graph (through torch's graph API) and replayed
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
@@ -146,9 +217,8 @@ def test_batch_relaunch_and_graph_replay(ctx, tuning):
             torch.cuda.synchronize()
             g.replay()
             torch.cuda.synchronize()
-            for o, r in zip(outs, refs):
-                for got, want in zip(o, r):
-                    assert np.array_equal(got.cpu().numpy(), want), f"graph replay {rep}"
+            for i, (o, r) in enumerate(zip(outs, ora)):
+                refs.assert_views(o, r, f"graph replay {rep} frame {i}")
     finally:
         torch.cuda.synchronize()
         pstereo_batch_destroy(b)
@@ -160,8 +230,8 @@ def test_batch_autotune_picks_a_candidate_and_stays_exact(ctx):
                                               pstereo_batch_destroy, pstereo_batch_get_tuning,
                                               pstereo_batch_launch)
     sizes = [(1280, 720), (640, 360), (1920, 1080), (2560, 1440)]
-    _, frames = _batch_frames(sizes, 950)
-    refs = [_plain(ctx, f, max_disparity=synth.default_disparity(f.shape[1])) for f in frames]
+    host, frames = _batch_frames(sizes, 950)
+    ora = _batch_oracle(host, sizes, 950)
     outs = [[torch.zeros_like(f) for _ in range(3)] for f in frames]
     s = torch.cuda.Stream()
     b = pstereo_batch_create(ctx.handle, 4, sum(w * h for w, h in sizes))
@@ -180,9 +250,8 @@ def test_batch_autotune_picks_a_candidate_and_stays_exact(ctx):
         torch.cuda.synchronize()
         pstereo_batch_launch(b, s)
         s.synchronize()
-        for o, r in zip(outs, refs):
-            for got, want in zip(o, r):
-                assert np.array_equal(got.cpu().numpy(), want)
+        for i, (o, r) in enumerate(zip(outs, ora)):
+            refs.assert_views(o, r, f"autotuned batch frame {i}")
     finally:
         torch.cuda.synchronize()
         pstereo_batch_destroy(b)

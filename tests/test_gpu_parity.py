@@ -83,7 +83,7 @@ def test_ragged_sizes(ctx, oracle_mod, w, h):
     _check(ctx, oracle_mod, f, min(12, 255), case=f"ragged {w}x{h}")
 
 
-@pytest.mark.parametrize("K", [4, 8, 16, 32, 64])
+@pytest.mark.parametrize("K", [2, 4, 8, 16, 32, 64])
 @pytest.mark.parametrize("r", [0, 1, 2, 3])
 def test_block_sizes_and_radii(ctx, oracle_mod, K, r):
     w, h = 400, 240
@@ -160,12 +160,101 @@ def test_zero_base_identity(ctx):
         assert np.array_equal(got[k], f)
 
 
-def test_deterministic_repeat(ctx):
-    f = synth.gen_frame(21, 1920, 1080, 40, 4.0)
-    a = _run(ctx, f, max_disparity=38)
-    b = _run(ctx, f, max_disparity=38)
-    for k in a:
-        assert np.array_equal(a[k], b[k])
+@pytest.mark.parametrize("w,h,seed", [(1920, 1080, 21), (3840, 2160, 22), (7680, 4320, 23)])
+def test_deterministic_repeat(ctx, w, h, seed):
+    """Three runs of one frame, plain and pipelined, each equal to the
+    oracle (4K and 8K take the two warp row shapes: two and four quads per
+    lane)."""
+    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE
+    import refs
+    f = synth.gen_frame(seed, w, h, 40, 4.0)
+    B = synth.default_disparity(w)
+    want = refs.views(("still", seed, w, h), f, B)
+    dev = torch.device("cuda:0")
+    ft = torch.from_numpy(f).to(dev)
+    for run in range(3):
+        print(f"repeat {w}x{h} run {run}", flush=True)
+        L, R, A = ctx.synthesize(ft, max_disparity=B, flags=PSTEREO_PIPELINE if run == 2 else 0)
+        torch.cuda.synchronize()
+        refs.assert_views((L, R, A), want, f"{w}x{h} run {run}")
+
+
+def test_default_stream_ordering(oracle_mod):
+    """Work on torch's default stream (the HIP null stream): the frame
+    written by a torch kernel just before the call, the outputs read by
+    .cpu() right after it -- no device-wide synchronisation anywhere -- and
+    on a side stream with only that stream's ordering."""
+    from paper_2009_09501_amd import Context
+    import refs
+    dev = torch.device("cuda:0")
+    w, h = 1920, 1080
+    frame = synth.gen_frame(41, w, h, 40, 4.0)
+    want = refs.views(("still", 41, w, h), frame, 38)
+    ctx = Context(0, w, h)
+    try:
+        src = torch.from_numpy(frame).to(dev)
+        for rep in range(3):
+            ft = torch.zeros_like(src)
+            ft.copy_(src)  # a kernel on the default stream writes the frame
+            outs = [torch.full_like(src, 7) for _ in range(3)]
+            ctx.synthesize(ft, out=outs, max_disparity=38)
+            refs.assert_views([o.cpu() for o in outs], want, f"default stream rep {rep}")
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            ft = torch.zeros_like(src)
+            ft.copy_(src)
+            outs = [torch.full_like(src, 7) for _ in range(3)]
+        ctx.synthesize(ft, out=outs, stream=s, max_disparity=38)
+        s.synchronize()
+        refs.assert_views([o.cpu() for o in outs], want, "side stream")
+    finally:
+        ctx.close()
+
+
+def test_pipelined_sequence(oracle_mod):
+    """PSTEREO_PIPELINE over a run of frames of one and of several sizes,
+    mixed with plain calls, a stream change and a block dump: every output
+    equals the oracle."""
+    from paper_2009_09501_amd import Context, pstereo_debug_blocks
+    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE
+    import refs
+    dev = torch.device("cuda:0")
+    sizes = [(1920, 1080), (1920, 1080), (640, 360), (1920, 1080), (1280, 720), (333, 191), (1920, 1080),
+             (1920, 1080)]
+    host = [synth.gen_frame(300 + i, w, h, 40, 4.0) for i, (w, h) in enumerate(sizes)]
+    frames = [torch.from_numpy(f).to(dev) for f in host]
+    ctx = Context(0, 1920, 1080)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        # flags per call: pipelined except calls 3 (plain) and 6 (other stream)
+        outs, streams = [], []
+        for i, (f, (w, h)) in enumerate(zip(frames, sizes)):
+            st = s2 if i == 6 else s1
+            fl = 0 if i == 3 else PSTEREO_PIPELINE
+            print(f"pipelined call {i}: {w}x{h} flags {fl}", flush=True)
+            outs.append(ctx.synthesize(f, stream=st, flags=fl, max_disparity=synth.default_disparity(w)))
+            streams.append(st)
+            if i == 4:
+                st.synchronize()
+                # the block dump of call 4 (pipelined) equals the oracle's
+                stt, lab, db = pstereo_debug_blocks(ctx.handle)
+                ref = oracle_mod.synthesize(host[4], synth.default_disparity(1280))
+                assert np.array_equal(stt, ref.stats) and np.array_equal(lab, ref.labels)
+                assert np.array_equal(db, ref.dblk)
+        torch.cuda.synchronize()
+        for i, ((w, h), f, o) in enumerate(zip(sizes, host, outs)):
+            refs.assert_views(o, refs.views(("pipe", 300 + i, w, h), f, synth.default_disparity(w)), f"call {i}")
+        # a long pipelined run on one stream, outputs checked frame by frame
+        ring = [frames[0], frames[1], frames[3]]
+        res = []
+        for i in range(24):
+            res.append(ctx.synthesize(ring[i % 3], stream=s1, flags=PSTEREO_PIPELINE, max_disparity=38))
+        s1.synchronize()
+        for i, o in enumerate(res):
+            k = [0, 1, 3][i % 3]
+            refs.assert_views(o, refs.views(("pipe", 300 + k, 1920, 1080), host[k], 38), f"run frame {i}")
+    finally:
+        ctx.close()
 
 
 def test_misaligned_buffers(ctx, oracle_mod):
