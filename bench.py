@@ -2,11 +2,15 @@
 
 One step = one 3840x2160 RGB24 frame through the whole per-frame pipeline
 (block statistics, region grouping, raw depth and cross-bilateral filter, both
-warps with hole fill and the anaglyph) with inputs already resident in HBM.
-Prints ONE JSON line with throughput, the HBM roofline fraction of the
-dominant kernel -- the warp, which moves the path's algorithmic bytes (HIP
-events on the launch stream, inside the timed region) -- and the CPU oracle
-timed on a bounded sample of the same workload.
+warps with hole fill and the anaglyph) with inputs already resident in HBM:
+one launch sequence per frame, the depth-map stages of frame i+1 on the
+context's second stream while frame i is filtered and warped
+(PSTEREO_PIPELINE).  Prints ONE JSON line with throughput, the HBM roofline
+fraction of the kernel that moves the path's algorithmic bytes (the warp; its
+duration from its own dispatch timestamps, HIP events taken by the launch
+itself over the timed region), the whole-path roofline fraction, latency from
+a separate loop of single frames, the 1080p rate, the other launch forms, and
+the CPU oracle timed on a bounded sample of the same workloads.
 """
 from __future__ import annotations
 
@@ -14,9 +18,9 @@ import argparse
 import hashlib
 import json
 import os
-import statistics
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -24,11 +28,14 @@ sys.path.insert(0, ROOT)
 METRIC = "4K stereo frames/s + % HBM roofline; p99 frame latency (served vs plain)"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PX = 12  # 3 B read (RGB24) + 9 B written (left, right, anaglyph)
-KERNELS = ["k_blockstats", "k_regions", "k_cbf", "k_warp"]
-# Algorithmic bytes per pixel charged to each kernel: the frame read and the
+STAGES = ["k_blockstats", "k_regions", "k_cbf", "k_warp"]
+# Algorithmic bytes per pixel charged to each stage: the frame read and the
 # three output images; intermediates (block tables, the filtered-depth byte)
 # are not counted.
-KERNEL_BYTES_PER_PX = {"k_blockstats": 3, "k_regions": 0, "k_cbf": 3, "k_warp": 12}
+STAGE_BYTES_PER_PX = {"k_blockstats": 3, "k_regions": 0, "k_cbf": 3, "k_warp": 12}
+# Host threads for generating inputs and for the oracle's row-parallel mode:
+# the CPUs this process may run on, at most 16 (one GPU's share of the host).
+HOST_THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def _kernel_source_sha() -> str:
@@ -55,44 +62,192 @@ def _traffic(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(frames, B, budget_s: float = 12.0, max_frames: int = 60):
-    """The oracle as it stands (single thread, plain C) on a bounded sample."""
-    import oracle
-    oracle.load()
-    n, t0 = 0, time.perf_counter()
-    while n < max_frames and (n == 0 or time.perf_counter() - t0 < budget_s):
-        oracle.synthesize_views(frames[n % len(frames)], B)
-        n += 1
-    dt = time.perf_counter() - t0
-    return {"value": round(n / dt, 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} 3840x2160 frames of the same workload, full pipeline, one thread, {dt:.1f} s"}
-
-
 def _pct(xs, q):
     xs = sorted(xs)
     return xs[min(len(xs) - 1, int(q * len(xs)))]
 
 
-def video_leg(torch, synth, ctx, steps: int, warmup: int, bank: int):
+def _gen_many(fn, args):
+    """fn(*a) for every a in args on the host threads (numpy releases the GIL
+    in the array work), in order."""
+    with ThreadPoolExecutor(HOST_THREADS) as ex:
+        return list(ex.map(lambda a: fn(*a), args))
+
+
+# ----------------------------------------------------------------- CPU oracle
+def cpu_baseline(budget_s: float = 4.0):
+    """The oracle as it stands (plain C, -O2) on the host cores of this run:
+    single thread and row-parallel over HOST_THREADS threads (the
+    row-independent stages split into row bands; outputs asserted equal to
+    the single-thread ones), on the seeded inputs of each workload: 640x360
+    (B = 12), 1080p (B = 38) and 4K (B = 77) stills, and three frames of the
+    4K video (extrapolated to its 300 frames).  ``value`` is the 4K
+    row-parallel rate."""
+    import numpy as np
+
+    import oracle
+    import synth
+    oracle.load()
+    nt = HOST_THREADS
+
+    def timed(fn, frames, B, budget):
+        n, t0 = 0, time.perf_counter()
+        while n < len(frames) * 4 and (n < len(frames) or time.perf_counter() - t0 < budget):
+            fn(frames[n % len(frames)], B)
+            n += 1
+        return n, time.perf_counter() - t0
+
+    work = {
+        "640x360": ([synth.gen_frame(1, 640, 360, 12, 4.0)], 12),
+        "1920x1080": ([synth.gen_frame(2, 1920, 1080, 40, 4.0)], 38),
+        "3840x2160": ([synth.gen_frame(3, 3840, 2160, 40, 4.0)], 77),
+    }
+    spec = synth.VideoSpec(4, 3840, 2160, frames=300, n=40, sigma=3.0)
+    video = _gen_many(spec.frame, [(t,) for t in (0, 149, 299)])
+    res = {}
+    for name, (frames, B) in work.items():
+        st = oracle.synthesize_views(frames[0], B)
+        mt = oracle.synthesize_views_mt(frames[0], B, nt)
+        assert all(np.array_equal(a, b) for a, b in zip(st, mt)), f"{name}: threaded oracle differs"
+        n1, t1 = timed(oracle.synthesize_views, frames, B, budget_s / 2)
+        nm, tm = timed(lambda f, b: oracle.synthesize_views_mt(f, b, nt), frames, B, budget_s / 2)
+        res[name] = {"B": B, "single_thread_fps": round(n1 / t1, 4), "single_thread_frames": n1,
+                     f"threads_{nt}_fps": round(nm / tm, 4), f"threads_{nt}_frames": nm}
+    t0 = time.perf_counter()
+    for f in video:
+        oracle.synthesize_views(f, 77)
+    v1 = (time.perf_counter() - t0) / len(video)
+    t0 = time.perf_counter()
+    for f in video:
+        oracle.synthesize_views_mt(f, 77, nt)
+    vm = (time.perf_counter() - t0) / len(video)
+    res["video_4k_300"] = {"frames_timed": [0, 149, 299], "extrapolated": True,
+                           "single_thread_s_per_clip": round(v1 * 300, 2),
+                           f"threads_{nt}_s_per_clip": round(vm * 300, 2)}
+    k4 = res["3840x2160"]
+    return {"value": k4[f"threads_{nt}_fps"], "unit": "frames/s", "cores": nt, "kind": "oracle",
+            "single_thread_value": k4["single_thread_fps"],
+            "sample": (f"whole frames through the oracle (all stages), single thread and {nt} threads "
+                       f"(row bands), outputs equal; 640x360, 1080p and 4K stills (gen_frame seeds 1, 2, 3) "
+                       f"for about {budget_s / 2:.0f} s each, and 3 frames of the 4K video extrapolated to 300"),
+            "workloads": res}
+
+
+# ------------------------------------------------------------- plain path
+def plain_run(torch, ctx, stream, frames, outs, B, steps, warmup, prewarm_s, every, pipeline):
+    """`warmup` untimed steps (after `prewarm_s` seconds of the same work to
+    bring the clocks up), then `steps` timed steps bracketed by device
+    synchronisation, every `every`-th of them (0 = none) with each kernel's
+    dispatch timestamps recorded (a profiled launch costs the stream some
+    time, so not every step is profiled).  Returns (seconds, per-stage mean
+    ms over the profiled steps or None, their count)."""
+    from paper_2009_09501_amd import PSTEREO_PROFILE, pstereo_profile_collect
+    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE
+    base = PSTEREO_PIPELINE if pipeline else 0
+    nf, no = len(frames), len(outs)
+    # one profiled call first: the library creates its profiling events on
+    # the first profiled call, which must not fall in the timed region
+    ctx.synthesize(frames[0], out=outs[0], stream=stream, flags=base | PSTEREO_PROFILE, max_disparity=B)
+    t_end = time.perf_counter() + prewarm_s
+    i = 0
+    while time.perf_counter() < t_end:
+        ctx.synthesize(frames[i % nf], out=outs[i % no], stream=stream, flags=base, max_disparity=B)
+        i += 1
+        if i % 64 == 0:
+            stream.synchronize()
+    for i in range(warmup):
+        ctx.synthesize(frames[i % nf], out=outs[i % no], stream=stream, flags=base | PSTEREO_PROFILE,
+                       max_disparity=B)
+    torch.cuda.synchronize()
+    pstereo_profile_collect(ctx.handle)  # clear
+    prof = base | PSTEREO_PROFILE
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fl = prof if every and i % every == 0 else base
+        ctx.synthesize(frames[i % nf], out=outs[i % no], stream=stream, flags=fl, max_disparity=B)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if not every:
+        return dt, None, 0
+    ms_sum, count, _ = pstereo_profile_collect(ctx.handle, cap=1)
+    return dt, [m / max(count, 1) for m in ms_sum], count
+
+
+def latency_run(torch, ctx, stream, frames, outs, B, samples):
+    """Each frame alone on an idle stream: GPU time from the first kernel's
+    start to the last kernel's stop, and host time from the call to the end
+    of the stream synchronisation."""
+    from paper_2009_09501_amd import PSTEREO_PROFILE, pstereo_profile_collect
+    torch.cuda.synchronize()
+    pstereo_profile_collect(ctx.handle)
+    host = []
+    for i in range(samples):
+        t0 = time.perf_counter()
+        ctx.synthesize(frames[i % len(frames)], out=outs[i % len(outs)], stream=stream, flags=PSTEREO_PROFILE,
+                       max_disparity=B)
+        stream.synchronize()
+        host.append((time.perf_counter() - t0) * 1e3)
+    _, count, per = pstereo_profile_collect(ctx.handle, cap=samples)
+    return {"samples": count, "gpu_ms": {"p50": round(_pct(per, 0.5), 4), "p99": round(_pct(per, 0.99), 4)},
+            "host_ms": {"p50": round(_pct(host, 0.5), 4), "p99": round(_pct(host, 0.99), 4)},
+            "what": "one frame alone on an idle stream; gpu = first kernel start to last kernel stop, "
+                    "host = call to stream synchronised"}
+
+
+def plain_leg(torch, synth, W, H, B, n_frames, n_outs, steps, warmup, prewarm_s, every, pipeline, seed0):
+    """Frames/s, per-stage kernel times and roofline figures of the plain
+    path at W x H over n_frames distinct inputs and n_outs output triples."""
+    from paper_2009_09501_amd import Context
+    dev = torch.device("cuda:0")
+    seeds = [seed0 + 100 * i for i in range(n_frames)]
+    host = _gen_many(synth.gen_frame, [(s, W, H, 40, 4.0) for s in seeds])
+    frames = [torch.from_numpy(f).to(dev) for f in host]
+    outs = [[torch.empty_like(frames[0]) for _ in range(3)] for _ in range(n_outs)]
+    ctx = Context(0, W, H)
+    stream = torch.cuda.Stream(device=dev)
+    try:
+        dt, stage_ms, count = plain_run(torch, ctx, stream, frames, outs, B, steps, warmup, prewarm_s, every,
+                                        pipeline)
+    finally:
+        torch.cuda.synchronize()
+    px = W * H
+    res = {"fps": round(steps / dt, 2), "ms_per_frame": round(dt / steps * 1e3, 5), "seconds": dt,
+           "working_set_MB": round((n_frames * 3 + n_outs * 9) * px / 1e6, 1),
+           "frames": f"gen_frame seeds {seeds}, 40 shapes, noise sigma 4; {n_outs} output triples cycled",
+           "path_hbm_frac": round(BYTES_PER_PX * px * steps / dt / 1e9 / HBM_PEAK_GBS, 4)}
+    if stage_ms:
+        res["stage_ms"] = {k: round(v, 5) for k, v in zip(STAGES, stage_ms)}
+        res["stage_count"] = count
+        ksum = sum(stage_ms)
+        res["kernel_sum_us"] = round(ksum * 1e3, 3)
+        res["kernel_sum_hbm_frac"] = round(BYTES_PER_PX * px / (ksum / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    return res, ctx, stream, frames, outs
+
+
+# ------------------------------------------------------------------ forms
+def video_leg(torch, synth, steps: int, warmup: int, bank: int, n_outs: int):
     """4K moving-ellipse video through the replayed kernel graphs: a bank of
-    ``bank`` frames spread over the 300-frame clip, cycled."""
-    from paper_2009_09501_amd import pstereo_params_init
+    ``bank`` frames spread over the 300-frame clip, cycled, into ``n_outs``
+    output triples."""
+    from paper_2009_09501_amd import Context, pstereo_params_init
     from paper_2009_09501_amd.pstereo import pstereo_video_begin, pstereo_video_end, pstereo_video_frame
     W, H = 3840, 2160
     spec = synth.VideoSpec(4, W, H, frames=300, n=40, sigma=3.0)
     ts = [round(i * 299 / max(bank - 1, 1)) for i in range(bank)]
     dev = torch.device("cuda:0")
-    frames = [torch.from_numpy(spec.frame(t)).to(dev) for t in ts]
-    outs = [torch.empty_like(frames[0]) for _ in range(3)]
-    stream = torch.cuda.current_stream(dev)
+    frames = [torch.from_numpy(f).to(dev) for f in _gen_many(spec.frame, [(t,) for t in ts])]
+    outs = [[torch.empty_like(frames[0]) for _ in range(3)] for _ in range(n_outs)]
+    ctx = Context(0, W, H)
+    stream = torch.cuda.Stream(device=dev)
     p = pstereo_params_init(max_disparity=synth.default_disparity(W))
     p.stream = stream.cuda_stream
     v = pstereo_video_begin(ctx.handle, W, H, p)
     try:
         for i in range(warmup):
-            pstereo_video_frame(v, frames[i % bank], *outs)
-        # per-frame GPU time on every 8th frame only: an event record costs
-        # stream time, as in the plain leg
+            pstereo_video_frame(v, frames[i % bank], *outs[i % n_outs])
+        # per-frame GPU time on every 8th frame only (an event pair costs
+        # stream time)
         sampled = list(range(0, steps, 8))
         ev = {i: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for i in sampled}
         torch.cuda.synchronize()
@@ -100,40 +255,54 @@ def video_leg(torch, synth, ctx, steps: int, warmup: int, bank: int):
         for i in range(steps):
             if i in ev:
                 ev[i][0].record(stream)
-            pstereo_video_frame(v, frames[i % bank], *outs)
+            pstereo_video_frame(v, frames[i % bank], *outs[i % n_outs])
             if i in ev:
                 ev[i][1].record(stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
     finally:
         pstereo_video_end(v)
+        ctx.close()
     lat = [a.elapsed_time(b) for a, b in ev.values()]
     return {"fps": round(steps / dt, 2), "ms_per_frame": round(dt / steps * 1e3, 4),
             "frame_gpu_ms": {"p50": round(_pct(lat, 0.5), 4), "p99": round(_pct(lat, 0.99), 4)},
-            "pipeline_hbm_frac": round(BYTES_PER_PX * W * H * steps / dt / 1e9 / HBM_PEAK_GBS, 4),
-            "frames": f"VideoSpec(seed 4, 3840x2160, 300 frames, 40 ellipses, sigma 3) frames {ts} cycled"}
+            "path_hbm_frac": round(BYTES_PER_PX * W * H * steps / dt / 1e9 / HBM_PEAK_GBS, 4),
+            "frames": f"VideoSpec(seed 4, 3840x2160, 300 frames, 40 ellipses, sigma 3) frames {ts} cycled "
+                      f"into {n_outs} output triples"}
 
 
-def batch_leg(torch, synth, ctx, steps: int, warmup: int, distinct: int):
-    """64 frames of uneven size (the seeded 720p..8K mix) in one persistent
-    launch, prepared once and launched ``steps`` times."""
-    from paper_2009_09501_amd import pstereo_params_init
+def _batch_inputs(torch, synth, sizes, seed0):
+    """One distinct device frame per job: two generated frames per
+    resolution, each job's a copy of one of them rolled by a seeded offset
+    (distinct content and a distinct buffer for every job)."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    uniq = sorted(set(sizes))
+    args = [(seed0 + 10 * k + j, w, h, 40, 4.0) for k, (w, h) in enumerate(uniq) for j in range(2)]
+    base = {}
+    for a, f in zip(args, _gen_many(synth.gen_frame, args)):
+        base.setdefault((a[1], a[2]), []).append(torch.from_numpy(f).to(dev))
+    rng = np.random.default_rng(seed0)
+    frames = []
+    for i, (w, h) in enumerate(sizes):
+        dy, dx = int(rng.integers(0, h)), int(rng.integers(0, w))
+        frames.append(torch.roll(base[(w, h)][i % 2], shifts=(dy, dx), dims=(0, 1)).contiguous())
+    return frames
+
+
+def batch_leg(torch, synth, steps: int, warmup: int):
+    """64 frames of uneven size (the seeded 720p..8K mix), each its own input
+    buffer, autotuned, then launched ``steps`` times (the winning form)."""
+    from paper_2009_09501_amd import Context, pstereo_params_init
     from paper_2009_09501_amd.pstereo import (make_jobs, pstereo_batch_autotune, pstereo_batch_create,
                                               pstereo_batch_destroy, pstereo_batch_launch)
     sizes = synth.batch_mix_sizes(5, 64)
-    dev = torch.device("cuda:0")
-    bank = {}
-    frames = []
-    for i, (w, h) in enumerate(sizes):
-        lst = bank.setdefault((w, h), [])
-        if len(lst) < distinct:
-            lst.append(torch.from_numpy(synth.gen_frame(10000 + i, w, h, 40, 4.0)).to(dev))
-            frames.append(lst[-1])
-        else:
-            frames.append(lst[i % distinct])
+    frames = _batch_inputs(torch, synth, sizes, 10000)
     outs = [[torch.empty_like(f) for _ in range(3)] for f in frames]
     px = sum(w * h for w, h in sizes)
-    stream = torch.cuda.current_stream(dev)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    ctx = Context(0, 64, 64)
     b = pstereo_batch_create(ctx.handle, len(frames), px)
     try:
         p = pstereo_params_init()
@@ -153,28 +322,29 @@ def batch_leg(torch, synth, ctx, steps: int, warmup: int, distinct: int):
     finally:
         torch.cuda.synchronize()
         pstereo_batch_destroy(b)
+        ctx.close()
     lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
     mps = px * steps / dt / 1e6
-    return {"frames_per_s": round(len(frames) * steps / dt, 2),
+    return {"form": "staged" if best["mode"] == 0 else "fused",
+            "frames_per_s": round(len(frames) * steps / dt, 2),
             "megapixels_per_s": round(mps, 1),
             "fps_4k_equivalent": round(mps / (3840 * 2160 / 1e6), 2),
             "ms_per_batch": round(dt / steps * 1e3, 4),
             "batch_gpu_ms": {"p50": round(_pct(lat, 0.5), 4), "p99": round(_pct(lat, 0.99), 4)},
-            "pipeline_hbm_frac": round(BYTES_PER_PX * px * steps / dt / 1e9 / HBM_PEAK_GBS, 4),
+            "path_hbm_frac": round(BYTES_PER_PX * px * steps / dt / 1e9 / HBM_PEAK_GBS, 4),
             "autotune": {"best": best, "best_ms": round(best_ms, 4),
                          "trials": [dict(t, ms=round(t["ms"], 4)) for t in trials]},
-            "frames": f"64 frames, batch_mix_sizes(seed 5) = {px / 1e6:.1f} MP, "
-                      f"{distinct} distinct gen_frame inputs per resolution"}
+            "frames": f"64 frames, batch_mix_sizes(seed 5) = {px / 1e6:.1f} MP, one input buffer per job "
+                      f"(two gen_frame frames per resolution, each job's rolled by a seeded offset)"}
 
 
 SERVE_SIZES = [(1920, 1080), (3840, 2160), (7680, 4320)]
 
 
-def _serve_run(torch, srv_mod, policy, streams, banks, arrivals, slots, lanes, closed_loop):
+def _serve_run(torch, m, policy, streams, banks, arrivals, slots, lanes, closed_loop):
     """Feed one server the arrival schedule (or, closed_loop, everything at
     once) and return per-request latencies and the span."""
     import numpy as np
-    m = srv_mod
     dev = torch.device("cuda:0")
     srv = m.pstereo_server_create(0, 32 << 30, len(streams), lanes, policy)
     try:
@@ -184,14 +354,12 @@ def _serve_run(torch, srv_mod, policy, streams, banks, arrivals, slots, lanes, c
             rings.append([[torch.empty((h, w, 3), dtype=torch.uint8, device=dev) for _ in range(3)]
                           for _ in range(2 * slots)])
         torch.cuda.synchronize()
-        # warm-up: one frame per stream
         for i, (w, h, _) in enumerate(streams):
             m.pstereo_server_submit(srv, sids[i], banks[(w, h)][0], *rings[i][0])
         m.pstereo_server_drain(srv)
         m.pstereo_server_poll(srv, 4096)
         count = [0] * len(streams)
         t0 = time.perf_counter()
-        base = None
         for t, i in arrivals:
             if not closed_loop:
                 while True:
@@ -202,13 +370,15 @@ def _serve_run(torch, srv_mod, policy, streams, banks, arrivals, slots, lanes, c
             k = count[i]
             count[i] += 1
             w, h, _ = streams[i]
-            rid = m.pstereo_server_submit(srv, sids[i], banks[(w, h)][k % len(banks[(w, h)])],
-                                          *rings[i][k % len(rings[i])])
-            if base is None:
-                base = rid
+            while True:
+                rc, _ = m.pstereo_server_submit(srv, sids[i], banks[(w, h)][k % len(banks[(w, h)])],
+                                                *rings[i][k % len(rings[i])], check=False)
+                if rc != m.PSTEREO_E_BUSY:
+                    break
+                time.sleep(0.0002)
         m.pstereo_server_drain(srv)
         span = time.perf_counter() - t0
-        done = m.pstereo_server_poll(srv, 1 << 16)
+        done = m.pstereo_server_poll(srv, 1 << 17)
     finally:
         m.pstereo_server_destroy(srv)
     lat = {}
@@ -216,7 +386,7 @@ def _serve_run(torch, srv_mod, policy, streams, banks, arrivals, slots, lanes, c
         w, h, _ = streams[c["stream_id"]]
         lat.setdefault(f"{w}x{h}", []).append((c["t_done"] - c["t_submit"]) * 1e3)
     allv = np.concatenate([np.asarray(v) for v in lat.values()])
-    out = {"frames": int(allv.size), "span_s": round(span, 3), "frames_per_s": round(allv.size / span, 1),
+    out = {"frames": int(allv.size), "span_s": round(span, 4), "frames_per_s": round(allv.size / span, 1),
            "latency_ms": {"p50": round(float(np.percentile(allv, 50)), 3),
                           "p99": round(float(np.percentile(allv, 99)), 3)},
            "latency_ms_by_size": {k: {"p50": round(float(np.percentile(v, 50)), 3),
@@ -227,11 +397,13 @@ def _serve_run(torch, srv_mod, policy, streams, banks, arrivals, slots, lanes, c
     return out
 
 
-def serve_leg(torch, synth, duration_s: float, burst: int):
+def serve_leg(torch, synth, duration_s: float, burst: int, compress):
     """Eight synthetic video streams (1080p / 4K / 8K, Poisson arrivals at 30
-    or 60 frames/s each) through the continuous-batching server and through the
-    plain one-frame-at-a-time policy; then a closed-loop burst of ``burst``
-    frames per stream (everything submitted at once) for capacity."""
+    or 60 frames/s each) through the continuous-batching server and through
+    the plain one-frame-at-a-time policy: paced in real time, then with the
+    same arrival schedule compressed k-fold (saturation sweep, until the
+    served rate stops rising), then a closed-loop burst of ``burst`` frames
+    per stream (everything submitted at once)."""
     import numpy as np
 
     from paper_2009_09501_amd import pstereo as m
@@ -245,16 +417,30 @@ def serve_leg(torch, synth, duration_s: float, burst: int):
     for w, h, _ in streams:
         if (w, h) not in banks:
             spec = synth.VideoSpec(20 + w, w, h, frames=300, n=40, sigma=3.0)
-            banks[(w, h)] = [torch.from_numpy(spec.frame(t)).to(dev) for t in (0, 150)]
+            banks[(w, h)] = [torch.from_numpy(f).to(dev) for f in _gen_many(spec.frame, [(t,) for t in (0, 75, 150, 225)])]
     arrivals = []
     for i, (_, _, fps) in enumerate(streams):
         arrivals += [(float(t), i) for t in synth.poisson_arrivals(100 + i, fps, duration_s)]
     arrivals.sort()
     burst_arr = [(0.0, i) for k in range(burst) for i in range(len(streams))]
     res = {"streams": [f"{w}x{h}@{fps}" for w, h, fps in streams], "duration_s": duration_s,
-           "hbm_budget_bytes": 32 << 30}
-    for name, pol, lanes in (("served", m.PSTEREO_SERVE_BATCH, 4), ("plain", m.PSTEREO_SERVE_PLAIN, 1)):
+           "hbm_budget_bytes": 32 << 30, "slots_per_stream": 4}
+    pols = (("served", m.PSTEREO_SERVE_BATCH, 4), ("plain", m.PSTEREO_SERVE_PLAIN, 1))
+    for name, pol, lanes in pols:
         res[name] = _serve_run(torch, m, pol, streams, banks, arrivals, 4, lanes, False)
+    sweep = []
+    for k in compress:
+        row = {"compress": k, "offered_fps": round(len(arrivals) * k / duration_s, 1)}
+        sched = [(t / k, i) for t, i in arrivals]
+        for name, pol, lanes in pols:
+            r = _serve_run(torch, m, pol, streams, banks, sched, 4, lanes, False)
+            row[name] = {"frames_per_s": r["frames_per_s"], "fps_4k_equivalent": r["fps_4k_equivalent"],
+                         "latency_ms": r["latency_ms"], "latency_ms_by_size": r["latency_ms_by_size"]}
+        sweep.append(row)
+        if len(sweep) >= 2 and row["served"]["frames_per_s"] < 1.05 * sweep[-2]["served"]["frames_per_s"]:
+            break
+    res["saturation"] = sweep
+    for name, pol, lanes in pols:
         res[name + "_burst"] = _serve_run(torch, m, pol, streams, banks, burst_arr, 4, lanes, True)
     return res
 
@@ -268,7 +454,7 @@ def host_leg(torch, synth, frames_n: int, lanes: int):
     from paper_2009_09501_amd import pstereo as m
     W, H = 3840, 2160
     spec = synth.VideoSpec(4, W, H, frames=300, n=40, sigma=3.0)
-    bank = [torch.from_numpy(spec.frame(t)).pin_memory() for t in (0, 150)]
+    bank = [torch.from_numpy(f).pin_memory() for f in _gen_many(spec.frame, [(0,), (150,)])]
     ring = 8
     outs = [[torch.empty((H, W, 3), dtype=torch.uint8).pin_memory() for _ in range(3)] for _ in range(ring)]
     res = {"frames": frames_n, "lanes": lanes, "bytes_per_frame": {"h2d": W * H * 3, "d2h": 3 * W * H * 3}}
@@ -292,21 +478,22 @@ def host_leg(torch, synth, frames_n: int, lanes: int):
     finally:
         m.pstereo_server_destroy(srv)
     res["overlapped_fps"] = round(frames_n / dt, 1)
-    # one frame at a time on one stream
     dev = torch.device("cuda:0")
     ctx = Context(0, W, H)
     dfr = torch.empty((H, W, 3), dtype=torch.uint8, device=dev)
     dout = [torch.empty_like(dfr) for _ in range(3)]
-    st = torch.cuda.current_stream(dev)
+    st = torch.cuda.Stream(device=dev)
     B = synth.default_disparity(W)
     n2 = max(frames_n // 2, 4)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(n2):
-        dfr.copy_(bank[k % 2], non_blocking=True)
+        with torch.cuda.stream(st):
+            dfr.copy_(bank[k % 2], non_blocking=True)
         ctx.synthesize(dfr, out=dout, stream=st, max_disparity=B)
-        for o, hbuf in zip(dout, outs[k % ring]):
-            hbuf.copy_(o, non_blocking=True)
+        with torch.cuda.stream(st):
+            for o, hbuf in zip(dout, outs[k % ring]):
+                hbuf.copy_(o, non_blocking=True)
         st.synchronize()
     dt = time.perf_counter() - t0
     ctx.close()
@@ -314,28 +501,66 @@ def host_leg(torch, synth, frames_n: int, lanes: int):
     return res
 
 
+def inpaint_leg(torch, synth, reps: int):
+    """The paper's block-iterative inpainting (PSTEREO_INPAINT_BLOCKS: Jacobi
+    sweeps until one fills nothing, the host checking convergence) against
+    the row fill of the hot path, at 1080p and 4K: time per frame and the
+    pixels where the two fills' views differ.  There is no ground truth for
+    which fill looks better (parity of the two against the oracle is in the
+    tests; their quality relative to each other is unpinned)."""
+    from paper_2009_09501_amd import Context
+    from paper_2009_09501_amd.pstereo import PSTEREO_INPAINT_BLOCKS
+    dev = torch.device("cuda:0")
+    res = {}
+    for (W, H, seed) in ((1920, 1080, 2), (3840, 2160, 3)):
+        B = synth.default_disparity(W)
+        f = torch.from_numpy(synth.gen_frame(seed, W, H, 40, 4.0)).to(dev)
+        ctx = Context(0, W, H)
+        st = torch.cuda.Stream(device=dev)
+        out = {}
+        for name, fl in (("row_fill", 0), ("block_inpaint", PSTEREO_INPAINT_BLOCKS)):
+            o = [torch.empty_like(f) for _ in range(3)]
+            ctx.synthesize(f, out=o, stream=st, flags=fl, max_disparity=B)
+            st.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.synthesize(f, out=o, stream=st, flags=fl, max_disparity=B)
+            st.synchronize()
+            out[name] = ((time.perf_counter() - t0) / reps * 1e3, o)
+        ctx.close()
+        diff = [int((a != b).any(-1).sum().item()) for a, b in zip(out["row_fill"][1], out["block_inpaint"][1])]
+        res[f"{W}x{H}"] = {"row_fill_ms": round(out["row_fill"][0], 4),
+                           "block_inpaint_ms": round(out["block_inpaint"][0], 4),
+                           "pixels_differing": {"left": diff[0], "right": diff[1], "anaglyph": diff[2]},
+                           "frame": f"gen_frame seed {seed}, B = {B}"}
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # steady state: a 30-step warm-up left part of the clock and launch-queue
-    # ramp inside the timed region (about 7 % below the rate of a longer run)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--frames", type=int, default=4, help="distinct synthetic frames cycled")
+    ap.add_argument("--prewarm-ms", type=float, default=300.0,
+                    help="untimed seconds*1e-3 of the same work before the warm-up steps (clock ramp)")
+    ap.add_argument("--frames", type=int, default=8, help="distinct synthetic 4K frames cycled")
+    ap.add_argument("--outs", type=int, default=4, help="output triples cycled")
     ap.add_argument("--profile-every", type=int, default=16,
-                    help="record per-stage HIP events on every N-th timed step")
+                    help="record each kernel's dispatch timestamps on every N-th timed step (0 = never)")
+    ap.add_argument("--serial", action="store_true", help="headline without PSTEREO_PIPELINE")
+    ap.add_argument("--latency-samples", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="video,batch,serve,host",
-                    help="extra launch forms measured after the plain path (video, batch, serve, host; "
-                         "empty = none)")
+    ap.add_argument("--forms", default="serial,1080p,video,batch,serve,host,inpaint",
+                    help="extra measurements after the headline (serial, 1080p, video, batch, serve, host, "
+                         "inpaint; empty = none)")
     ap.add_argument("--host-frames", type=int, default=120)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (to scale HBM byte counters)")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-burst", type=int, default=16)
+    ap.add_argument("--serve-compress", default="4,16,64,256")
     ap.add_argument("--form-steps", type=int, default=60)
     ap.add_argument("--video-bank", type=int, default=8)
-    ap.add_argument("--batch-distinct", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -343,7 +568,6 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     if args.calibrate_copy:
@@ -359,77 +583,22 @@ def main() -> int:
         return 0
 
     import synth
-    from paper_2009_09501_amd import PSTEREO_PROFILE, Context, pstereo_profile_collect
 
     W, H = 3840, 2160
     B = synth.default_disparity(W)
-    seeds = [3 + 100 * i for i in range(args.frames)]
-    host = [synth.gen_frame(s, W, H, 40, 4.0) for s in seeds]
-    dev = torch.device("cuda:0")
-    frames = [torch.from_numpy(f).to(dev) for f in host]
-    outs = [torch.empty_like(frames[0]) for _ in range(3)]
-    ctx = Context(0, W, H)
-    # a stream of our own (default priority): torch's current stream would
-    # otherwise be the NULL stream, which the library maps to its own stream
-    stream = torch.cuda.Stream(device=dev)
-    torch.cuda.set_stream(stream)
-    params = dict(max_disparity=B)
-
-    for i in range(args.warmup):
-        ctx.synthesize(frames[i % len(frames)], out=outs, stream=stream, **params)
-    torch.cuda.synchronize()
-    pstereo_profile_collect(ctx.handle)  # clear
-    # what an event pair adds to the kernel it brackets, subtracted from the
-    # event-bracketed stage durations: a pair around one tiny kernel, less
-    # that kernel's share of a long back-to-back run of it (one pair around
-    # 256 launches)
-    tiny = torch.zeros(1, dtype=torch.int32, device=dev)
-    for _ in range(16):
-        tiny.fill_(1)
-    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(64)]
-    for a, b in pairs:
-        a.record(stream)
-        tiny.fill_(1)
-        b.record(stream)
-    run0, run1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    run0.record(stream)
-    for _ in range(256):
-        tiny.fill_(1)
-    run1.record(stream)
-    torch.cuda.synchronize()
-    ev_overhead_ms = max(statistics.median(a.elapsed_time(b) for a, b in pairs) - run0.elapsed_time(run1) / 256,
-                         0.0)
-
-    # per-stage HIP events on every `sample`-th timed step: each event record
-    # adds a few microseconds of stream time, so recording them on every step
-    # would slow the throughput being measured
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        fl = PSTEREO_PROFILE if i % args.profile_every == 0 else 0
-        ctx.synthesize(frames[i % len(frames)], out=outs, stream=stream, flags=fl, **params)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_sum, count, per_call = pstereo_profile_collect(ctx.handle)
-
-    fps = args.steps / dt
     px = W * H
-    kern_s = {k: ms_sum[i] / count / 1e3 for i, k in enumerate(KERNELS)}
-    # the roofline kernel: the one that moves the path's algorithmic bytes
-    # (the warp: frame in, three views out).  The depth filter runs about as
-    # long but is bound by VALU issue, not HBM (SQ counters in profiles/);
-    # the longest stage is reported beside it
-    dom = "k_warp"
-    longest = max(kern_s, key=kern_s.get)
-    dom_s = max(kern_s[dom] - ev_overhead_ms / 1e3, 1e-9)
-    achieved = KERNEL_BYTES_PER_PX[dom] * px / dom_s / 1e9
-    pipe_s = sum(ms_sum) / count / 1e3
-    lat = sorted(per_call)
-    traffic = _traffic(dom, "4k")
+    every = args.profile_every
+    pipeline = not args.serial
+    head, ctx, stream, frames, outs = plain_leg(torch, synth, W, H, B, args.frames, args.outs, args.steps,
+                                                args.warmup, args.prewarm_ms / 1e3, every, pipeline, 3)
+    lat = latency_run(torch, ctx, stream, frames, outs, B, args.latency_samples)
+    ctx.close()
+    del frames, outs
+    dt = head.pop("seconds")
 
     out = {
         "metric": METRIC,
-        "value": round(fps, 2),
+        "value": head["fps"],
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -440,39 +609,65 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": "4K 3840x2160 RGB24 single frames, plain per-frame launch "
-                               "(blockstats, regions, cbf, warp), max disparity 77 px",
-                   "frames": f"gen_frame seeds {seeds}, 40 shapes, noise sigma 4",
-                   "path": "plain"},
-        "roofline": {"bound": "hbm", "kernel": dom,
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "duration_us": round(dom_s * 1e6, 3), "event_overhead_us": round(ev_overhead_ms * 1e3, 3),
-                     "bytes_per_launch": KERNEL_BYTES_PER_PX[dom] * px,
-                     "longest_kernel": longest},
-        "kernels_ms": {k: round(v * 1e3, 5) for k, v in kern_s.items()},
-        "kernels_hbm_frac": {k: round(KERNEL_BYTES_PER_PX[k] * px / v / 1e9 / HBM_PEAK_GBS, 4)
-                             for k, v in kern_s.items()},
-        "pipeline_hbm_frac": round(BYTES_PER_PX * px / pipe_s / 1e9 / HBM_PEAK_GBS, 4),
-        "latency_ms": {"p50": round(statistics.median(lat), 4),
-                       "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4)},
+        "config": {"workload": "4K 3840x2160 RGB24 single frames, plain per-frame launch sequence "
+                               "(blockstats, region grouping, cbf, warp), max disparity 77 px",
+                   "frames": head["frames"], "working_set_MB": head["working_set_MB"],
+                   "path": ("plain, pipelined: frame i+1's block statistics and region grouping on the "
+                            "context's second stream during frame i's filter and warp (PSTEREO_PIPELINE)")
+                   if pipeline else "plain, serial (one stream)",
+                   "prewarm_ms": args.prewarm_ms},
     }
+    if head.get("stage_ms"):
+        st = head["stage_ms"]
+        dom = "k_warp"
+        dom_s = st[dom] / 1e3
+        achieved = STAGE_BYTES_PER_PX[dom] * px / dom_s / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": _traffic(dom, "4k"), "duration_us": round(dom_s * 1e6, 3),
+                           "duration_from": "the kernel's own dispatch start/stop timestamps (HIP events "
+                                            f"attached to its launch), mean over every {every}-th timed step",
+                           "bytes_per_launch": STAGE_BYTES_PER_PX[dom] * px,
+                           "longest_kernel": max(st, key=st.get)}
+        out["kernels_ms"] = st
+        out["kernels_hbm_frac"] = {k: round(STAGE_BYTES_PER_PX[k] * px / (v / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                                   for k, v in st.items()}
+    out["roofline_path"] = {"bytes_per_frame": BYTES_PER_PX * px, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac_by_step_time": head["path_hbm_frac"],
+                            "kernel_sum_us": head.get("kernel_sum_us"),
+                            "frac_by_kernel_sum": head.get("kernel_sum_hbm_frac")}
+    out["latency_ms"] = {"p50": lat["gpu_ms"]["p50"], "p99": lat["gpu_ms"]["p99"]}
+    out["latency"] = lat
     forms = [f for f in args.forms.split(",") if f]
-    if forms:
-        out["forms"] = {}
+    out["forms"] = {}
+    if "serial" in forms and pipeline:
+        r, c, _, _, _ = plain_leg(torch, synth, W, H, B, args.frames, args.outs, args.steps, 30,
+                                  args.prewarm_ms / 1e3, every, False, 3)
+        c.close()
+        r.pop("seconds")
+        out["forms"]["plain_serial_4k"] = r
+    if "1080p" in forms:
+        r, c, s, f, o = plain_leg(torch, synth, 1920, 1080, 38, args.frames, args.outs, 2 * args.steps, 100,
+                                  args.prewarm_ms / 1e3, every, pipeline, 2)
+        r["latency"] = latency_run(torch, c, s, f, o, 38, args.latency_samples)
+        c.close()
+        del f, o
+        r.pop("seconds")
+        out["forms"]["plain_1080p"] = r
     if "video" in forms:
-        out["forms"]["video_graph_4k"] = video_leg(torch, synth, ctx, args.form_steps * 5, 10, args.video_bank)
+        out["forms"]["video_graph_4k"] = video_leg(torch, synth, args.form_steps * 5, 10, args.video_bank, 4)
     if "batch" in forms:
-        out["forms"]["batch_uneven_64"] = batch_leg(torch, synth, ctx, args.form_steps, 3, args.batch_distinct)
+        out["forms"]["batch_uneven_64"] = batch_leg(torch, synth, args.form_steps // 2, 3)
     if "serve" in forms:
-        out["forms"]["serve_8_streams"] = serve_leg(torch, synth, args.serve_seconds, args.serve_burst)
+        comp = [float(x) for x in args.serve_compress.split(",") if x]
+        out["forms"]["serve_8_streams"] = serve_leg(torch, synth, args.serve_seconds, args.serve_burst, comp)
     if "host" in forms:
         out["forms"]["host_pinned_4k"] = host_leg(torch, synth, args.host_frames, 3)
+    if "inpaint" in forms:
+        out["forms"]["inpaint_vs_row_fill"] = inpaint_leg(torch, synth, 5)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(host, B)
-    ctx.close()
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
-    _ = np
     return 0
 
 
