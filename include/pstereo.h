@@ -201,6 +201,30 @@ int pstereo_profile_collect(pstereo_ctx *ctx, double ms_sum[4], int *count,
                             double *per_call_ms, int cap);
 
 /*
+ * pstereo_synthesize_noalloc: pstereo_synthesize without a context, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Its scratch (one
+ * set of block tables and one filtered-depth image, about 9 MB) is a static
+ * device array that each GPU the library runs on holds until the process
+ * ends; the first call on a device takes that array's address there.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library call):
+ *   device       HIP device of the frame and outputs (0..63)
+ *   frame, w, h, p, out_left, out_right, out_anaglyph: as pstereo_synthesize,
+ *                with w * h <= PSTEREO_NOALLOC_MAX_PIXELS (one 4K frame);
+ *                larger frames return PSTEREO_E_INVALID
+ * PSTEREO_PROFILE, PSTEREO_INPAINT_BLOCKS and PSTEREO_PIPELINE return
+ * PSTEREO_E_UNSUPPORTED (they need a context's events, scratch or stream).
+ * Every call on one GPU shares that GPU's array, whose contents the last call
+ * left: calls that overlap on one GPU (two host threads, or two streams not
+ * ordered with each other) race and must be serialised by the caller.  The
+ * message of a failure is read with pstereo_last_error(NULL) on the calling
+ * thread.
+ */
+#define PSTEREO_NOALLOC_MAX_PIXELS (3840 * 2160)
+int pstereo_synthesize_noalloc(int device, const uint8_t *frame, int w, int h, const pstereo_params *p,
+                               uint8_t *out_left, uint8_t *out_right, uint8_t *out_anaglyph);
+
+/*
  * Video: the frame's launch sequence captured once as a HIP graph and
  * replayed per frame (the paper converts video frame by frame, Section 5;
  * there is no state between frames).  pstereo_video_begin fixes the frame

@@ -38,6 +38,10 @@ __global__ void __launch_bounds__(kStripLanes) k_rg_merge(FrameDesc f) {
 
 __global__ void __launch_bounds__(256) k_rg_final(FrameDesc f) { rg_final_block(f, blockIdx.x * 256 + threadIdx.x); }
 
+__global__ void __launch_bounds__(64) k_clear_words(uint32_t* p, int n) {
+    for (int i = threadIdx.x; i < n; i += 64) p[i] = 0u;
+}
+
 // ---------------------------------------------------------------------------
 // host-side launch helpers
 
@@ -89,6 +93,11 @@ LaunchSpec spec_rg_merge(const FrameDesc& f) {
 
 LaunchSpec spec_rg_final(const FrameDesc& f) {
     return {reinterpret_cast<const void*>(&k_rg_final), dim3((f.gw * f.gh + 255) / 256), dim3(256), 0};
+}
+
+hipError_t launch_clear_words(uint32_t* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
 }
 
 hipError_t prepare_depth_kernels() {

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,7 +23,8 @@ constexpr int kProfSets = 4096;
 constexpr int kMaxKernels = 6;
 constexpr int kProfEvents = 2 * kMaxKernels;
 
-thread_local std::string g_create_error;
+// message of the last failed create or context-free call on this thread
+thread_local char g_create_error[512];
 
 // The per-frame tables of the depth-map stages (block statistics, region
 // grouping) that the filter reads: one set per frame in flight.
@@ -38,28 +40,46 @@ struct BlockScratch {
     uint32_t* rctl = nullptr;
 };
 
-size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+constexpr size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// Byte sizes of the tables of one set, in carving order: statistics, block
+// info, labels, slot entries, slot rows, slot finals, boundary candidates,
+// control words.
+constexpr size_t kBlkTableBytes[8] = {
+    PSTEREO_MAX_BLOCKS * 4, PSTEREO_MAX_BLOCKS * 8, PSTEREO_MAX_BLOCKS * 4, pstereo::kRegionSlots * 8,
+    pstereo::kRegionSlots * 4, pstereo::kRegionSlots * 4, pstereo::kBoundSlots * 8, 4 * 4};
+
+constexpr size_t block_scratch_bytes() {
+    size_t tot = 0;
+    for (size_t b : kBlkTableBytes) tot += align256(b);
+    return tot;
+}
+
+// Lay one set out in `mem` (block_scratch_bytes() bytes, 256-byte aligned).
+void block_scratch_carve(BlockScratch& b, uint8_t* mem) {
+    size_t off[8], tot = 0;
+    for (int i = 0; i < 8; ++i) {
+        off[i] = tot;
+        tot += align256(kBlkTableBytes[i]);
+    }
+    b.mem = mem;
+    b.stats = reinterpret_cast<uint32_t*>(mem + off[0]);
+    b.binfo = reinterpret_cast<uint2*>(mem + off[1]);
+    b.labels = reinterpret_cast<int32_t*>(mem + off[2]);
+    b.rent = reinterpret_cast<uint2*>(mem + off[3]);
+    b.rrow = reinterpret_cast<uint32_t*>(mem + off[4]);
+    b.rfin = reinterpret_cast<uint32_t*>(mem + off[5]);
+    b.rbnd = reinterpret_cast<uint2*>(mem + off[6]);
+    b.rctl = reinterpret_cast<uint32_t*>(mem + off[7]);
+}
 
 // Allocate and carve one set; the control words start at zero (the merge
 // kernel leaves them zero after each frame).
 hipError_t block_scratch_alloc(BlockScratch& b) {
-    const size_t nb = PSTEREO_MAX_BLOCKS, ns = pstereo::kRegionSlots, nd = pstereo::kBoundSlots;
-    const size_t sz[8] = {nb * 4, nb * 8, nb * 4, ns * 8, ns * 4, ns * 4, nd * 8, 4 * 4};
-    size_t off[8], tot = 0;
-    for (int i = 0; i < 8; ++i) {
-        off[i] = tot;
-        tot += align256(sz[i]);
-    }
-    hipError_t e = hipMalloc(&b.mem, tot);
+    uint8_t* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, block_scratch_bytes());
     if (e != hipSuccess) return e;
-    b.stats = reinterpret_cast<uint32_t*>(b.mem + off[0]);
-    b.binfo = reinterpret_cast<uint2*>(b.mem + off[1]);
-    b.labels = reinterpret_cast<int32_t*>(b.mem + off[2]);
-    b.rent = reinterpret_cast<uint2*>(b.mem + off[3]);
-    b.rrow = reinterpret_cast<uint32_t*>(b.mem + off[4]);
-    b.rfin = reinterpret_cast<uint32_t*>(b.mem + off[5]);
-    b.rbnd = reinterpret_cast<uint2*>(b.mem + off[6]);
-    b.rctl = reinterpret_cast<uint32_t*>(b.mem + off[7]);
+    block_scratch_carve(b, mem);
     return hipMemset(b.rctl, 0, 4 * sizeof(uint32_t));
 }
 
@@ -86,7 +106,7 @@ struct pstereo_ctx {
     uint32_t* d_ipn = nullptr;
     uint32_t* h_ipn = nullptr;  // pinned read-back of one sweep counter
     pstereo_batch* batch = nullptr;  // pstereo_synthesize_batch's batch object, made on first use
-    std::string err;
+    char err[512] = {0};  // message of the last failure
     // last generated-depth call, for pstereo_debug_blocks
     bool have_blocks = false;
     int last_gw = 0, last_gh = 0;
@@ -103,19 +123,17 @@ struct pstereo_ctx {
 namespace pstereo {
 int ctx_device(const pstereo_ctx* c) { return c->device; }
 pstereo_batch** ctx_batch(pstereo_ctx* c) { return &c->batch; }
-void ctx_set_error(pstereo_ctx* c, const char* msg) { c->err = msg ? msg : ""; }
+void ctx_set_error(pstereo_ctx* c, const char* msg) { snprintf(c->err, sizeof c->err, "%s", msg ? msg : ""); }
 }  // namespace pstereo
 
 namespace {
 
 int fail(pstereo_ctx* c, int code, const char* fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    if (c) vsnprintf(c->err, sizeof c->err, fmt, ap);
+    else vsnprintf(g_create_error, sizeof g_create_error, fmt, ap);
     va_end(ap);
-    if (c) c->err = buf;
-    else g_create_error = buf;
     return code;
 }
 
@@ -174,7 +192,7 @@ int pstereo_params_init(pstereo_params* p) {
 }
 
 int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
-    g_create_error.clear();
+    g_create_error[0] = '\0';
     if (!out) return fail(nullptr, PSTEREO_E_INVALID, "out is NULL");
     *out = nullptr;
     if (max_w < 1 || max_w > 65535 || max_h < 1 || max_h > 65535)
@@ -237,7 +255,7 @@ int pstereo_destroy(pstereo_ctx* c) {
 }
 
 const char* pstereo_last_error(const pstereo_ctx* c) {
-    return c ? c->err.c_str() : g_create_error.c_str();
+    return c ? c->err : g_create_error;
 }
 
 }  // extern "C"
@@ -387,7 +405,7 @@ extern "C" {
 int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const pstereo_params* pin,
                        uint8_t* out_l, uint8_t* out_r, uint8_t* out_a) {
     if (!c) return PSTEREO_E_INVALID;
-    c->err.clear();
+    c->err[0] = '\0';
     FrameDesc f;
     WarpShape ws{};
     hipStream_t s;
@@ -543,7 +561,7 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
 int pstereo_debug_blocks(pstereo_ctx* c, uint32_t* stats, int32_t* labels, uint8_t* dblk, int cap, int* gw,
                          int* gh) {
     if (!c) return PSTEREO_E_INVALID;
-    c->err.clear();
+    c->err[0] = '\0';
     if (!c->have_blocks) return fail(c, PSTEREO_E_INVALID, "no generated-depth synthesis yet");
     const int nb = c->last_gw * c->last_gh;
     if (gw) *gw = c->last_gw;
@@ -574,7 +592,7 @@ int pstereo_debug_blocks(pstereo_ctx* c, uint32_t* stats, int32_t* labels, uint8
 
 int pstereo_profile_collect(pstereo_ctx* c, double ms_sum[4], int* count, double* per_call_ms, int cap) {
     if (!c || !ms_sum || !count) return PSTEREO_E_INVALID;
-    c->err.clear();
+    c->err[0] = '\0';
     ms_sum[0] = ms_sum[1] = ms_sum[2] = ms_sum[3] = 0.0;
     *count = 0;
     if (c->prof_head == 0) return PSTEREO_OK;
@@ -664,7 +682,7 @@ static hipKernelNodeParams node_params(const pstereo::LaunchSpec& ls, void** arg
 
 int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, pstereo_video** out) {
     if (!c) return PSTEREO_E_INVALID;
-    c->err.clear();
+    c->err[0] = '\0';
     if (!out) return fail(c, PSTEREO_E_INVALID, "out is NULL");
     *out = nullptr;
     pstereo_params pp;
@@ -723,7 +741,7 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
 int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, uint8_t* out_r, uint8_t* out_a) {
     if (!v) return PSTEREO_E_INVALID;
     pstereo_ctx* c = v->ctx;
-    c->err.clear();
+    c->err[0] = '\0';
     FrameDesc f;
     WarpShape ws{};
     hipStream_t s;
@@ -787,3 +805,101 @@ int pstereo_video_end(pstereo_video* v) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ no-alloc call
+// pstereo_synthesize_noalloc: the plain call with its scratch (one set of
+// block tables and the filtered depth of a frame of up to
+// PSTEREO_NOALLOC_MAX_PIXELS pixels) in a file-scope device array, so that a
+// call allocates nothing.  Each GPU the library runs on holds its own copy of
+// the array until the process ends; host code reaches it only through the
+// device address hipGetSymbolAddress gives on that device.
+namespace {
+
+constexpr size_t kNoAllocBytes = block_scratch_bytes() + align256(PSTEREO_NOALLOC_MAX_PIXELS);
+constexpr int kNoAllocDevices = 64;
+
+__device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+struct NoAllocDevice {
+    std::mutex mu;
+    bool ready = false;
+    uint8_t* ptr = nullptr;  // this device's address of `scratch`
+    pstereo_ctx ctx;         // sizes, device and the scratch carved from ptr
+};
+
+NoAllocDevice g_noalloc[kNoAllocDevices];
+
+// Once per device, with the device current: its address of the array, and
+// the kernels' launch attributes.
+int noalloc_setup(int device, NoAllocDevice** out) {
+    if (device < 0 || device >= kNoAllocDevices)
+        return fail(nullptr, PSTEREO_E_INVALID, "device %d outside 0..%d", device, kNoAllocDevices - 1);
+    NoAllocDevice& d = g_noalloc[device];
+    std::lock_guard<std::mutex> g(d.mu);
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(nullptr, PSTEREO_E_INVALID, "device %d not available: %s", device, hipGetErrorString(e));
+    }
+    if (!d.ready) {
+        void* ptr = nullptr;
+        if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(nullptr, PSTEREO_E_DEVICE, "static scratch address on device %d: %s", device,
+                        hipGetErrorString(e));
+        }
+        if ((e = pstereo::prepare_depth_kernels()) != hipSuccess || (e = pstereo::prepare_render_kernels()) != hipSuccess)
+            return fail(nullptr, PSTEREO_E_DEVICE, "device setup failed: %s", hipGetErrorString(e));
+        d.ptr = static_cast<uint8_t*>(ptr);
+        d.ctx.device = device;
+        d.ctx.max_w = 65535;
+        d.ctx.max_h = 65535;
+        block_scratch_carve(d.ctx.blk[0], d.ptr);
+        d.ctx.d_df = d.ptr + block_scratch_bytes();
+        d.ready = true;
+    }
+    *out = &d;
+    return PSTEREO_OK;
+}
+
+}  // namespace
+
+extern "C" int pstereo_synthesize_noalloc(int device, const uint8_t* frame, int w, int h, const pstereo_params* pin,
+                                          uint8_t* out_l, uint8_t* out_r, uint8_t* out_a) {
+    g_create_error[0] = '\0';
+    NoAllocDevice* d = nullptr;
+    int rc = noalloc_setup(device, &d);
+    if (rc != PSTEREO_OK) return rc;
+    if (pin && pin->struct_size == sizeof(pstereo_params) &&
+        (pin->flags & (PSTEREO_PROFILE | PSTEREO_INPAINT_BLOCKS | PSTEREO_PIPELINE)))
+        return fail(nullptr, PSTEREO_E_UNSUPPORTED,
+                    "PSTEREO_PROFILE, PSTEREO_INPAINT_BLOCKS and PSTEREO_PIPELINE need a context");
+    if (w < 1 || h < 1 || (int64_t)w * h > (int64_t)PSTEREO_NOALLOC_MAX_PIXELS)
+        return fail(nullptr, PSTEREO_E_INVALID, "frame %dx%d outside 1..%d pixels of the static scratch", w, h,
+                    PSTEREO_NOALLOC_MAX_PIXELS);
+    std::lock_guard<std::mutex> g(d->mu);  // the per-device descriptor state
+    pstereo_ctx* c = &d->ctx;
+    FrameDesc f;
+    WarpShape ws{};
+    hipStream_t s;
+    uint32_t flags;
+    rc = build_desc(c, frame, w, h, pin, out_l, out_r, out_a, &f, &ws, &s, &flags);
+    if (rc != PSTEREO_OK) {
+        snprintf(g_create_error, sizeof g_create_error, "%s", c->err);
+        return rc;
+    }
+    hipError_t e = hipSetDevice(device);
+    // the grouping's control words start at zero on every call: an earlier
+    // call on this GPU may have stopped between its strips and its merge
+    if (e == hipSuccess && !f.depth_in) e = pstereo::launch_clear_words(f.rctl, 4, s);
+    if (e != hipSuccess) return fail(nullptr, PSTEREO_E_DEVICE, "launch: %s", hipGetErrorString(e));
+    pstereo::LaunchSpec ls[kMaxSpecs];
+    int n;
+    frame_specs(f, ws, ls, n);
+    for (int i = 0; i < n; ++i)
+        if ((e = pstereo::launch(ls[i], f, s)) != hipSuccess)
+            return fail(nullptr, PSTEREO_E_DEVICE, "launch: %s", hipGetErrorString(e));
+    if ((flags & PSTEREO_SYNC) && (e = hipStreamSynchronize(s)) != hipSuccess)
+        return fail(nullptr, PSTEREO_E_DEVICE, "stream synchronize: %s", hipGetErrorString(e));
+    return PSTEREO_OK;
+}

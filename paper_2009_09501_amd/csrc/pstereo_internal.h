@@ -103,6 +103,8 @@ inline hipError_t launch_timed(const LaunchSpec& ls, const FrameDesc& f, hipStre
     return hipExtLaunchKernel(ls.func, ls.grid, ls.block, args, ls.lds, s, start, stop, 0);
 }
 size_t regions_lds_bytes(int nb);
+// Zero n words with a kernel (no memset node, so it can sit in a captured graph).
+hipError_t launch_clear_words(uint32_t* p, int n, hipStream_t s);
 hipError_t prepare_depth_kernels();
 hipError_t prepare_render_kernels();
 

@@ -49,6 +49,7 @@ EXPORTED = [
     "pstereo_video_begin", "pstereo_video_frame", "pstereo_video_end",
     "pstereo_batch_create", "pstereo_batch_prepare", "pstereo_batch_launch", "pstereo_batch_run",
     "pstereo_batch_destroy", "pstereo_batch_last_error", "pstereo_synthesize_batch",
+    "pstereo_synthesize_noalloc",
     "pstereo_batch_set_tuning", "pstereo_batch_get_tuning", "pstereo_batch_autotune",
     "pstereo_server_create", "pstereo_server_open_stream", "pstereo_server_close_stream",
     "pstereo_server_submit", "pstereo_server_poll", "pstereo_server_drain", "pstereo_server_info",
@@ -139,6 +140,8 @@ def load_library():
     lib.pstereo_create.restype = ci
     lib.pstereo_synthesize.argtypes = [vp, vp, ci, ci, P, vp, vp, vp]
     lib.pstereo_synthesize.restype = ci
+    lib.pstereo_synthesize_noalloc.argtypes = [ci, vp, ci, ci, P, vp, vp, vp]
+    lib.pstereo_synthesize_noalloc.restype = ci
     lib.pstereo_destroy.argtypes = [vp]
     lib.pstereo_destroy.restype = ci
     lib.pstereo_last_error.argtypes = [vp]
@@ -240,6 +243,16 @@ def pstereo_synthesize(ctx: int, frame, w: int, h: int, params: Optional[Pstereo
         ctx, _ptr(frame), w, h, ctypes.byref(params) if params is not None else None,
         _ptr(out_left), _ptr(out_right), _ptr(out_anaglyph))
     return _check(rc, ctx) if check else rc
+
+
+def pstereo_synthesize_noalloc(device: int, frame, w: int, h: int, params: Optional[PstereoParams],
+                               out_left, out_right, out_anaglyph, check: bool = True) -> int:
+    """The context-free call whose scratch is the library's static device
+    array (allocates nothing); errors read with pstereo_last_error(None)."""
+    rc = load_library().pstereo_synthesize_noalloc(
+        device, _ptr(frame), w, h, ctypes.byref(params) if params is not None else None,
+        _ptr(out_left), _ptr(out_right), _ptr(out_anaglyph))
+    return _check(rc, None) if check else rc
 
 
 def pstereo_destroy(ctx: int) -> int:
