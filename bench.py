@@ -226,10 +226,11 @@ def plain_leg(torch, synth, W, H, B, n_frames, n_outs, steps, warmup, prewarm_s,
 
 
 # ------------------------------------------------------------------ forms
-def video_leg(torch, synth, steps: int, warmup: int, bank: int, n_outs: int):
-    """4K moving-ellipse video through the replayed kernel graphs: a bank of
-    ``bank`` frames spread over the 300-frame clip, cycled, into ``n_outs``
-    output triples."""
+def video_leg(torch, synth, steps: int, warmup: int, bank: int, n_outs: int, pipeline: bool):
+    """4K moving-ellipse video through the replayed kernel graphs (pipelined:
+    a frame's depth-map graph on the context's second stream during the
+    previous frame's filter and warp): a bank of ``bank`` frames spread over
+    the 300-frame clip, cycled, into ``n_outs`` output triples."""
     from paper_2009_09501_amd import Context, pstereo_params_init
     from paper_2009_09501_amd.pstereo import pstereo_video_begin, pstereo_video_end, pstereo_video_frame
     W, H = 3840, 2160
@@ -240,7 +241,8 @@ def video_leg(torch, synth, steps: int, warmup: int, bank: int, n_outs: int):
     outs = [[torch.empty_like(frames[0]) for _ in range(3)] for _ in range(n_outs)]
     ctx = Context(0, W, H)
     stream = torch.cuda.Stream(device=dev)
-    p = pstereo_params_init(max_disparity=synth.default_disparity(W))
+    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE
+    p = pstereo_params_init(max_disparity=synth.default_disparity(W), flags=PSTEREO_PIPELINE if pipeline else 0)
     p.stream = stream.cuda_stream
     v = pstereo_video_begin(ctx.handle, W, H, p)
     try:
@@ -267,6 +269,7 @@ def video_leg(torch, synth, steps: int, warmup: int, bank: int, n_outs: int):
     return {"fps": round(steps / dt, 2), "ms_per_frame": round(dt / steps * 1e3, 4),
             "frame_gpu_ms": {"p50": round(_pct(lat, 0.5), 4), "p99": round(_pct(lat, 0.99), 4)},
             "path_hbm_frac": round(BYTES_PER_PX * W * H * steps / dt / 1e9 / HBM_PEAK_GBS, 4),
+            "pipelined": pipeline,
             "frames": f"VideoSpec(seed 4, 3840x2160, 300 frames, 40 ellipses, sigma 3) frames {ts} cycled "
                       f"into {n_outs} output triples"}
 
@@ -655,7 +658,9 @@ def main() -> int:
         r.pop("seconds")
         out["forms"]["plain_1080p"] = r
     if "video" in forms:
-        out["forms"]["video_graph_4k"] = video_leg(torch, synth, args.form_steps * 5, 10, args.video_bank, 4)
+        out["forms"]["video_graph_4k"] = video_leg(torch, synth, args.form_steps * 5, 10, args.video_bank, 4, True)
+        out["forms"]["video_graph_4k_serial"] = video_leg(torch, synth, args.form_steps * 5, 10, args.video_bank, 4,
+                                                          False)
     if "batch" in forms:
         out["forms"]["batch_uneven_64"] = batch_leg(torch, synth, args.form_steps // 2, 3)
     if "serve" in forms:

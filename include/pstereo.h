@@ -237,6 +237,14 @@ int pstereo_synthesize_noalloc(int device, const uint8_t *frame, int w, int h, c
  * order on its stream and share the context's scratch, so a context drives
  * one video (or plain calls on the same stream) at a time.
  * pstereo_video_end waits for the stream and frees the graphs.
+ * With PSTEREO_PIPELINE in p->flags each copy is two graphs: the depth-map
+ * stages, replayed on the context's second stream, and the filter and warp,
+ * replayed on the video's stream after them; a frame's depth graph waits
+ * only for what the video's stream held before the previous frame's call,
+ * so it runs during that frame's filter and warp.  The caller then promises
+ * that each frame was complete on the stream (or on the host) before the
+ * previous pstereo_video_frame call was made -- frames are supplied one
+ * ahead, as a decoder does.
  * Errors as for pstereo_synthesize; PSTEREO_E_UNSUPPORTED for the excluded
  * parameters.
  */

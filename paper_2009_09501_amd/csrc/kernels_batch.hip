@@ -149,12 +149,20 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchDesc bd) {
         else if (sg.phase == 1) task_regions(fp, lds);
         else if (sg.phase == 2) task_cbf<R>(fp, k, sg.items, sg.gx, lds);
         else task_warp(fp, k, lds);
-        // publish: every lane's stores reach agent scope, then one release add
-        __threadfence();
-        __syncthreads();
-        if (tid == 0)
-            __hip_atomic_fetch_add(&bd.ctr[1 + 4 * sg.frame + sg.phase], 1u, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        // publish: every lane's stores reach agent scope, then one release
+        // add.  Warp tasks have no dependent task (their outputs are read
+        // after the kernel), so they publish nothing: on this part every
+        // agent-scope release writes the XCD's L2 back, the dominant cost of
+        // a task
+        if (sg.phase < 3) {
+            __threadfence();
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_fetch_add(&bd.ctr[1 + 4 * sg.frame + sg.phase], 1u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __syncthreads();  // the task's LDS is free for the next claim
+        }
     }
 }
 

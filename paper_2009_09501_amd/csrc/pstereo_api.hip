@@ -629,30 +629,39 @@ int pstereo_profile_collect(pstereo_ctx* c, double ms_sum[4], int* count, double
 
 
 // ------------------------------------------------------------------ video
-// The frame's launch sequence as a HIP graph, replayed per frame with the
-// frame and output pointers written into the kernel nodes' arguments.  A
-// small ring of instantiated graphs lets the host prepare frame i+1 while
-// frame i runs; an exec is only updated once its previous replay finished.
-// A ring of kRing instantiated graphs of the frame's launch sequence.  Frame
-// c replays graph c % kRing after rewriting the arguments of the nodes that
-// read the frame and output pointers (the region grouping reads only the
-// context's scratch and keeps its template arguments).  A graph is rewritten
-// only after its previous replay has finished: completion events are
-// recorded after every kEvery-th frame, alternating between two events.
+// The frame's launch sequence as HIP graphs, replayed per frame with the
+// frame and output pointers written into the kernel nodes' arguments.  A ring
+// of kRing instantiated copies lets the host prepare frame n+1 while frame n
+// runs; copy k is rewritten only after its previous replay (frame n - kRing)
+// has finished: completion events are recorded after every kEvery-th frame,
+// alternating between two events.  The region grouping reads only the
+// block tables and keeps its template arguments.
+//
+// Pipelined video (PSTEREO_PIPELINE at begin): each copy is two graphs, the
+// depth-map stages (replayed on the context's side stream) and the filter +
+// warp (on the video's stream, after the depth graph of the same frame), and
+// copy k works in block-table set k % 2; frame n's depth graph waits only for
+// what the video's stream held before frame n-1's call, so it runs during
+// frame n-1's filter and warp.
 struct pstereo_video {
     static constexpr int kRing = 8;
     static constexpr int kEvery = 4;
+    static_assert(kRing % 2 == 0, "ring copy k uses block-table set k % 2");
     pstereo_ctx* ctx = nullptr;
     int w = 0, h = 0;
     pstereo_params params{};
     hipStream_t stream = nullptr;
+    bool pipe = false;
+    bool pipe_started = false;  // the side stream's mark covers the previous frame
     FrameDesc tmpl{};
     WarpShape ws{};
     pstereo::LaunchSpec ls[kMaxSpecs];
+    int stage[kMaxSpecs] = {};
     bool per_frame[kMaxSpecs] = {};  // node i reads the frame / output pointers
+    int gidx[kMaxSpecs] = {};        // node i's graph: 0, or 1 for the filter + warp of a pipelined video
     int nk = 0;
-    hipGraph_t graph[kRing] = {};
-    hipGraphExec_t exec[kRing] = {};
+    hipGraph_t graph[2][kRing] = {};
+    hipGraphExec_t exec[2][kRing] = {};
     hipGraphNode_t node[kRing][kMaxSpecs] = {};
     hipEvent_t done[2] = {};
     long long waited = -1;  // last event group known complete
@@ -660,9 +669,11 @@ struct pstereo_video {
 };
 
 static void video_free(pstereo_video* v) {
-    for (int k = 0; k < pstereo_video::kRing; ++k) {
-        if (v->exec[k]) (void)hipGraphExecDestroy(v->exec[k]);
-        if (v->graph[k]) (void)hipGraphDestroy(v->graph[k]);
+    for (int g = 0; g < 2; ++g) {
+        for (int k = 0; k < pstereo_video::kRing; ++k) {
+            if (v->exec[g][k]) (void)hipGraphExecDestroy(v->exec[g][k]);
+            if (v->graph[g][k]) (void)hipGraphDestroy(v->graph[g][k]);
+        }
     }
     for (int k = 0; k < 2; ++k)
         if (v->done[k]) (void)hipEventDestroy(v->done[k]);
@@ -678,6 +689,21 @@ static hipKernelNodeParams node_params(const pstereo::LaunchSpec& ls, void** arg
     kp.extra = nullptr;
     kp.sharedMemBytes = (unsigned)ls.lds;
     return kp;
+}
+
+// The descriptor of ring copy k: f with the block tables of its set.
+static FrameDesc video_desc(const pstereo_video* v, const FrameDesc& f, int k) {
+    FrameDesc d = f;
+    const BlockScratch& bs = v->ctx->blk[v->pipe ? k % 2 : 0];
+    d.stats = bs.stats;
+    d.binfo = bs.binfo;
+    d.labels = bs.labels;
+    d.rent = bs.rent;
+    d.rrow = bs.rrow;
+    d.rfin = bs.rfin;
+    d.rbnd = bs.rbnd;
+    d.rctl = bs.rctl;
+    return d;
 }
 
 int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, pstereo_video** out) {
@@ -703,6 +729,7 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
     v->w = w;
     v->h = h;
     v->params = pp;
+    v->pipe = (pp.flags & PSTEREO_PIPELINE) != 0;
     uint32_t flags;
     // template descriptor: aligned placeholders stand in for the frame buffers
     // (the graphs run on p->stream, NULL = the HIP null stream)
@@ -715,19 +742,26 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
     v->tmpl.out_l = v->tmpl.out_r = v->tmpl.out_a = nullptr;
     v->tmpl.frame = nullptr;
     v->tmpl.aligned = (w % 4 == 0);
-    int stage[kMaxSpecs];
-    frame_specs(v->tmpl, v->ws, v->ls, v->nk, &stage);
-    for (int i = 0; i < v->nk; ++i) v->per_frame[i] = stage[i] != 1;
+    frame_specs(v->tmpl, v->ws, v->ls, v->nk, &v->stage);
+    for (int i = 0; i < v->nk; ++i) {
+        v->per_frame[i] = v->stage[i] != 1;
+        v->gidx[i] = v->pipe && v->stage[i] >= 2 ? 1 : 0;
+    }
     hipError_t e = hipSetDevice(c->device);
     for (int k = 0; k < pstereo_video::kRing && e == hipSuccess; ++k) {
-        e = hipGraphCreate(&v->graph[k], 0);
-        FrameDesc arg = v->tmpl;
+        FrameDesc arg = video_desc(v, v->tmpl, k);
         void* args[] = {&arg};
+        for (int g = 0; g < (v->pipe ? 2 : 1) && e == hipSuccess; ++g) e = hipGraphCreate(&v->graph[g][k], 0);
+        int prev[2] = {-1, -1};  // last node added to each graph
         for (int i = 0; i < v->nk && e == hipSuccess; ++i) {
+            const int g = v->gidx[i];
             hipKernelNodeParams kp = node_params(v->ls[i], args);
-            e = hipGraphAddKernelNode(&v->node[k][i], v->graph[k], i ? &v->node[k][i - 1] : nullptr, i ? 1 : 0, &kp);
+            hipGraphNode_t* dep = prev[g] >= 0 ? &v->node[k][prev[g]] : nullptr;
+            e = hipGraphAddKernelNode(&v->node[k][i], v->graph[g][k], dep, dep ? 1 : 0, &kp);
+            prev[g] = i;
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&v->exec[k], v->graph[k], nullptr, nullptr, 0);
+        for (int g = 0; g < (v->pipe ? 2 : 1) && e == hipSuccess; ++g)
+            e = hipGraphInstantiate(&v->exec[g][k], v->graph[g][k], nullptr, nullptr, 0);
     }
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&v->done[k], hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -750,21 +784,24 @@ int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, 
     if (rc != PSTEREO_OK) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return fail(c, PSTEREO_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+    c->pipe_valid = false;  // a later plain pipelined call waits for this frame
     if (f.aligned != v->tmpl.aligned) {
-        // the captured kernels assume the first frame's alignment; launch directly
+        // the captured kernels assume the first frame's alignment; launch
+        // directly on the stream, in set 0, after everything before
         pstereo::LaunchSpec ls[kMaxSpecs];
         int n;
         frame_specs(f, ws, ls, n);
         for (int i = 0; i < n; ++i)
             if ((e = pstereo::launch(ls[i], f, s)) != hipSuccess)
                 return fail(c, PSTEREO_E_DEVICE, "launch: %s", hipGetErrorString(e));
+        v->pipe_started = false;  // the next frame's depth graph waits for this one
         return PSTEREO_OK;
     }
     constexpr int R = pstereo_video::kRing, E = pstereo_video::kEvery;
     const long long n = v->count;
     const int k = (int)(n % R);
     if (n >= R) {
-        // the previous replay of graph k (frame n - R) is covered by the event
+        // the previous replay of copy k (frame n - R) is covered by the event
         // recorded after frame ((n - R) / E) * E + E - 1 < n
         const long long g = (n - R) / E;
         if (g > v->waited) {
@@ -773,22 +810,37 @@ int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, 
             v->waited = g;
         }
     }
-    FrameDesc arg = f;
+    FrameDesc arg = video_desc(v, f, k);
     void* args[] = {&arg};
     for (int i = 0; i < v->nk; ++i) {
         if (!v->per_frame[i]) continue;
         hipKernelNodeParams kp = node_params(v->ls[i], args);
-        if ((e = hipGraphExecKernelNodeSetParams(v->exec[k], v->node[k][i], &kp)) != hipSuccess)
+        if ((e = hipGraphExecKernelNodeSetParams(v->exec[v->gidx[i]][k], v->node[k][i], &kp)) != hipSuccess)
             return fail(c, PSTEREO_E_DEVICE, "graph node update: %s", hipGetErrorString(e));
     }
-    if ((e = hipGraphLaunch(v->exec[k], v->stream)) != hipSuccess)
+    if (v->pipe) {
+        // the depth graph after what the stream held before the previous
+        // frame's call (everything, for the first frame); the filter and
+        // warp after it, on the stream
+        if ((!v->pipe_started && (e = hipEventRecord(c->ev_before, v->stream)) != hipSuccess) ||
+            (e = hipStreamWaitEvent(c->side, c->ev_before, 0)) != hipSuccess ||
+            (e = hipEventRecord(c->ev_before, v->stream)) != hipSuccess ||
+            (e = hipGraphLaunch(v->exec[0][k], c->side)) != hipSuccess ||
+            (e = hipEventRecord(c->ev_depth, c->side)) != hipSuccess ||
+            (e = hipStreamWaitEvent(v->stream, c->ev_depth, 0)) != hipSuccess ||
+            (e = hipGraphLaunch(v->exec[1][k], v->stream)) != hipSuccess) {
+            v->pipe_started = false;
+            return fail(c, PSTEREO_E_DEVICE, "pipelined graph launch: %s", hipGetErrorString(e));
+        }
+        v->pipe_started = true;
+    } else if ((e = hipGraphLaunch(v->exec[0][k], v->stream)) != hipSuccess) {
         return fail(c, PSTEREO_E_DEVICE, "graph launch: %s", hipGetErrorString(e));
+    }
     if (n % E == E - 1 && (e = hipEventRecord(v->done[(n / E) % 2], v->stream)) != hipSuccess)
         return fail(c, PSTEREO_E_DEVICE, "event record: %s", hipGetErrorString(e));
     v->count++;
-    c->pipe_valid = false;
     c->have_blocks = true;
-    c->last_fd = f;
+    c->last_fd = arg;
     c->blocks_final = f.rstrip == 0;
     c->last_gw = f.gw;
     c->last_gh = f.gh;

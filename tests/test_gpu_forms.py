@@ -27,18 +27,20 @@ def _plain(ctx, frame_t, **params):
     return L.cpu().numpy(), R.cpu().numpy(), A.cpu().numpy()
 
 
+@pytest.mark.parametrize("pipelined", [False, True])
 @pytest.mark.parametrize("w,h", [(1920, 1080), (640, 360), (333, 190)])
-def test_video_graph_matches_plain_and_oracle(ctx, oracle_mod, w, h):
+def test_video_graph_matches_plain_and_oracle(ctx, oracle_mod, w, h, pipelined):
     from paper_2009_09501_amd import pstereo_params_init
-    from paper_2009_09501_amd.pstereo import pstereo_video_begin, pstereo_video_end, pstereo_video_frame
+    from paper_2009_09501_amd.pstereo import (PSTEREO_PIPELINE, pstereo_video_begin, pstereo_video_end,
+                                              pstereo_video_frame)
     dev = torch.device("cuda:0")
     # 21 frames: the ring of graphs wraps twice, through both completion events
     spec = synth.VideoSpec(4, w, h, frames=21, n=40, sigma=3.0)
     frames = [torch.from_numpy(spec.frame(t)).to(dev) for t in range(21)]
     B = synth.default_disparity(w)
-    print(f"video {w}x{h} B={B}: 21 frames through the graph", flush=True)
+    print(f"video {w}x{h} B={B} pipelined={pipelined}: 21 frames through the graphs", flush=True)
     outs = [[torch.empty_like(frames[0]) for _ in range(3)] for _ in frames]
-    p = pstereo_params_init(max_disparity=B)
+    p = pstereo_params_init(max_disparity=B, flags=PSTEREO_PIPELINE if pipelined else 0)
     p.stream = torch.cuda.current_stream().cuda_stream
     v = pstereo_video_begin(ctx.handle, w, h, p)
     try:
@@ -55,12 +57,13 @@ def test_video_graph_matches_plain_and_oracle(ctx, oracle_mod, w, h):
 
 
 def test_video_4k_clip_frames_vs_oracle(ctx):
-    """The 4K clip's replay over 300 frames: frames 0, 149 and 299 of the
-    moving-ellipse clip against the oracle, the frames in between from a bank
-    of four (the graph ring wraps 37 times); every output compared on the
-    device with the plain call's output for the same input."""
+    """The 4K clip's pipelined replay over 300 frames: frames 0, 149 and 299
+    of the moving-ellipse clip against the oracle, the frames in between from
+    a bank of four (the graph ring wraps 37 times); every output compared on
+    the device with the plain call's output for the same input."""
     from paper_2009_09501_amd import pstereo_params_init
-    from paper_2009_09501_amd.pstereo import pstereo_video_begin, pstereo_video_end, pstereo_video_frame
+    from paper_2009_09501_amd.pstereo import (PSTEREO_PIPELINE, pstereo_video_begin, pstereo_video_end,
+                                              pstereo_video_frame)
     dev = torch.device("cuda:0")
     W, H = 3840, 2160
     B = synth.default_disparity(W)
@@ -74,7 +77,7 @@ def test_video_4k_clip_frames_vs_oracle(ctx):
     for t, f in dframes.items():
         plain[t] = ctx.synthesize(f, max_disparity=B)
     torch.cuda.synchronize()
-    p = pstereo_params_init(max_disparity=B)
+    p = pstereo_params_init(max_disparity=B, flags=PSTEREO_PIPELINE)
     p.stream = torch.cuda.current_stream().cuda_stream
     v = pstereo_video_begin(ctx.handle, W, H, p)
     kept = {}
