@@ -9,6 +9,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace pstereo {
@@ -16,24 +18,32 @@ namespace pstereo {
 // ---------------------------------------------------------------------------
 // block statistics: per K x K block, rounded mean colour and edge flag.
 //
-// Tiles of 64 x 64 px, 256 lanes: lane = one quad (4 px) in each of four
-// rows 16 apart, so K | 64 keeps every block inside one tile.
-// Horizontal luma steps use the next pixel's bytes; vertical steps go through
-// an LDS tile of packed luma that also holds the first row below the tile.
-// The lanes of one block reduce by cross-lane xor within the wave, then one
-// LDS atomic per wave and block.
+// Tiles of 256 px x 4 RW rows on 256 lanes (four waves): wave w covers the RW
+// rows [RW w, RW w + RW) of the tile (RW = 8 for blocks up to 16 px, 16 for
+// larger ones, so that a block lies in one tile) and lane l the quad of
+// pixels 4l .. 4l+3 in each of them, so every load instruction of a wave
+// reads 768 contiguous bytes of one row; a lane issues all RW + 1 of its rows
+// (its RW and the one below, for the vertical luma steps) before using any.
+// Sums and luma come from byte dot products in registers; the horizontal step
+// into the next quad takes that quad's first luma from the next lane (the
+// tile's last lane loads the next tile's first pixel); the lanes of one block
+// combine by lane shuffles, and blocks taller than a wave's rows add the
+// waves' shares in LDS.
+constexpr int kBsTileW = 256;  // px: 64 quads, one per lane of a wave
+
 template <int K>
 struct BsTile {
-    static constexpr int TH = 64;               // tile rows
-    static constexpr int RPT = 4;               // consecutive rows per lane
-    static constexpr int BC = 64 / K;           // block columns per tile
-    static constexpr int BR = TH / K;           // block rows per tile
-    static constexpr int QB = K / 4;            // quads per block row
-    static constexpr int LB = K / RPT;          // lane rows per block
-    static constexpr bool kInWave = LB <= 4;    // a block's lanes lie in one wave (K <= 16)
-    // luma of each lane row's first row; block sums of blocks spanning waves
-    static constexpr int kLdsWords = 16 * 16 + (kInWave ? 0 : BC * BR * 4);
+    static constexpr int RW = K <= 16 ? 8 : 16;                            // rows per wave
+    static constexpr int TH = 4 * RW;                                      // tile rows
+    static constexpr int QB = K / 4;                                       // lanes per block
+    static constexpr int NBR = K >= RW ? 1 : RW / K;                       // block rows per wave
+    static constexpr int kBlocks = (kBsTileW / K) * (TH / K);              // blocks per tile (K >= 4)
+    static constexpr bool kCross = K > RW;                                 // blocks span waves
+    static constexpr int kLdsWords = kCross ? 4 * kBlocks : 1;             // r, g, b, edge per block
 };
+
+// Tile rows of the block statistics for block size K (2 px blocks: 64).
+__host__ __device__ constexpr int bs_tile_rows(int K) { return K <= 2 ? 64 : K <= 16 ? 32 : 64; }
 
 // Rounded mean sum / cnt of a block of cnt pixels, (sum + cnt / 2) / cnt: a
 // shift for a whole K x K block (cnt = K * K, a power of two), the division
@@ -46,206 +56,182 @@ __device__ __forceinline__ uint32_t block_mean(uint32_t sum, uint32_t cnt) {
     return (sum + cnt / 2) / cnt;
 }
 
-// One 64 x 64 tile (tile_x, tile_y) on 256 lanes t = 0..255 (a multiple of
-// four whole waves): lane t takes quad t % 16 of the four consecutive rows
-// from 4 (t / 16), all four rows' loads in flight together, and sums them in
-// registers; a block's lanes then combine by lane shuffles (blocks spanning
-// waves through LDS atomics as well).  lds: BsTile<K>::kLdsWords words.
-// Inactive lane groups (active == false) do no memory work but pass the same
-// barriers.
+// The n (1..4) pixels of a quad starting at p as three dwords of RGB24 bytes,
+// zero past the n-th pixel.  ALIGNED: a whole quad at a 4-byte aligned address.
+template <bool ALIGNED>
+__device__ __forceinline__ uint3 load_quad_words(const uint8_t* p, int n) {
+    if constexpr (ALIGNED) {
+        return *reinterpret_cast<const uint3*>(p);
+    } else {
+        uint32_t w[3] = {0u, 0u, 0u};
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            if (i < 3 * n) w[i >> 2] |= (uint32_t)p[i] << (8 * (i & 3));
+        return make_uint3(w[0], w[1], w[2]);
+    }
+}
+
+// Luma of the four pixels of a quad held in three dwords.
+__device__ __forceinline__ void bs_quad_luma(uint3 q, uint32_t (&Y)[4]) {
+    constexpr uint32_t wlo = 77u | (150u << 8) | (29u << 16);
+    Y[0] = __builtin_amdgcn_udot4(q.x, wlo, 128u, false) >> 8;
+    Y[1] = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(q.y, q.x, 3), wlo, 128u, false) >> 8;
+    Y[2] = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(q.z, q.y, 2), wlo, 128u, false) >> 8;
+    Y[3] = __builtin_amdgcn_udot4(q.z, wlo << 8, 128u, false) >> 8;
+}
+
+// One 256 x TH tile (tile_x, tile_y) on 256 lanes t = 0..255.  lds:
+// BsTile<K>::kLdsWords words.  Inactive lane groups (active == false) do no
+// memory work but pass the same barriers (blocks spanning waves only).
 template <int K, bool ALIGNED>
 __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile_y, int t, uint32_t* lds,
                                         bool active) {
     using T = BsTile<K>;
-    constexpr int RPT = T::RPT, QB = T::QB, LB = T::LB;
-    uint32_t* yfirst = lds;     // [lane row][quad]
-    uint32_t* acc = lds + 256;  // blocks spanning waves: r, g, b, edge
+    constexpr int QB = T::QB, NBR = T::NBR, RW = T::RW;
+    constexpr uint32_t wlo = 77u | (150u << 8) | (29u << 16);
+    const int wave = t >> 6, lane = t & 63;
     const int W = f.w, H = active ? f.h : 0;
-    const int qx = t & 15, lr = t >> 4;
-    const int tx0 = tile_x * 64, ty0 = tile_y * T::TH;
-    const int x0 = tx0 + 4 * qx, y0 = ty0 + RPT * lr;
-    const int n = ALIGNED ? 4 : min(4, W - x0);  // aligned frames hold whole quads
+    const int x0 = tile_x * kBsTileW + 4 * lane;
+    const int y0 = tile_y * T::TH + RW * wave;
+    const int n = min(4, W - x0);  // pixels of the lane's quad inside the image (<= 0: none)
     const uint32_t g = (uint32_t)f.g;
-    if (!T::kInWave)
-        for (int i = t; i < T::BC * T::BR * 4; i += 256) acc[i] = 0;
+    if (T::kCross)
+        for (int i = t; i < T::kLdsWords; i += 256) lds[i] = 0;
 
-    // edge: the block has a luma step above g; emax: the largest step seen
-    // by the aligned path (compared with g once at the end)
-    uint32_t sr = 0, sg = 0, sb = 0, edge = 0, emax = 0;
-    uint32_t yq[RPT];     // packed luma bytes of the lane's quad, one word per row
-    uint32_t ybelow = 0;  // the row below the tile (last lane row only)
-    if (ALIGNED) {
-        uint3 v[RPT + 1];
-        uint32_t nx[RPT];
-        // the lane's quad in its first row; the next rows one uniform row
-        // stride apart
-        const uint8_t* p0 = f.frame + ((size_t)y0 * W + x0) * 3;
-        const size_t stride = (size_t)W * 3;
+    // every row's loads in flight before any is used
+    const uint8_t* p0 = f.frame + ((size_t)y0 * W + x0) * 3;
+    const size_t stride = (size_t)W * 3;
+    uint3 v[RW + 1];
+    uint32_t nx[RW];  // the tile's last lane: the next tile's first pixel per row
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) {
+    for (int k = 0; k <= RW; ++k) {
+        v[k] = make_uint3(0u, 0u, 0u);
+        if (y0 + k < H && n > 0) v[k] = load_quad_words<ALIGNED>(p0 + k * stride, n);
+    }
+    const bool edge_lane = lane == 63 && x0 + 4 < W;
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        nx[k] = 0u;
+        if (edge_lane && y0 + k < H) {
+            const uint8_t* q = p0 + k * stride + 12;
+            nx[k] = ALIGNED ? *reinterpret_cast<const uint32_t*>(q)
+                            : (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16);
+        }
+    }
+
+    // a step from pixel j to the right exists when j + 1 is in the image;
+    // a pixel exists when j < n
+    uint32_t sr[NBR], sg[NBR], sb[NBR], em[NBR];
+#pragma unroll
+    for (int i = 0; i < NBR; ++i) sr[i] = sg[i] = sb[i] = em[i] = 0u;
+    // FULL: the wave's rows and the row below all lie inside the image (the
+    // common case), so no row needs a bounds test
+    auto rows = [&](auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        uint32_t Yc[4];
+        bs_quad_luma(v[0], Yc);
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int br = (k * NBR) / RW;  // block row of row k inside the wave
             const int y = y0 + k;
-            if (y < H && x0 < W) {
-                const uint8_t* p = p0 + k * stride;
-                v[k] = *reinterpret_cast<const uint3*>(p);
-                if (x0 + 4 < W) nx[k] = *reinterpret_cast<const uint32_t*>(p + 12);
-            }
-        }
-        if (lr == 15 && ty0 + T::TH < H && x0 < W)
-            v[RPT] = *reinterpret_cast<const uint3*>(f.frame + ((size_t)(ty0 + T::TH) * W + x0) * 3);
-        constexpr uint32_t wlo = 77u | (150u << 8) | (29u << 16);
-        auto quad_luma = [&](uint3 q, uint32_t (&Y)[4]) {
-            Y[0] = __builtin_amdgcn_udot4(q.x, wlo, 128u, false) >> 8;
-            Y[1] = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(q.y, q.x, 3), wlo, 128u, false) >> 8;
-            Y[2] = __builtin_amdgcn_udot4(__builtin_amdgcn_alignbyte(q.z, q.y, 2), wlo, 128u, false) >> 8;
-            Y[3] = __builtin_amdgcn_udot4(q.z, wlo << 8, 128u, false) >> 8;
-        };
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const bool in = y0 + k < H && x0 < W;
-            yq[k] = 0;
-            if (!in) continue;
-            // four pixels = three dwords; sums and luma by byte dot products
-            sr = __builtin_amdgcn_udot4(v[k].x, 0x01000001u, sr, false);
-            sr = __builtin_amdgcn_udot4(v[k].y, 0x00010000u, sr, false);
-            sr = __builtin_amdgcn_udot4(v[k].z, 0x00000100u, sr, false);
-            sg = __builtin_amdgcn_udot4(v[k].x, 0x00000100u, sg, false);
-            sg = __builtin_amdgcn_udot4(v[k].y, 0x01000001u, sg, false);
-            sg = __builtin_amdgcn_udot4(v[k].z, 0x00010000u, sg, false);
-            sb = __builtin_amdgcn_udot4(v[k].x, 0x00010000u, sb, false);
-            sb = __builtin_amdgcn_udot4(v[k].y, 0x00000100u, sb, false);
-            sb = __builtin_amdgcn_udot4(v[k].z, 0x01000001u, sb, false);
-            uint32_t Y[4];
-            quad_luma(v[k], Y);
-            const uint32_t Yn = x0 + 4 < W ? __builtin_amdgcn_udot4(nx[k], wlo, 128u, false) >> 8 : Y[3];  // no step past the last column
-            const uint32_t hmax = max(max(__builtin_amdgcn_sad_u16(Y[1], Y[0], 0u), __builtin_amdgcn_sad_u16(Y[2], Y[1], 0u)),
-                                      max(__builtin_amdgcn_sad_u16(Y[3], Y[2], 0u), __builtin_amdgcn_sad_u16(Yn, Y[3], 0u)));
-            emax = max(emax, hmax);
-            yq[k] = Y[0] | (Y[1] << 8) | (Y[2] << 16) | (Y[3] << 24);
-        }
-        if (lr == 15 && ty0 + T::TH < H && x0 < W) {
-            uint32_t Y[4];
-            quad_luma(v[RPT], Y);
-            ybelow = Y[0] | (Y[1] << 8) | (Y[2] << 16) | (Y[3] << 24);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-            const int y = y0 + k;
-            yq[k] = 0;
-            if (y < H && x0 < W) {
-                const uint8_t* p = f.frame + ((size_t)y * W + x0) * 3;
-                int r[4], gg[4], b[4], Y[4];
-                load_quad<false>(p, n, r, gg, b);
-                int ynext = 0;
-                if (x0 + 4 < W) ynext = luma(p[12], p[13], p[14]);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) Y[j] = luma(r[j], gg[j], b[j]);
+            uint32_t Yb[4];
+            bs_quad_luma(v[k + 1], Yb);  // the row below (zero past the image)
+            const uint32_t yn_lane = (uint32_t)__shfl_down((int)Yc[0], 1);  // pixel x0 + 4 from the next lane
+            if (FULL || y < H) {
+                sr[br] = __builtin_amdgcn_udot4(v[k].x, 0x01000001u, sr[br], false);
+                sr[br] = __builtin_amdgcn_udot4(v[k].y, 0x00010000u, sr[br], false);
+                sr[br] = __builtin_amdgcn_udot4(v[k].z, 0x00000100u, sr[br], false);
+                sg[br] = __builtin_amdgcn_udot4(v[k].x, 0x00000100u, sg[br], false);
+                sg[br] = __builtin_amdgcn_udot4(v[k].y, 0x01000001u, sg[br], false);
+                sg[br] = __builtin_amdgcn_udot4(v[k].z, 0x00010000u, sg[br], false);
+                sb[br] = __builtin_amdgcn_udot4(v[k].x, 0x00010000u, sb[br], false);
+                sb[br] = __builtin_amdgcn_udot4(v[k].y, 0x00000100u, sb[br], false);
+                sb[br] = __builtin_amdgcn_udot4(v[k].z, 0x01000001u, sb[br], false);
+                const uint32_t Yn = lane == 63 ? __builtin_amdgcn_udot4(nx[k], wlo, 128u, false) >> 8 : yn_lane;
+                const uint32_t Yr[4] = {Yc[1], Yc[2], Yc[3], Yn};
+                uint32_t dh[4], dv[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    if (j < n) {
-                        sr += r[j]; sg += gg[j]; sb += b[j];
-                        yq[k] |= (uint32_t)Y[j] << (8 * j);
-                        if (x0 + j + 1 < W && iabs((j < 3 ? Y[j + 1] : ynext) - Y[j]) > f.g) edge = 1;
-                    }
+                    const bool h_ok = ALIGNED ? (j < 3 || x0 + 4 < W) : (j < n && x0 + j + 1 < W);
+                    const bool v_ok = (ALIGNED || j < n) && (FULL || y + 1 < H);
+                    dh[j] = h_ok ? __builtin_amdgcn_sad_u16(Yr[j], Yc[j], 0u) : 0u;
+                    dv[j] = v_ok ? __builtin_amdgcn_sad_u16(Yb[j], Yc[j], 0u) : 0u;
                 }
+                em[br] = max(max(max(em[br], dh[0]), max(dh[1], dh[2])),
+                             max(max(dh[3], dv[0]), max(max(dv[1], dv[2]), dv[3])));
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Yc[j] = Yb[j];
+        }
+    };
+    if (y0 + RW < H) rows(std::true_type{});
+    else rows(std::false_type{});
+
+    const int bx = x0 / K;  // the lane's block column (x0 >= 0)
+    if (!T::kCross) {
+        // K <= 16: a block lies in one wave, QB lanes wide; two 16-bit sums
+        // per register (QB * K * 4 * 255 < 2^16)
+#pragma unroll
+        for (int br = 0; br < NBR; ++br) {
+            uint32_t rg = sr[br] | (sg[br] << 16), be = sb[br] | ((em[br] > g ? 1u : 0u) << 16);
+#pragma unroll
+            for (int o = 1; o < QB; o <<= 1) {
+                rg += (uint32_t)__shfl_xor((int)rg, o);
+                be += (uint32_t)__shfl_xor((int)be, o);
+            }
+            const int by = (y0 + br * K) / K;
+            if (active && lane % QB == 0 && bx < f.gw && by < f.gh && n > 0) {
+                const uint32_t cnt = (uint32_t)((min(bx * K + K, W) - bx * K) * (min(by * K + K, H) - by * K));
+                f.stats[by * f.gw + bx] = block_mean<K>(rg & 0xFFFFu, cnt) | (block_mean<K>(rg >> 16, cnt) << 8) |
+                                          (block_mean<K>(be & 0xFFFFu, cnt) << 16) | ((be >> 16) ? 1u << 24 : 0u);
             }
         }
-        if (lr == 15 && ty0 + T::TH < H && x0 < W) {
-            int r[4], gg[4], b[4];
-            load_quad<false>(f.frame + ((size_t)(ty0 + T::TH) * W + x0) * 3, n, r, gg, b);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) if (j < n) ybelow |= (uint32_t)luma(r[j], gg[j], b[j]) << (8 * j);
-        }
-    }
-    yfirst[lr * 16 + qx] = yq[0];
-    __syncthreads();
-    // vertical steps: rows inside the lane's four, then the next lane row's
-    // first row (the row below the tile for the last lane row)
-    const uint32_t below_last = lr < 15 ? yfirst[(lr + 1) * 16 + qx] : ybelow;
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-        const int y = y0 + k;
-        if (y + 1 < H && x0 < W) {
-            const uint32_t below = k + 1 < RPT ? yq[k + 1] : below_last;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (j < n) emax = max(emax, __builtin_amdgcn_sad_u16((below >> (8 * j)) & 255u, (yq[k] >> (8 * j)) & 255u, 0u));
-        }
-    }
-    if (emax > g) edge = 1;
-    const int bxl = qx / QB, byl = lr / LB;  // the lane's block in the tile
-    if (T::kInWave) {
-        // two 16-bit sums per register: a block holds K * K / 16 <= 16 lanes
-        // of at most 16 pixels, 16 x 16 x 255 < 2^16
-        uint32_t rg = sr | (sg << 16), be = sb | (edge << 16);
-#pragma unroll
-        for (int o = 1; o < QB; o <<= 1) {
-            rg += __shfl_xor(rg, o);
-            be += __shfl_xor(be, o);
-        }
-#pragma unroll
-        for (int o = 1; o < LB; o <<= 1) {
-            rg += __shfl_xor(rg, 16 * o);
-            be += __shfl_xor(be, 16 * o);
-        }
-        const int bx = tile_x * T::BC + bxl, by = tile_y * T::BR + byl;
-        if (active && qx % QB == 0 && lr % LB == 0 && bx < f.gw && by < f.gh) {
-            const uint32_t cnt = (uint32_t)((min(bx * K + K, W) - bx * K) * (min(by * K + K, H) - by * K));
-            const uint32_t mr = block_mean<K>((rg & 0xFFFFu), cnt);
-            const uint32_t mg = block_mean<K>((rg >> 16), cnt);
-            const uint32_t mb = block_mean<K>((be & 0xFFFFu), cnt);
-            f.stats[by * f.gw + bx] = mr | (mg << 8) | (mb << 16) | ((be >> 16) ? 1u << 24 : 0u);
-        }
     } else {
-        // the wave's share of each block (four lane rows), then across waves
+        // blocks taller than RW: the wave's RW rows of its blocks, then across
+        // waves (32-bit sums)
+        uint32_t r = sr[0], gg = sg[0], b = sb[0], e = em[0] > g ? 1u : 0u;
 #pragma unroll
         for (int o = 1; o < QB; o <<= 1) {
-            sr += __shfl_xor(sr, o);
-            sg += __shfl_xor(sg, o);
-            sb += __shfl_xor(sb, o);
-            edge |= __shfl_xor(edge, o);
+            r += (uint32_t)__shfl_xor((int)r, o);
+            gg += (uint32_t)__shfl_xor((int)gg, o);
+            b += (uint32_t)__shfl_xor((int)b, o);
+            e |= (uint32_t)__shfl_xor((int)e, o);
         }
-#pragma unroll
-        for (int o = 16; o < 64; o <<= 1) {
-            sr += __shfl_xor(sr, o);
-            sg += __shfl_xor(sg, o);
-            sb += __shfl_xor(sb, o);
-            edge |= __shfl_xor(edge, o);
-        }
-        if (qx % QB == 0 && (lr & 3) == 0) {
-            const int blk = bxl + T::BC * byl;
-            atomicAdd(&acc[4 * blk + 0], sr);
-            atomicAdd(&acc[4 * blk + 1], sg);
-            atomicAdd(&acc[4 * blk + 2], sb);
-            if (edge) atomicOr(&acc[4 * blk + 3], 1u);
+        __syncthreads();  // the LDS sums are zero
+        constexpr int BC = kBsTileW / K;  // block columns per tile
+        const int blk = (lane / QB) + BC * ((wave * RW) / K);
+        if (lane % QB == 0) {
+            atomicAdd(&lds[4 * blk + 0], r);
+            atomicAdd(&lds[4 * blk + 1], gg);
+            atomicAdd(&lds[4 * blk + 2], b);
+            if (e) atomicOr(&lds[4 * blk + 3], 1u);
         }
         __syncthreads();
-        for (int i = t; i < T::BC * T::BR; i += 256) {
-            const int bx = tile_x * T::BC + i % T::BC, by = tile_y * T::BR + i / T::BC;
-            if (active && bx < f.gw && by < f.gh) {
-                const uint32_t cnt = (uint32_t)((min(bx * K + K, W) - bx * K) * (min(by * K + K, H) - by * K));
-                const uint32_t mr = block_mean<K>(acc[4 * i + 0], cnt);
-                const uint32_t mg = block_mean<K>(acc[4 * i + 1], cnt);
-                const uint32_t mb = block_mean<K>(acc[4 * i + 2], cnt);
-                f.stats[by * f.gw + bx] = mr | (mg << 8) | (mb << 16) | (acc[4 * i + 3] << 24);
+        if (t < T::kBlocks) {
+            const int cbx = tile_x * BC + t % BC, cby = tile_y * (T::TH / K) + t / BC;
+            if (active && cbx < f.gw && cby < f.gh) {
+                const uint32_t cnt =
+                    (uint32_t)((min(cbx * K + K, W) - cbx * K) * (min(cby * K + K, H) - cby * K));
+                f.stats[cby * f.gw + cbx] = block_mean<K>(lds[4 * t + 0], cnt) |
+                                            (block_mean<K>(lds[4 * t + 1], cnt) << 8) |
+                                            (block_mean<K>(lds[4 * t + 2], cnt) << 16) | (lds[4 * t + 3] << 24);
             }
         }
     }
 }
 
 // Block statistics for blocks of 2 x 2 px (frames of at most 2^17 pixels,
-// so this path is never the bulk of the work): the same 64 x 64 px tiles on
-// 256 lanes; lane t takes block column t % 32 of the tile's 32 x 32 blocks in
-// block rows t / 32 + 8 k, k = 0..3, reading pixels bytewise and the luma
-// steps to the right and below directly.  No barriers.
+// so this path is never the bulk of the work): 256 x 64 px tiles on 256
+// lanes; lane t takes blocks t, t + 256, ... of the tile's 128 x 32 blocks,
+// reading pixels bytewise and the luma steps to the right and below
+// directly.  No barriers.
 __device__ __forceinline__ void bs_tile_k2(const FrameDesc& f, int tile_x, int tile_y, int t, bool active) {
     if (!active) return;
     const int W = f.w, H = f.h;
-    const int bx = tile_x * 32 + (t & 31);
-    if (bx >= f.gw) return;
-    for (int k = 0; k < 4; ++k) {
-        const int by = tile_y * 32 + (t >> 5) + 8 * k;
-        if (by >= f.gh) break;
+    constexpr int BC = kBsTileW / 2, BR = 64 / 2;
+    for (int i = t; i < BC * BR; i += 256) {
+        const int bx = tile_x * BC + i % BC, by = tile_y * BR + i / BC;
+        if (bx >= f.gw || by >= f.gh) continue;
         uint32_t sr = 0, sg = 0, sb = 0, cnt = 0, edge = 0;
         for (int dy = 0; dy < 2; ++dy) {
             for (int dx = 0; dx < 2; ++dx) {

@@ -187,17 +187,19 @@ __device__ __forceinline__ int frame_of(const int* first, int n, int idx) {
     return lo;
 }
 
-constexpr int kBsLdsMax = BsTile<32>::kLdsWords;  // the largest: blocks spanning waves, most per tile
+constexpr int kBsLdsMax = BsTile<16>::kLdsWords > BsTile<32>::kLdsWords ? BsTile<16>::kLdsWords
+                                                                          : BsTile<32>::kLdsWords;
 
 __global__ void __launch_bounds__(256) k_mf_blockstats(const FrameDesc* frames, const int* first, int n) {
     static_assert(BsTile<4>::kLdsWords <= kBsLdsMax && BsTile<8>::kLdsWords <= kBsLdsMax &&
-                  BsTile<16>::kLdsWords <= kBsLdsMax && BsTile<64>::kLdsWords <= kBsLdsMax, "blockstats LDS");
+                  BsTile<16>::kLdsWords <= kBsLdsMax && BsTile<32>::kLdsWords <= kBsLdsMax &&
+                  BsTile<64>::kLdsWords <= kBsLdsMax, "blockstats LDS");
     __shared__ uint32_t lds[kBsLdsMax];
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
     const int fi = frame_of(first, n, idx);
     const FrameDesc f = frames[fi];
     const int local = idx - first[fi];
-    const int gx = (f.w + 63) / 64;
+    const int gx = (f.w + kBsTileW - 1) / kBsTileW;
     const int tx = local % gx, ty = local / gx;
     switch (f.K) {
         case 2: bs_tile_k2(f, tx, ty, threadIdx.x, true); break;
@@ -290,8 +292,8 @@ hipError_t launch_staged(const FrameDesc* d_frames, const int* d_first, const St
 int batch_tasks(const FrameDesc& f, int phase, int* items, int* gx) {
     switch (phase) {
         case 0: {
-            const int th = 64;  // block-statistics tile rows
-            *gx = (f.w + 63) / 64;
+            const int th = bs_tile_rows(f.K);
+            *gx = (f.w + kBsTileW - 1) / kBsTileW;
             *items = *gx * ((f.h + th - 1) / th);
             return (*items + 3) / 4;
         }

@@ -47,17 +47,16 @@ __global__ void __launch_bounds__(64) k_clear_words(uint32_t* p, int n) {
 
 template <int K, bool A>
 static LaunchSpec bs_spec(const FrameDesc& f) {
-    constexpr int TH = BsTile<K>::TH;
-    return {reinterpret_cast<const void*>(&k_blockstats<K, A>), dim3((f.w + 63) / 64, (f.h + TH - 1) / TH),
-            dim3(256), 0};
+    return {reinterpret_cast<const void*>(&k_blockstats<K, A>),
+            dim3((f.w + kBsTileW - 1) / kBsTileW, (f.h + BsTile<K>::TH - 1) / BsTile<K>::TH), dim3(256), 0};
 }
 
 template <bool A>
 static LaunchSpec bs_k(const FrameDesc& f) {
     switch (f.K) {
         case 2:
-            return {reinterpret_cast<const void*>(&k_blockstats_k2), dim3((f.w + 63) / 64, (f.h + 63) / 64), dim3(256),
-                    0};
+            return {reinterpret_cast<const void*>(&k_blockstats_k2),
+                    dim3((f.w + kBsTileW - 1) / kBsTileW, (f.h + 63) / 64), dim3(256), 0};
         case 4: return bs_spec<4, A>(f);
         case 8: return bs_spec<8, A>(f);
         case 16: return bs_spec<16, A>(f);
