@@ -111,13 +111,21 @@ __device__ __forceinline__ uint32_t block_depth_from_slots(const FrameDesc& f, i
     return ((v >> 8) & 1u) ? (uint32_t)ramp(by, f.gh) : (v & 255u);
 }
 
+// The search key of a block in the filter's staged table (second word of its
+// entry): its region depth when it is a non-edge block, else kNoCandidate,
+// which stays above every candidate's key (distance << 16 | index << 8 |
+// depth, distance <= 765) with any index or distance added and does not
+// overflow.
+constexpr uint32_t kNoCandidate = 0xFC000000u;
+
 // Raw depth of the four pixels of a quad: the region depth of their block, or
 // for an edge block that of the non-edge 3x3 neighbour block whose mean colour
 // is nearest (L1), first strict minimum in raster order; with no candidate
 // the ramp of the block row.  col[j] = R | G << 8 | B << 16 of pixel j; the
 // L1 distance to a block mean (stats word, edge byte zero for candidates) is
-// one v_sad_u8.  The blocks come from a table staged in LDS: tab holds the blocks [bx_lo, bx_lo + bw) x [by_lo, ...) and covers every
-// in-grid block the lookup can touch; K = 1 << ks.
+// one v_sad_u8.  The blocks come from a table staged in LDS: tab holds the
+// blocks [bx_lo, bx_lo + bw) x [by_lo, ...), {statistics, search key}, and
+// covers every in-grid block the lookup can touch; K = 1 << ks.
 __device__ __forceinline__ void quad_depth_tab(const FrameDesc& f, int x0, int yy, int ks, const uint2* tab,
                                                int bx_lo, int by_lo, int bw, const uint32_t (&col)[4],
                                                uint32_t (&D)[4]) {
@@ -131,25 +139,23 @@ __device__ __forceinline__ void quad_depth_tab(const FrameDesc& f, int x0, int y
     // branch-free: per pixel the minimum of (distance << 16) + (k << 8 |
     // depth) over the candidates k in raster order (distance <= 765), so
     // that ties go to the first -- one v_sad_hi_u8 per candidate; a
-    // non-candidate adds kNone, which no candidate key reaches and no
-    // distance carries past 2^32
-    constexpr uint32_t kNone = 0xFC000000u;
+    // non-candidate's key starts at kNoCandidate
     uint32_t best[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const uint2 c = tab[(by - by_lo + k / 3 - 1) * bw + (bx - bx_lo + k % 3 - 1)];
-        const uint32_t tag = (c.x >> 24) ? kNone : (((uint32_t)k << 8) | c.y);
+        const uint32_t tag = c.y | ((uint32_t)k << 8);
 #pragma unroll
         for (int j = 0; j < 4; ++j) best[j] = min(best[j], __builtin_amdgcn_sad_hi_u8(col[j], c.x, tag));
     }
     // the ramp of the block row only where a pixel found no candidate (rare)
     bool none = false;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) none |= best[j] >= kNone;
+    for (int j = 0; j < 4; ++j) none |= best[j] >= kNoCandidate;
     uint32_t fallback = 0;
     if (none) fallback = (uint32_t)ramp(by, f.gh);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) D[j] = best[j] >= kNone ? fallback : (best[j] & 255u);
+    for (int j = 0; j < 4; ++j) D[j] = best[j] >= kNoCandidate ? fallback : (best[j] & 255u);
 }
 
 // Raw depth of the four pixels of a quad for blocks of 2 px (the quad spans
@@ -348,10 +354,11 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
         for (int i = t; i < nbt; i += 256) {
             const int r = i / bw;
             const int by = by_lo + r, bx = bx_lo + (i - r * bw);
-            uint2 e = make_uint2(1u << 24, 0u);
+            uint2 e = make_uint2(1u << 24, kNoCandidate);
             if (by >= 0 && by < f.gh && bx >= 0 && bx < f.gw) {
                 e = f.binfo[by * f.gw + bx];
                 if (strips) e.y = block_depth_from_slots(f, by, e);
+                if (e.x >> 24) e.y = kNoCandidate;  // an edge block is never a candidate
             }
             btab[i] = e;
         }
@@ -450,16 +457,23 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
             // inside the image lie in at most 2 x 2 blocks: when those are
             // non-edge blocks of one region depth the window is uniform
             // (four table reads); else the depths are compared pixel by pixel
-            uint32_t c = 0, bad = 1;
+            // (a window over non-edge blocks of different depths holds pixels
+            // of each -- every block under it holds a window pixel -- so it
+            // is not uniform and goes to the filter without the pixel test:
+            // the block-row steps of the background ramp are most of these)
+            uint32_t c = 0, bad = 1, sure = 0;
             if (!K2 && !f.depth_in && ks >= 3) {
                 const int bxa = max(x0 - R, 0) >> ks, bxb = min(x0 + 3 + R, W - 1) >> ks;
                 const int bya = max(y - R, 0) >> ks, byb = min(y + R, H - 1) >> ks;
                 const uint2 e00 = btab[(bya - by_lo) * bw + (bxa - bx_lo)], e01 = btab[(bya - by_lo) * bw + (bxb - bx_lo)];
                 const uint2 e10 = btab[(byb - by_lo) * bw + (bxa - bx_lo)], e11 = btab[(byb - by_lo) * bw + (bxb - bx_lo)];
                 c = e00.y;
-                bad = ((e00.x | e01.x | e10.x | e11.x) >> 24) | (e01.y ^ c) | (e10.y ^ c) | (e11.y ^ c);
+                const uint32_t edge = (e00.x | e01.x | e10.x | e11.x) >> 24;
+                const uint32_t differ = (e01.y ^ c) | (e10.y ^ c) | (e11.y ^ c);
+                bad = edge | differ;
+                sure = !edge && differ;
             }
-            if (bad) {
+            if (bad && !sure) {
                 c = tD[(ty + R) * kRowWords + 2 * qx + 2] & 0xFFFFu;
                 bad = 0;
                 const uint32_t splat = c | (c << 16);
