@@ -50,16 +50,86 @@ def _kernel_source_sha() -> str:
 def _traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None if there is none for the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = _profile_record("traffic.json", f"{kernel}@{workload}")
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def _profile_record(name: str, key: str):
+    """One entry of a committed rocprofv3 summary (profiles/<name>.json) for
+    the current kernel sources, or None (absent, or taken from other
+    sources)."""
     try:
-        with open(path) as fh:
-            data = json.load(fh)
+        with open(os.path.join(ROOT, "profiles", name)) as fh:
+            rec = json.load(fh).get(key)
     except (OSError, ValueError):
         return None
-    rec = data.get(f"{kernel}@{workload}")
     if not rec or rec.get("source_sha") != _kernel_source_sha():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def _short_kernel(name: str) -> str:
+    """k_warp from 'void pstereo::k_warp<true, 2>(pstereo::FrameDesc)'."""
+    base = name.split("(")[0].split("<")[0].replace("void ", "").strip()
+    return base.split("::")[-1]
+
+
+def summarize_trace(csv_dir: str, workload: str) -> None:
+    """Record the mean kernel durations of a rocprofv3 --kernel-trace --stats
+    run (DIR/run_kernel_stats.csv) in profiles/kernels.json under
+    <kernel>@<workload>, with the kernel sources' hash, and print them."""
+    import csv
+    path = os.path.join(ROOT, "profiles", "kernels.json")
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        data = {}
+    sha = _kernel_source_sha()
+    rows = []
+    for r in csv.DictReader(open(os.path.join(csv_dir, "run_kernel_stats.csv"))):
+        if "pstereo" not in r["Name"]:
+            continue
+        k = _short_kernel(r["Name"])
+        avg = float(r["AverageNs"]) / 1e3
+        key = f"{k}@{workload}"
+        data[key] = {"avg_us": round(avg, 3), "calls": int(r["Calls"]), "min_us": round(float(r["MinNs"]) / 1e3, 3),
+                     "max_us": round(float(r["MaxNs"]) / 1e3, 3), "source_sha": sha}
+        rows.append((k, int(r["Calls"]), avg))
+    with open(path, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    for k, n, avg in rows:
+        print(f"| `{k}` | {n} | {avg:.2f} |")
+
+
+def summarize_traffic(fetch_dir: str, write_dir: str, workload: str, fetch_factor: float,
+                      write_factor: float) -> None:
+    """Record HBM bytes per dispatch from two rocprofv3 --pmc runs (FETCH_SIZE,
+    WRITE_SIZE; KiB per dispatch, medians per kernel) scaled by the copy
+    calibration's factors, in profiles/traffic.json under <kernel>@<workload>."""
+    import csv
+    import statistics as st
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        data = {}
+
+    def med(d, counter):
+        vals = {}
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if r["Counter_Name"] == counter and "pstereo" in r["Kernel_Name"]:
+                vals.setdefault(_short_kernel(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        return {k: st.median(v) for k, v in vals.items()}
+    fetch, write = med(fetch_dir, "FETCH_SIZE"), med(write_dir, "WRITE_SIZE")
+    sha = _kernel_source_sha()
+    for k in sorted(set(fetch) & set(write)):
+        rd = fetch[k] * 1024 * fetch_factor
+        wr = write[k] * 1024 * write_factor
+        data[f"{k}@{workload}"] = {"read_bytes": int(rd), "write_bytes": int(wr), "bytes_per_launch": int(rd + wr),
+                                   "fetch_factor": fetch_factor, "write_factor": write_factor, "source_sha": sha}
+        print(f"| `{k}` | {fetch[k]:.0f} | {write[k]:.0f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} |")
+    with open(path, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
 
 
 def _pct(xs, q):
@@ -559,12 +629,25 @@ def main() -> int:
     ap.add_argument("--host-frames", type=int, default=120)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (to scale HBM byte counters)")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="only record DIR/run_kernel_stats.csv (rocprofv3) in profiles/kernels.json")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="only record two rocprofv3 --pmc runs in profiles/traffic.json")
+    ap.add_argument("--workload", default="4k_pipelined", help="workload name for --summarize-*")
+    ap.add_argument("--fetch-factor", type=float, default=2.0)
+    ap.add_argument("--write-factor", type=float, default=1.0)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-burst", type=int, default=16)
     ap.add_argument("--serve-compress", default="4,16,64,256")
     ap.add_argument("--form-steps", type=int, default=60)
     ap.add_argument("--video-bank", type=int, default=8)
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.workload)
+        return 0
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, args.workload, args.fetch_factor, args.write_factor)
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(frames and streams shard across GPUs with no exchange; see the design notes)",
@@ -625,9 +708,15 @@ def main() -> int:
         dom = "k_warp"
         dom_s = st[dom] / 1e3
         achieved = STAGE_BYTES_PER_PX[dom] * px / dom_s / 1e9
+        wl = "4k_pipelined" if pipeline else "4k_serial"
+        trace = _profile_record("kernels.json", f"{dom}@{wl}")
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                           "traffic": _traffic(dom, "4k"), "duration_us": round(dom_s * 1e6, 3),
+                           "traffic": _traffic(dom, wl), "duration_us": round(dom_s * 1e6, 3),
+                           "trace_duration_us": trace["avg_us"] if trace else None,
+                           "frac_by_trace": round(STAGE_BYTES_PER_PX[dom] * px / (trace["avg_us"] * 1e-6) / 1e9
+                                                  / HBM_PEAK_GBS, 4) if trace else None,
+                           "trace": f"profiles/kernels.json {dom}@{wl} (rocprofv3 kernel trace of this command)",
                            "duration_from": "the kernel's own dispatch start/stop timestamps (HIP events "
                                             f"attached to its launch), mean over every {every}-th timed step",
                            "bytes_per_launch": STAGE_BYTES_PER_PX[dom] * px,
