@@ -323,11 +323,17 @@ int pstereo_synthesize_batch(pstereo_ctx *ctx, const pstereo_job *jobs, int n, c
  *    the batch (block statistics, region grouping with one workgroup per
  *    frame, depth filter, then one row-warp launch per distinct row shape);
  *    kernel boundaries order the stages.
- *  PSTEREO_BATCH_FUSED: the single persistent kernel described above.
+ *  PSTEREO_BATCH_FUSED: one persistent kernel: its workgroups claim tasks
+ *    (per frame: block statistics, region grouping, depth filter, warp) in a
+ *    dependency order from one queue per XCD -- each frame belongs to one
+ *    XCD, so a task and the tasks it waits for share that XCD's L2 and
+ *    synchronise without cache write-back -- so one frame's region grouping
+ *    overlaps the streaming work of the others.
  * Tuning fields: warp_lanes (64..1024, multiple of 64) caps the lanes of a
  * row-warp workgroup before quads per lane grow (1, 2, 4); warp_rows (1..8)
  * rows per row-warp workgroup; fused_grid = persistent workgroups (0 = one
- * per compute unit).  A new tuning takes effect at the next prepare.
+ * per compute unit, else 8..65536: every XCD needs workgroups for its
+ * queue).  A new tuning takes effect at the next prepare.
  * pstereo_batch_autotune: runs the jobs (outputs are written) under each
  *   candidate tuning -- staged with warp_lanes in {128, 256, 512, 1024} x
  *   warp_rows in {1, 2, 4}, and fused -- timing `reps` launches of each with

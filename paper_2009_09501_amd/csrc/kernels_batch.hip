@@ -1,20 +1,27 @@
 // Batched forms: many frames of uneven size per launch.
 //
 // Fused form: one persistent kernel.
-// Every workgroup (1024 lanes, one per CU) loops: claim the next task from a
-// global counter, wait until the task's inputs are complete, run it, signal
-// completion.  Tasks are numbered in a topological order:
-//   for each frame: its block-statistics tasks, then its region task;
-//   then for each frame: its depth-filter tasks, then its warp tasks.
-// A task is four 64-px tiles (block statistics, depth filter: four 256-lane
-// groups), 1024/G image rows (warp: groups of G lanes), or the whole frame
-// (region grouping: all 1024 lanes).  A workgroup only waits on tasks that
-// were claimed before its own, i.e. by running workgroups, so the loop cannot
-// deadlock whatever the number of resident workgroups.  Completion counters
-// use agent-scope release / acquire so results written through one XCD's L2
-// are visible to the others.  A dependency wait is also bounded in wall-clock
-// time: should one ever exceed it, the workgroup raises the abort word and
-// every workgroup leaves its loop at its next claim or wait.
+// Every workgroup (1024 lanes, one per CU) loops: claim the next task from
+// its XCD's queue (the next one is claimed while the current one runs), wait
+// until the task's inputs are complete, run it, count it done.  Each frame
+// belongs to one of the eight queues (the host balances their pixels), and
+// each queue's tasks are numbered in a topological order:
+//   for each of its frames: the block-statistics tasks, then the region task;
+//   then for each: the depth-filter tasks, then the warp tasks.
+// A task is four 256-px-wide block-statistics tiles or four 64 x 32 filter
+// tiles (four 256-lane groups), 1024/G image rows (warp: groups of G lanes),
+// or the whole frame (region grouping: all 1024 lanes).  The smallest
+// unfinished claimed task depends only on finished tasks and is some
+// workgroup's current task, so the loop cannot deadlock whatever the number
+// of resident workgroups.
+// A task and the tasks it waits for run on one XCD, whose L2 all its CUs
+// share: a producer waits until its stores are acknowledged (s_waitcnt 0)
+// before counting, and a consumer invalidates its CU's L1 after seeing the
+// count -- no agent-scope release or acquire, which on this part would write
+// back or invalidate the whole L2 at every task.  A dependency wait is also
+// bounded in wall-clock time: should one ever exceed it, the workgroup raises
+// the abort word and every workgroup leaves its loop at its next claim or
+// wait.
 //
 // Staged form (below the fused kernel): one launch per stage, each over all
 // frames of the batch.
@@ -112,26 +119,35 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchDesc bd) {
     extern __shared__ uint32_t lds[];
     int* slot = reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(lds) + kBatchSlotOffset);
     const int tid = threadIdx.x;
-    uint32_t* abort_word = bd.ctr + 1 + 4 * bd.nframes;
-    int seg = 0;
+    // this workgroup's XCD, from the hardware register: it serves that XCD's
+    // queue only
+    const int q = (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kXcds - 1));
+    const int ntask = bd.qntask[q];
+    uint32_t* abort_word = bd.ctr + kXcds + 4 * bd.nframes;
+    int seg = bd.qseg[q];
+    // the next task is claimed while the current one runs
+    if (tid == 0) slot[0] = (int)atomicAdd(&bd.ctr[q], 1u);
+    __syncthreads();
+    int task = slot[0];
     while (true) {
-        if (tid == 0) slot[0] = load_relaxed(abort_word) ? bd.ntask : (int)atomicAdd(&bd.ctr[0], 1u);
-        __syncthreads();
-        const int task = slot[0];
-        __syncthreads();
-        if (task >= bd.ntask) break;
+        __syncthreads();  // every lane has read slot[0]
+        if (task >= ntask) break;
+        uint32_t next = 0;
+        if (tid == 0) next = load_relaxed(abort_word) ? (uint32_t)ntask : atomicAdd(&bd.ctr[q], 1u);
         while (task >= bd.segs[seg].first + bd.segs[seg].ntask) ++seg;
         const BatchSeg sg = bd.segs[seg];
         const FrameDesc* fp = bd.frames + sg.frame;
         const int k = task - sg.first;  // task index inside the segment
-        // wait for the inputs of this phase of this frame
+        // wait for the inputs of this phase of this frame: written on this
+        // XCD by tasks that waited for their stores before counting, so they
+        // are in this XCD's L2; this CU's L1 is invalidated before reading
         if (sg.phase > 0) {
             if (tid == 0) {
-                const uint32_t* dep = &bd.ctr[1 + 4 * sg.frame + sg.phase - 1];
+                const uint32_t* dep = &bd.ctr[kXcds + 4 * sg.frame + sg.phase - 1];
                 const uint32_t need = (uint32_t)bd.need[4 * sg.frame + sg.phase - 1];
                 const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
                 int ok = 1;
-                while (load_acquire(dep) < need) {
+                while (load_relaxed(dep) < need) {
                     if (load_relaxed(abort_word) || __builtin_amdgcn_s_memrealtime() - t0 > kWaitLimitTicks) {
                         __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         ok = 0;
@@ -143,26 +159,25 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchDesc bd) {
             }
             __syncthreads();
             if (!slot[1]) break;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            asm volatile("buffer_inv sc0" ::: "memory");
         }
         if (sg.phase == 0) task_blockstats(fp, k, sg.items, sg.gx, lds);
         else if (sg.phase == 1) task_regions(fp, lds);
         else if (sg.phase == 2) task_cbf<R>(fp, k, sg.items, sg.gx, lds);
         else task_warp(fp, k, lds);
-        // publish: every lane's stores reach agent scope, then one release
-        // add.  Warp tasks have no dependent task (their outputs are read
-        // after the kernel), so they publish nothing: on this part every
-        // agent-scope release writes the XCD's L2 back, the dominant cost of
-        // a task
-        if (sg.phase < 3) {
-            __threadfence();
-            __syncthreads();
-            if (tid == 0)
-                __hip_atomic_fetch_add(&bd.ctr[1 + 4 * sg.frame + sg.phase], 1u, __ATOMIC_RELEASE,
+        // publish: every lane's stores acknowledged by the L2, then one count
+        // (warp tasks have no dependent task: their outputs are read after
+        // the kernel)
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+            if (sg.phase < 3)
+                __hip_atomic_fetch_add(&bd.ctr[kXcds + 4 * sg.frame + sg.phase], 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __syncthreads();  // the task's LDS is free for the next claim
+            slot[0] = (int)next;
         }
+        __syncthreads();
+        task = slot[0];
     }
 }
 
@@ -336,7 +351,7 @@ hipError_t prepare_batch_kernels() {
 }
 
 hipError_t launch_batch(const BatchDesc& bd, int r, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, bd.ctr, 2 + 4 * bd.nframes);
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(256), 0, s, bd.ctr, kXcds + 1 + 4 * bd.nframes);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (r) {

@@ -18,14 +18,21 @@ struct BatchSeg {
     int gx;     // tiles per tile row (phases 0, 2)
 };
 
+// The fused kernel's work is split into kXcds queues, one per XCD: every
+// frame belongs to one queue, and only the workgroups running on that XCD
+// (read from the hardware's XCC id) claim its tasks, so a task and the tasks
+// it depends on run on one XCD and share its L2.
+constexpr int kXcds = 8;
+
 struct BatchDesc {
     const FrameDesc* frames;  // [nframes]
-    const BatchSeg* segs;     // [4 * nframes] in claim order
+    const BatchSeg* segs;     // [4 * nframes]: queue q's segments are [qseg[q], qseg[q + 1]), in claim order
     const int* need;          // [4 * nframes]: tasks of (frame, phase)
-    uint32_t* ctr;            // [0]: next task; [1 + 4 f + p]: finished tasks of (frame f, phase p);
-                              // [1 + 4 nframes]: abort word (a dependency wait timed out)
+    uint32_t* ctr;            // [q]: next task of queue q; [kXcds + 4 f + p]: finished tasks of (frame f,
+                              // phase p); [kXcds + 4 nframes]: abort word (a dependency wait timed out)
     int nframes;
-    int ntask;
+    int qseg[kXcds + 1];
+    int qntask[kXcds];        // tasks of each queue
 };
 
 // Launch plan of the staged form: per-stage workgroup counts and the warp

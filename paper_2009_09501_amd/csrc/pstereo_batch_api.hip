@@ -41,6 +41,8 @@ struct pstereo_batch {
     bool staged_pending = false;
     // the prepared batch
     int n = 0, ntask = 0, r = 2;
+    int qseg[pstereo::kXcds + 1] = {};  // fused form: segments of each XCD's queue
+    int qntask[pstereo::kXcds] = {};
     bool prepared = false;
     // tuning and the staged form's tables
     pstereo_batch_tuning tune{PSTEREO_BATCH_STAGED, 256, 1, 0};
@@ -134,7 +136,7 @@ int batch_create_internal(pstereo_ctx* ctx, int max_jobs, int64_t max_pixels, bo
     bool ok = hipMalloc(&b->d_frames, sizeof(FrameDesc) * max_jobs) == hipSuccess &&
               hipMalloc(&b->d_segs, sizeof(BatchSeg) * 4 * max_jobs) == hipSuccess &&
               hipMalloc(&b->d_need, sizeof(int) * 4 * max_jobs) == hipSuccess &&
-              hipMalloc(&b->d_ctr, sizeof(uint32_t) * (2 + 4 * max_jobs)) == hipSuccess &&
+              hipMalloc(&b->d_ctr, sizeof(uint32_t) * (pstereo::kXcds + 1 + 4 * max_jobs)) == hipSuccess &&
               hipMalloc(&b->d_first, sizeof(int) * first_ints) == hipSuccess &&
               hipHostMalloc(&b->h_first, sizeof(int) * first_ints, hipHostMallocDefault) == hipSuccess &&
               (!own_scratch || (hipMalloc(&b->d_stats, sizeof(uint32_t) * nb * max_jobs) == hipSuccess &&
@@ -287,24 +289,47 @@ int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, con
     hipStream_t st = b->stream;
     hipError_t e;
     if (b->tune.mode == PSTEREO_BATCH_FUSED) {
-        // tasks in claim order: (blockstats, regions) of every frame, then
-        // (depth filter, warp) of every frame
-        int task = 0, s = 0;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int i = 0; i < n; ++i) {
-                for (int ph = 2 * pass; ph < 2 * pass + 2; ++ph) {
-                    BatchSeg sg;
-                    sg.frame = i;
-                    sg.phase = ph;
-                    sg.first = task;
-                    sg.ntask = pstereo::batch_tasks(b->h_frames[i], ph, &sg.items, &sg.gx);
-                    b->h_need[4 * i + ph] = sg.ntask;
-                    b->h_segs[s++] = sg;
-                    task += sg.ntask;
+        // frames to the XCDs' queues, largest first onto the queue with the
+        // fewest pixels; per queue, tasks in claim order: (blockstats,
+        // regions) of each of its frames, then (depth filter, warp) of each
+        constexpr int X = pstereo::kXcds;
+        std::vector<int> order(n), owner(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+            return (int64_t)jobs[a].w * jobs[a].h > (int64_t)jobs[c].w * jobs[c].h;
+        });
+        int64_t load[X] = {};
+        for (int i : order) {
+            int best = 0;
+            for (int x = 1; x < X; ++x)
+                if (load[x] < load[best]) best = x;
+            owner[i] = best;
+            load[best] += (int64_t)jobs[i].w * jobs[i].h;
+        }
+        int s = 0;
+        b->ntask = 0;
+        for (int x = 0; x < X; ++x) {
+            b->qseg[x] = s;
+            int task = 0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = 0; i < n; ++i) {
+                    if (owner[i] != x) continue;
+                    for (int ph = 2 * pass; ph < 2 * pass + 2; ++ph) {
+                        BatchSeg sg;
+                        sg.frame = i;
+                        sg.phase = ph;
+                        sg.first = task;
+                        sg.ntask = pstereo::batch_tasks(b->h_frames[i], ph, &sg.items, &sg.gx);
+                        b->h_need[4 * i + ph] = sg.ntask;
+                        b->h_segs[s++] = sg;
+                        task += sg.ntask;
+                    }
                 }
             }
+            b->qntask[x] = task;
+            b->ntask += task;
         }
-        b->ntask = task;
+        b->qseg[X] = s;
         b->grid = b->tune.fused_grid > 0 ? b->tune.fused_grid : b->cus;
         if ((e = hipMemcpyAsync(b->d_frames, b->h_frames, sizeof(FrameDesc) * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
             (e = hipMemcpyAsync(b->d_segs, b->h_segs, sizeof(BatchSeg) * 4 * n, hipMemcpyHostToDevice, st)) != hipSuccess ||
@@ -404,7 +429,8 @@ int pstereo_batch_launch(pstereo_batch* b, void* stream) {
     bd.need = b->d_need;
     bd.ctr = b->d_ctr;
     bd.nframes = b->n;
-    bd.ntask = b->ntask;
+    for (int x = 0; x <= pstereo::kXcds; ++x) bd.qseg[x] = b->qseg[x];
+    for (int x = 0; x < pstereo::kXcds; ++x) bd.qntask[x] = b->qntask[x];
     hipStream_t st = stream ? (hipStream_t)stream : b->stream;
     hipError_t e = b->tune.mode == PSTEREO_BATCH_FUSED ? pstereo::launch_batch(bd, b->r, b->grid, st)
                                                         : pstereo::launch_staged(b->d_frames, b->d_first, b->plan, st);
@@ -420,7 +446,8 @@ int pstereo_batch_run(pstereo_batch* b, const pstereo_job* jobs, int n, const ps
     if (p && (p->flags & PSTEREO_SYNC)) {
         if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, PSTEREO_E_DEVICE, "stream synchronize");
         uint32_t aborted = 0;
-        if (b->tune.mode == PSTEREO_BATCH_FUSED && hipMemcpy(&aborted, b->d_ctr + 1 + 4 * b->n, sizeof(aborted), hipMemcpyDeviceToHost) != hipSuccess)
+        if (b->tune.mode == PSTEREO_BATCH_FUSED &&
+            hipMemcpy(&aborted, b->d_ctr + pstereo::kXcds + 4 * b->n, sizeof(aborted), hipMemcpyDeviceToHost) != hipSuccess)
             return bfail(b, PSTEREO_E_DEVICE, "abort word read-back");
         if (aborted) return bfail(b, PSTEREO_E_DEVICE, "a dependency wait timed out; outputs are incomplete");
     }
@@ -435,7 +462,8 @@ int pstereo_batch_set_tuning(pstereo_batch* b, const pstereo_batch_tuning* t) {
     if (t->warp_lanes < 64 || t->warp_lanes > 1024 || t->warp_lanes % 64)
         return bfail(b, PSTEREO_E_INVALID, "warp_lanes %d not a multiple of 64 in 64..1024", t->warp_lanes);
     if (t->warp_rows < 1 || t->warp_rows > 8) return bfail(b, PSTEREO_E_INVALID, "warp_rows %d outside 1..8", t->warp_rows);
-    if (t->fused_grid < 0 || t->fused_grid > 65536) return bfail(b, PSTEREO_E_INVALID, "fused_grid out of range");
+    if (t->fused_grid < 0 || (t->fused_grid > 0 && t->fused_grid < pstereo::kXcds) || t->fused_grid > 65536)
+        return bfail(b, PSTEREO_E_INVALID, "fused_grid %d: 0 or 8..65536 (every XCD serves a queue)", t->fused_grid);
     b->tune = *t;
     b->prepared = false;  // the tables depend on the tuning
     return PSTEREO_OK;
