@@ -166,9 +166,9 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchDesc bd) {
         else if (sg.phase == 2) task_cbf<R>(fp, k, sg.items, sg.gx, lds);
         else task_warp(fp, k, lds);
         // publish: every lane's stores acknowledged by the L2, then one count
-        // (warp tasks have no dependent task: their outputs are read after
-        // the kernel)
-        __builtin_amdgcn_s_waitcnt(0);
+        // (warp tasks have no dependent task -- their outputs are read after
+        // the kernel -- so their stores need not drain here)
+        if (sg.phase < 3) __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0) {
             if (sg.phase < 3)
