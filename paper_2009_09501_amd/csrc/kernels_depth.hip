@@ -21,9 +21,22 @@ __global__ void __launch_bounds__(256) k_blockstats_k2(FrameDesc f) {
     bs_tile_k2(f, blockIdx.x, blockIdx.y, threadIdx.x, true);
 }
 
+// The signal of a finished depth map (pipelined calls; the kernel is one
+// workgroup): every wave waits until its stores are acknowledged, then one
+// lane's system-scope release store (which writes the L2 back first) sets the
+// word a stream's wait-value packet polls, so the kernels that packet releases
+// read the whole depth map from any XCD.
+__device__ __forceinline__ void signal_done(const FrameDesc& f) {
+    if (!f.sig) return;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(f.sig, f.sig_value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void __launch_bounds__(kRegionThreads) k_regions(FrameDesc f) {
     extern __shared__ uint32_t lds[];
     regions_body(f, lds);
+    signal_done(f);
 }
 
 __global__ void __launch_bounds__(kStripLanes) k_rg_strip(FrameDesc f) {
@@ -34,6 +47,7 @@ __global__ void __launch_bounds__(kStripLanes) k_rg_strip(FrameDesc f) {
 __global__ void __launch_bounds__(kStripLanes) k_rg_merge(FrameDesc f) {
     extern __shared__ uint32_t lds[];
     rg_merge_body(f, lds);
+    signal_done(f);
 }
 
 __global__ void __launch_bounds__(256) k_rg_final(FrameDesc f) { rg_final_block(f, blockIdx.x * 256 + threadIdx.x); }

@@ -96,7 +96,8 @@ struct pstereo_ctx {
     // pipelined calls (PSTEREO_PIPELINE): the depth-map stages go on `side`
     hipStream_t side = nullptr;
     hipEvent_t ev_before = nullptr;  // the caller's stream before the last pipelined call
-    hipEvent_t ev_depth = nullptr;   // the depth-map stages of the last pipelined call done
+    hipEvent_t ev_depth = nullptr;   // pipelined video: the depth-map graph of the frame done
+    unsigned long long* d_sig = nullptr;  // pipelined calls: number of the last call whose depth map is done
     bool pipe_valid = false;         // ev_before holds the previous pipelined call's mark
     hipStream_t pipe_stream = nullptr;
     long long pipe_n = 0;
@@ -215,7 +216,8 @@ int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
         return fail(nullptr, PSTEREO_E_DEVICE, "device setup failed: %s", hipGetErrorString(e));
     }
     if (block_scratch_alloc(c->blk[0]) != hipSuccess || block_scratch_alloc(c->blk[1]) != hipSuccess ||
-        hipMalloc(&c->d_df, (size_t)max_w * max_h) != hipSuccess) {
+        hipMalloc(&c->d_df, (size_t)max_w * max_h) != hipSuccess || hipMalloc(&c->d_sig, 64) != hipSuccess ||
+        hipMemset(c->d_sig, 0, 64) != hipSuccess) {
         (void)hipGetLastError();
         pstereo_destroy(c);
         return fail(nullptr, PSTEREO_E_NOMEM, "scratch allocation failed");
@@ -242,6 +244,7 @@ int pstereo_destroy(pstereo_ctx* c) {
     for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
     for (BlockScratch& b : c->blk) (void)hipFree(b.mem);
     (void)hipFree(c->d_df);
+    (void)hipFree(c->d_sig);
     if (c->ev_before) (void)hipEventDestroy(c->ev_before);
     if (c->ev_depth) (void)hipEventDestroy(c->ev_depth);
     if (c->side) (void)hipStreamDestroy(c->side);
@@ -469,8 +472,13 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
     // then); the filter and warp follow on the caller's stream once they are
     // done.  So this frame's depth map is built while the previous frame's
     // filter and warp run, and the set it writes was last read by the filter
-    // two frames back, which that mark already covers.
+    // two frames back, which that mark already covers.  The caller's stream
+    // learns that the depth map is done from a word of the context that the
+    // grouping's last kernel sets to the call's number and a wait-value packet
+    // polls (a few us, where an event pair between streams costs ~12 us); the
+    // word only grows, since only the side stream's kernels write it, in order.
     const bool pipe = (flags & PSTEREO_PIPELINE) && !ext && !inpaint;
+    const unsigned long long pv = (unsigned long long)c->pipe_n + 1;  // this call's number
     if (pipe) {
         const BlockScratch& bs = c->blk[c->pipe_n % 2];
         f.stats = bs.stats;
@@ -487,6 +495,8 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
             (e = hipStreamWaitEvent(c->side, c->ev_before, 0)) != hipSuccess ||
             (e = hipEventRecord(c->ev_before, s)) != hipSuccess)
             return fail(c, PSTEREO_E_DEVICE, "pipeline ordering: %s", hipGetErrorString(e));
+        f.sig = c->d_sig;
+        f.sig_value = pv;
     } else {
         c->pipe_valid = false;
     }
@@ -500,8 +510,7 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
         hipStream_t si = s;
         if (pipe && stage[i] <= 1) si = c->side;
         if (pipe && stage[i] == 2 &&
-            ((e = hipEventRecord(c->ev_depth, c->side)) != hipSuccess ||
-             (e = hipStreamWaitEvent(s, c->ev_depth, 0)) != hipSuccess)) {
+            (e = hipStreamWaitValue64(s, c->d_sig, pv, hipStreamWaitValueGte, ~0ull)) != hipSuccess) {
             if (prof) ev_stage[0] = -1;
             return fail(c, PSTEREO_E_DEVICE, "pipeline ordering: %s", hipGetErrorString(e));
         }

@@ -44,6 +44,10 @@ struct FrameDesc {
     uint32_t* ipc;           // colours, [2][h][w]
     uint16_t* ipt;           // tags, [2][h][w]
     uint32_t* ipn;           // pixels filled per sweep, [kMaxSweeps + 1]
+    // end-of-depth-map signal (pipelined calls): the grouping's last kernel
+    // stores sig_value to *sig when it is done (null: no signal)
+    unsigned long long* sig;
+    unsigned long long sig_value;
 };
 
 // Launch shape of the warp kernel (one image row per workgroup).
