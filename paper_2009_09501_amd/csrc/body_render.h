@@ -37,18 +37,36 @@ __host__ __device__ constexpr int k_index(int k) {
 }
 __host__ __device__ constexpr int k_count(int r) { return r == 0 ? 1 : r == 1 ? 3 : r == 2 ? 6 : 10; }
 
-// Product weights ws(k) * wr(d) of the cross-bilateral filter for every
-// distinct squared distance k (k_index order) and luma difference d = 0..255,
-// as u16 pairs (d even low, d + 1 high); the table for radius r is the prefix
-// of k_count(r) rows.  Built at compile time, copied into LDS per tile.
+// Product weights ws(k) * wr(|d|) of the cross-bilateral filter for every
+// distinct squared distance k (k_index order) and signed luma difference
+// d = -255..255.  In LDS row k holds 512 u16 entries, entry d + 255 (the last
+// one unused), two to a word; the table for radius r is the prefix of
+// k_count(r) rows.  Indexed by the signed difference, a tap's entry sits at
+// byte offset 2 Yq + (510 - 2 Yp) of its row (doubled luma), one add per tap.
+__host__ __device__ constexpr uint32_t cbf_w(int k, int j) {
+    return j < 511 ? spatial_w(k_value(k)) * range_w(j < 255 ? 255 - j : j - 255) : 0u;
+}
+// The range weight is 0 from |d| = kRangeTaps on, so only words kCbfW0 ..
+// kCbfW0 + kCbfWords - 1 of a row are non-zero; global memory holds just
+// those, in kCbfCopies copies that successive workgroups take in turn (every
+// workgroup reads the table, and one copy would sit in few L2 channels).
+constexpr int kRangeTaps = 43;
+constexpr int kCbfW0 = (255 - (kRangeTaps - 1)) / 2;             // 106
+constexpr int kCbfWords = (255 + (kRangeTaps - 1)) / 2 + 1 - kCbfW0;  // 43
+constexpr int kCbfCopies = 32;
+static_assert(range_w(kRangeTaps) == 0 && range_w(kRangeTaps - 1) != 0, "range weight support");
 struct CbfWeightTable {
-    uint32_t w[10 * 128];
+    uint32_t w[kCbfCopies][10 * kCbfWords];
 };
 __host__ __device__ constexpr CbfWeightTable make_cbf_weights() {
     CbfWeightTable t{};
     for (int k = 0; k < 10; ++k)
-        for (int d = 0; d < 256; d += 2)
-            t.w[k * 128 + d / 2] = spatial_w(k_value(k)) * range_w(d) | (spatial_w(k_value(k)) * range_w(d + 1)) << 16;
+        for (int i = 0; i < kCbfWords; ++i) {
+            const int j = 2 * (kCbfW0 + i);
+            t.w[0][k * kCbfWords + i] = cbf_w(k, j) | cbf_w(k, j + 1) << 16;
+        }
+    for (int c = 1; c < kCbfCopies; ++c)
+        for (int i = 0; i < 10 * kCbfWords; ++i) t.w[c][i] = t.w[0][i];
     return t;
 }
 __device__ const CbfWeightTable kCbfWeights = make_cbf_weights();
@@ -211,20 +229,21 @@ constexpr int kTileQuads = kTileQ + 2;       // quads per LDS row: one extra eac
 constexpr int kRowWords = 2 * kTileQuads;    // 36 dwords per LDS row and plane
 
 // Window of a pixel pair at an even LDS column c0: the words from the one
-// holding column c0 - R through the one holding c0 + 1 + R, plus one so that
-// an unpaired last tap may read its (zero-weight) neighbour.
+// holding column c0 - R through the one holding c0 + 1 + R.
 template <int R>
 struct CbfPairWin {
     static constexpr int kW0 = (R + 1) >> 1;  // words before c0's word
-    static constexpr int kWords = kW0 + 1 + ((R + 2) >> 1);
+    static constexpr int kWords = (2 * kW0 + 1 + R) / 2 + 1;
 };
 
 // Filtered depth of the two pixels x0, x0 + 1 of one row.  yw / dw: the
 // window words of each of the 2R + 1 rows, luma doubled and raw depth as u16
 // pairs; pixel j sits at window column 2 kW0 + j, so every tap's word and half
-// are compile-time constants.  Taps are paired (dx, dx + 1) so the weighted
-// depth sum and the weight sum each take one dot2 per pair.  CLIP: some
-// window column lies outside the image and gets weight 0.
+// are compile-time constants.  Taps go in pairs (c, c + 1) of one word (c
+// even; a pair's tap outside dx = -R..R has weight 0 and reads nothing), so
+// the weighted depth sum and the weight sum each take one dot2 per pair on the
+// word as stored.  CLIP: some window column lies outside the image and gets
+// weight 0.
 template <int R, bool CLIP>
 __device__ __forceinline__ void cbf_pair(const uint32_t (&yw)[2 * R + 1][CbfPairWin<R>::kWords],
                                          const uint32_t (&dw)[2 * R + 1][CbfPairWin<R>::kWords], uint32_t rows_ok,
@@ -234,7 +253,8 @@ __device__ __forceinline__ void cbf_pair(const uint32_t (&yw)[2 * R + 1][CbfPair
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int pc = 2 * CbfPairWin<R>::kW0 + j;
-        const uint32_t yp = (yw[R][pc >> 1] >> (16 * (pc & 1))) & 0xFFFFu;
+        // byte offset of a tap's weight in its table row: 2 Yq + (510 - 2 Yp)
+        const uint32_t base = 510u - ((yw[R][pc >> 1] >> (16 * (pc & 1))) & 0xFFFFu);
         uint32_t acc = 0, wsum = 0;
 #pragma unroll
         for (int dy = -R; dy <= R; ++dy) {
@@ -242,24 +262,21 @@ __device__ __forceinline__ void cbf_pair(const uint32_t (&yw)[2 * R + 1][CbfPair
             const uint32_t(&yr)[PW] = yw[dy + R];
             const uint32_t(&dr)[PW] = dw[dy + R];
 #pragma unroll
-            for (int dx = -R; dx <= R; dx += 2) {
-                const int c = pc + dx;
-                const bool pair = dx + 1 <= R;
-                const uint32_t y0 = (yr[c >> 1] >> (16 * (c & 1))) & 0xFFFFu;
-                // weight table: u16 entries indexed by |dY|, i.e. byte offset 2|dY|
-                uint32_t w0 = *reinterpret_cast<const uint16_t*>(wt + k_index(dx * dx + dy * dy) * 512 + absdiff16(y0, yp));
-                uint32_t w1 = 0;
-                if (pair) {
-                    const uint32_t y1 = (yr[(c + 1) >> 1] >> (16 * ((c + 1) & 1))) & 0xFFFFu;
-                    w1 = *reinterpret_cast<const uint16_t*>(wt + k_index((dx + 1) * (dx + 1) + dy * dy) * 512 + absdiff16(y1, yp));
+            for (int dx = -R - ((pc - R) & 1); dx <= R; dx += 2) {
+                const int c = pc + dx;  // even
+                uint32_t w0 = 0, w1 = 0;
+                if (dx >= -R) {
+                    const uint32_t y0 = yr[c >> 1] & 0xFFFFu;
+                    w0 = *reinterpret_cast<const uint16_t*>(wt + k_index(dx * dx + dy * dy) * 1024 + (y0 + base));
+                    if (CLIP && (unsigned)(x0 + j + dx) >= (unsigned)W) w0 = 0;
                 }
-                if (CLIP) {
-                    if ((unsigned)(x0 + j + dx) >= (unsigned)W) w0 = 0;
-                    if ((unsigned)(x0 + j + dx + 1) >= (unsigned)W) w1 = 0;
+                if (dx + 1 <= R) {
+                    const uint32_t y1 = yr[c >> 1] >> 16;
+                    w1 = *reinterpret_cast<const uint16_t*>(wt + k_index((dx + 1) * (dx + 1) + dy * dy) * 1024 + (y1 + base));
+                    if (CLIP && (unsigned)(x0 + j + dx + 1) >= (unsigned)W) w1 = 0;
                 }
                 const uint32_t wp = w0 | (w1 << 16);
-                const uint32_t dp = (c & 1) ? alignbyte(dr[(c + 1) >> 1], dr[c >> 1], 2) : dr[c >> 1];
-                acc = dot2_u16(wp, dp, acc);
+                acc = dot2_u16(wp, dr[c >> 1], acc);
                 wsum = dot2_u16(wp, 0x00010001u, wsum);
             }
         }
@@ -271,11 +288,11 @@ template <int R>
 struct CbfTile {
     static constexpr int TR = kTileH + 2 * R;  // LDS rows incl. halo
     static constexpr int NK = k_count(R);
-    // tY, tD: TR * kRowWords words each; wtab: NK * 256 u16; work: 512 u16; nwork
+    // tY, tD: TR * kRowWords words each; wtab: NK * 512 u16; work: 512 u16; nwork
     // block table of the tile, its halo and one ring of neighbours: at most
     // 21 x 13 blocks (K = 4, R = 3), uint2 each
     static constexpr int kBlkEntries = 288;
-    static constexpr int kBlkOff = (2 * TR * kRowWords + NK * 128 + 256 + 1 + 1) & ~1;  // 8-byte aligned
+    static constexpr int kBlkOff = (2 * TR * kRowWords + NK * 256 + 256 + 1 + 1) & ~1;  // 8-byte aligned
     static constexpr int kLdsWords = kBlkOff + 2 * kBlkEntries;
 };
 
@@ -316,7 +333,7 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
     uint32_t* tY = lds;
     uint32_t* tD = tY + TR * kRowWords;
     uint16_t* wtab = reinterpret_cast<uint16_t*>(tD + TR * kRowWords);
-    uint16_t* work = wtab + NK * 256;
+    uint16_t* work = wtab + NK * 512;
     int* nwork_p = reinterpret_cast<int*>(work + 512);
     int& nwork = *nwork_p;
     uint2* btab = reinterpret_cast<uint2*>(lds + CbfTile<R>::kBlkOff);
@@ -330,12 +347,15 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
     CbfIn<R> in;
     cbf_load<R, ALIGNED>(f, tile_x, tile_y, t, H, in);
 
-    // the weight table (NK * 32 16-byte pieces) likewise
-    constexpr int NW4 = NK * 32, NWL = (NW4 + 255) / 256;
-    uint4 wq[NWL];
+    // the non-zero words of the weight table likewise: lane t holds word t
+    // of every row
+    uint32_t wq[NK];
+    {
+        const uint32_t* src = kCbfWeights.w[(blockIdx.x + blockIdx.y) % kCbfCopies];
+        const bool nz = (unsigned)(t - kCbfW0) < (unsigned)kCbfWords;
 #pragma unroll
-    for (int k = 0; k < NWL; ++k)
-        if (t + 256 * k < NW4) wq[k] = reinterpret_cast<const uint4*>(kCbfWeights.w)[t + 256 * k];
+        for (int k = 0; k < NK; ++k) wq[k] = nz ? src[k * kCbfWords + t - kCbfW0] : 0u;
+    }
 
     // the tile's block table (halo and one ring of neighbours, clipped to the
     // grid) into LDS, so the raw depth needs no global lookups
@@ -364,8 +384,7 @@ __device__ __forceinline__ void cbf_tile(const FrameDesc& f, int tile_x, int til
         }
     }
 #pragma unroll
-    for (int k = 0; k < NWL; ++k)
-        if (t + 256 * k < NW4) reinterpret_cast<uint4*>(wtab)[t + 256 * k] = wq[k];
+    for (int k = 0; k < NK; ++k) reinterpret_cast<uint32_t*>(wtab)[k * 256 + t] = wq[k];
     if (t == 0) nwork = 0;
     __syncthreads();
 
