@@ -91,10 +91,6 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t dot2_u16(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b), c, false);
 }
-// |a - b| of two u16 values.  Both operands must arrive with zero upper
-// halves: passing unmasked words (the instruction is documented to read bits
-// 15:0 only) gave wrong results that varied from run to run.
-__device__ __forceinline__ uint32_t absdiff16(uint32_t a, uint32_t b) { return __builtin_amdgcn_sad_u16(a, b, 0u); }
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) { return __builtin_amdgcn_perm(hi, lo, sel); }
 __device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t s) { return __builtin_amdgcn_alignbyte(hi, lo, s); }
 
