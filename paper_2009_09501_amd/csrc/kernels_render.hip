@@ -13,6 +13,11 @@ namespace pstereo {
 template <int R, bool ALIGNED, bool K2>
 __global__ void __launch_bounds__(256) k_cbf(FrameDesc f) {
     __shared__ uint32_t lds[CbfTile<R>::kLdsWords];
+    // the start mark of a pipelined call: this kernel runs only once all
+    // earlier work on its stream is done (a system-scope store that a
+    // stream's wait-value packet polls; it publishes no data)
+    if (f.mark && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        __hip_atomic_store(f.mark, f.mark_value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     const int gx = gridDim.x;
     const int tile = xcd_tile(blockIdx.y * gx + blockIdx.x, gx * gridDim.y);
     const int ty = tile / gx;

@@ -95,10 +95,15 @@ struct pstereo_ctx {
     uint8_t* d_df = nullptr;  // filtered depth, max_w * max_h bytes
     // pipelined calls (PSTEREO_PIPELINE): the depth-map stages go on `side`
     hipStream_t side = nullptr;
-    hipEvent_t ev_before = nullptr;  // the caller's stream before the last pipelined call
+    // ev_before: the caller's stream at the start of a pipelined call with no
+    // pipelined call before it on that stream; pipelined video: the video's
+    // stream before the previous frame
+    hipEvent_t ev_before = nullptr;
     hipEvent_t ev_depth = nullptr;   // pipelined video: the depth-map graph of the frame done
-    unsigned long long* d_sig = nullptr;  // pipelined calls: number of the last call whose depth map is done
-    bool pipe_valid = false;         // ev_before holds the previous pipelined call's mark
+    // pipelined calls, call numbers: [0] the last call whose depth map is
+    // done, [1] the last call whose depth filter has started
+    unsigned long long* d_sig = nullptr;
+    bool pipe_valid = false;  // the previous pipelined call was on pipe_stream and its launches all went out
     hipStream_t pipe_stream = nullptr;
     long long pipe_n = 0;
     // block-iterative inpainting scratch, allocated on first use
@@ -467,16 +472,22 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
 
     // Pipelined call: the depth-map stages (block statistics, region
     // grouping) run on the context's side stream into block-table set
-    // pipe_n % 2, after the work the caller's stream held before the
-    // previous pipelined call (the caller promises the frame was complete
-    // then); the filter and warp follow on the caller's stream once they are
+    // pipe_n % 2 once the depth filter of the previous pipelined call on the
+    // caller's stream has started, so after everything the caller's stream
+    // held before that call, when the caller promises the frame was complete;
+    // the filter and warp follow on the caller's stream once the depth map is
     // done.  So this frame's depth map is built while the previous frame's
     // filter and warp run, and the set it writes was last read by the filter
-    // two frames back, which that mark already covers.  The caller's stream
-    // learns that the depth map is done from a word of the context that the
-    // grouping's last kernel sets to the call's number and a wait-value packet
-    // polls (a few us, where an event pair between streams costs ~12 us); the
-    // word only grows, since only the side stream's kernels write it, in order.
+    // two calls back, which has finished by then.  Both orderings go through
+    // words of the context that a wait-value packet polls (a few us, where an
+    // event pair between streams costs ~12 us, and an event recorded on the
+    // caller's stream at every call holds that stream up): the filter stores
+    // the call's number to the start word as it starts, the grouping's last
+    // kernel to the depth word as it ends.  Both words only grow: the side
+    // stream writes the depth word in order, and the first call on a stream
+    // (whose depth stages wait for its own start, an event) first waits until
+    // the last pipelined call's filter on the previous stream has started, so
+    // no filter of an older call is still to store its start.
     const bool pipe = (flags & PSTEREO_PIPELINE) && !ext && !inpaint;
     const unsigned long long pv = (unsigned long long)c->pipe_n + 1;  // this call's number
     if (pipe) {
@@ -491,12 +502,20 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
         f.rctl = bs.rctl;
         const bool first = !c->pipe_valid || c->pipe_stream != s;
         c->pipe_valid = false;  // until this call's launches are all enqueued
-        if ((first && (e = hipEventRecord(c->ev_before, s)) != hipSuccess) ||
-            (e = hipStreamWaitEvent(c->side, c->ev_before, 0)) != hipSuccess ||
-            (e = hipEventRecord(c->ev_before, s)) != hipSuccess)
+        if (first) {
+            if ((c->pipe_n > 0 && (e = hipStreamWaitValue64(s, c->d_sig + 1, (unsigned long long)c->pipe_n,
+                                                            hipStreamWaitValueGte, ~0ull)) != hipSuccess) ||
+                (e = hipEventRecord(c->ev_before, s)) != hipSuccess ||
+                (e = hipStreamWaitEvent(c->side, c->ev_before, 0)) != hipSuccess)
+                return fail(c, PSTEREO_E_DEVICE, "pipeline ordering: %s", hipGetErrorString(e));
+        } else if ((e = hipStreamWaitValue64(c->side, c->d_sig + 1, pv - 1, hipStreamWaitValueGte, ~0ull)) !=
+                   hipSuccess) {
             return fail(c, PSTEREO_E_DEVICE, "pipeline ordering: %s", hipGetErrorString(e));
+        }
         f.sig = c->d_sig;
         f.sig_value = pv;
+        f.mark = c->d_sig + 1;
+        f.mark_value = pv;
     } else {
         c->pipe_valid = false;
     }

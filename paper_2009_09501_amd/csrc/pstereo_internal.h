@@ -48,6 +48,11 @@ struct FrameDesc {
     // stores sig_value to *sig when it is done (null: no signal)
     unsigned long long* sig;
     unsigned long long sig_value;
+    // start-of-filter mark (pipelined calls): the depth filter stores
+    // mark_value to *mark as it starts, i.e. once everything before it on
+    // its stream is done (null: no mark)
+    unsigned long long* mark;
+    unsigned long long mark_value;
 };
 
 // Launch shape of the warp kernel (one image row per workgroup).
