@@ -99,7 +99,6 @@ struct pstereo_ctx {
     // pipelined call before it on that stream; pipelined video: the video's
     // stream before the previous frame
     hipEvent_t ev_before = nullptr;
-    hipEvent_t ev_depth = nullptr;   // pipelined video: the depth-map graph of the frame done
     // pipelined calls, call numbers: [0] the last call whose depth map is
     // done, [1] the last call whose depth filter has started
     unsigned long long* d_sig = nullptr;
@@ -229,7 +228,6 @@ int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
     }
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_before, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_depth, hipEventDisableTiming) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
         pstereo_destroy(c);
@@ -251,7 +249,6 @@ int pstereo_destroy(pstereo_ctx* c) {
     (void)hipFree(c->d_df);
     (void)hipFree(c->d_sig);
     if (c->ev_before) (void)hipEventDestroy(c->ev_before);
-    if (c->ev_depth) (void)hipEventDestroy(c->ev_depth);
     if (c->side) (void)hipStreamDestroy(c->side);
     (void)hipFree(c->d_ipc);
     (void)hipFree(c->d_ipt);
@@ -680,12 +677,15 @@ struct pstereo_video {
     pstereo_params params{};
     hipStream_t stream = nullptr;
     bool pipe = false;
-    bool pipe_started = false;  // the side stream's mark covers the previous frame
+    bool pipe_started = false;  // the previous frame went through the pipelined graphs
+    // pipelined: frame numbers, [0] the last frame whose depth map is done,
+    // [1] the last frame whose depth filter has started (both only grow)
+    unsigned long long* d_sig = nullptr;
     FrameDesc tmpl{};
     WarpShape ws{};
     pstereo::LaunchSpec ls[kMaxSpecs];
     int stage[kMaxSpecs] = {};
-    bool per_frame[kMaxSpecs] = {};  // node i reads the frame / output pointers
+    bool per_frame[kMaxSpecs] = {};  // node i reads the frame / output pointers or a frame number
     int gidx[kMaxSpecs] = {};        // node i's graph: 0, or 1 for the filter + warp of a pipelined video
     int nk = 0;
     hipGraph_t graph[2][kRing] = {};
@@ -705,6 +705,7 @@ static void video_free(pstereo_video* v) {
     }
     for (int k = 0; k < 2; ++k)
         if (v->done[k]) (void)hipEventDestroy(v->done[k]);
+    (void)hipFree(v->d_sig);
     delete v;
 }
 
@@ -772,10 +773,13 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
     v->tmpl.aligned = (w % 4 == 0);
     frame_specs(v->tmpl, v->ws, v->ls, v->nk, &v->stage);
     for (int i = 0; i < v->nk; ++i) {
-        v->per_frame[i] = v->stage[i] != 1;
+        // a pipelined video's last grouping kernel signals the frame's number
+        const bool signals = v->pipe && v->stage[i] == 1 && (i + 1 == v->nk || v->stage[i + 1] != 1);
+        v->per_frame[i] = v->stage[i] != 1 || signals;
         v->gidx[i] = v->pipe && v->stage[i] >= 2 ? 1 : 0;
     }
     hipError_t e = hipSetDevice(c->device);
+    if (v->pipe && e == hipSuccess && (e = hipMalloc(&v->d_sig, 16)) == hipSuccess) e = hipMemset(v->d_sig, 0, 16);
     for (int k = 0; k < pstereo_video::kRing && e == hipSuccess; ++k) {
         FrameDesc arg = video_desc(v, v->tmpl, k);
         void* args[] = {&arg};
@@ -839,6 +843,13 @@ int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, 
         }
     }
     FrameDesc arg = video_desc(v, f, k);
+    const unsigned long long fn = (unsigned long long)n + 1;  // this frame's number
+    if (v->pipe) {
+        arg.sig = v->d_sig;
+        arg.sig_value = fn;
+        arg.mark = v->d_sig + 1;
+        arg.mark_value = fn;
+    }
     void* args[] = {&arg};
     for (int i = 0; i < v->nk; ++i) {
         if (!v->per_frame[i]) continue;
@@ -847,15 +858,17 @@ int pstereo_video_frame(pstereo_video* v, const uint8_t* frame, uint8_t* out_l, 
             return fail(c, PSTEREO_E_DEVICE, "graph node update: %s", hipGetErrorString(e));
     }
     if (v->pipe) {
-        // the depth graph after what the stream held before the previous
-        // frame's call (everything, for the first frame); the filter and
-        // warp after it, on the stream
-        if ((!v->pipe_started && (e = hipEventRecord(c->ev_before, v->stream)) != hipSuccess) ||
-            (e = hipStreamWaitEvent(c->side, c->ev_before, 0)) != hipSuccess ||
-            (e = hipEventRecord(c->ev_before, v->stream)) != hipSuccess ||
+        // the depth graph once the previous frame's filter has started, so
+        // after what the stream held before that frame's call (for the first
+        // frame: after everything, an event); the filter and warp once the
+        // depth graph's grouping has signalled this frame's number (both
+        // through the video's words, polled by wait-value packets)
+        if ((!v->pipe_started && ((e = hipEventRecord(c->ev_before, v->stream)) != hipSuccess ||
+                                  (e = hipStreamWaitEvent(c->side, c->ev_before, 0)) != hipSuccess)) ||
+            (v->pipe_started &&
+             (e = hipStreamWaitValue64(c->side, v->d_sig + 1, fn - 1, hipStreamWaitValueGte, ~0ull)) != hipSuccess) ||
             (e = hipGraphLaunch(v->exec[0][k], c->side)) != hipSuccess ||
-            (e = hipEventRecord(c->ev_depth, c->side)) != hipSuccess ||
-            (e = hipStreamWaitEvent(v->stream, c->ev_depth, 0)) != hipSuccess ||
+            (e = hipStreamWaitValue64(v->stream, v->d_sig, fn, hipStreamWaitValueGte, ~0ull)) != hipSuccess ||
             (e = hipGraphLaunch(v->exec[1][k], v->stream)) != hipSuccess) {
             v->pipe_started = false;
             return fail(c, PSTEREO_E_DEVICE, "pipelined graph launch: %s", hipGetErrorString(e));
