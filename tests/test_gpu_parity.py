@@ -179,6 +179,43 @@ def test_deterministic_repeat(ctx, w, h, seed):
         refs.assert_views((L, R, A), want, f"{w}x{h} run {run}")
 
 
+@pytest.mark.parametrize("variant", ["k2", "gather", "profiled", "r0"])
+def test_pipelined_variants(ctx, oracle_mod, variant):
+    """PSTEREO_PIPELINE with 2 px blocks, the Fig. 3 gather, per-kernel
+    profiling and an unfiltered depth map (radius 0): a run of six calls on
+    one stream cycling three frames, every output equal to the oracle."""
+    from paper_2009_09501_amd.pstereo import (PSTEREO_PIPELINE, PSTEREO_PROFILE, PSTEREO_WARP_GATHER,
+                                              pstereo_profile_collect)
+    import refs
+    w, h = (320, 200) if variant == "k2" else (1280, 720)
+    B = synth.default_disparity(w)
+    host = [synth.gen_frame(500 + i, w, h, 12, 4.0) for i in range(3)]
+    dev = torch.device("cuda:0")
+    frames = [torch.from_numpy(f).to(dev) for f in host]
+    kw = {"K": 2} if variant == "k2" else {"r": 0} if variant == "r0" else {}
+    params = {"block_size": 2} if variant == "k2" else {"cbf_radius": 0} if variant == "r0" else {}
+    flags = PSTEREO_PIPELINE | (PSTEREO_WARP_GATHER if variant == "gather" else 0) | \
+        (PSTEREO_PROFILE if variant == "profiled" else 0)
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    pstereo_profile_collect(ctx.handle)  # clear
+    outs = []
+    for i in range(6):
+        print(f"pipelined {variant} call {i}", flush=True)
+        outs.append(ctx.synthesize(frames[i % 3], stream=st, flags=flags, max_disparity=B, **params))
+    st.synchronize()
+    for i, o in enumerate(outs):
+        f = host[i % 3]
+        if variant == "gather":
+            want = oracle_mod.synthesize_gather(f, B)
+        else:
+            want = refs.views(("pipe-variant", 500 + i % 3, w, h), f, B, **kw)
+        refs.assert_views(o, want, f"{variant} call {i}")
+    if variant == "profiled":
+        ms, n, _ = pstereo_profile_collect(ctx.handle)
+        assert n == 6 and all(m > 0 for m in ms)
+
+
 def test_default_stream_ordering(oracle_mod):
     """Work on torch's default stream (the HIP null stream): the frame
     written by a torch kernel just before the call, the outputs read by
