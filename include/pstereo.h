@@ -47,7 +47,7 @@ extern "C" {
 #define PSTEREO_E_NOMEM (-2)       /* device allocation failed (create only) */
 #define PSTEREO_E_DEVICE (-3)      /* a HIP runtime call or kernel launch failed */
 #define PSTEREO_E_ALIAS (-4)       /* output buffers overlap each other or an input */
-#define PSTEREO_E_UNSUPPORTED (-5) /* valid request this build cannot run (e.g. too wide for LDS) */
+#define PSTEREO_E_UNSUPPORTED (-5) /* valid request the library cannot run (e.g. too wide for LDS) */
 #define PSTEREO_E_BUSY (-6)        /* server: request not admitted now, retry later */
 
 /* Flags. */
