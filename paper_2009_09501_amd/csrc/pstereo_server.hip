@@ -57,6 +57,11 @@ struct Lane {
     hipStream_t st = nullptr;
     hipEvent_t done = nullptr;
     pstereo_batch* batch = nullptr;
+    // the lane's own context for batches of one frame (made on first need,
+    // remade larger for a larger frame), its largest frame and HBM bytes
+    pstereo_ctx* ctx = nullptr;
+    int cw = 0, ch = 0;
+    int64_t ctx_bytes = 0;
     std::vector<Request> reqs;
     bool busy = false;
     std::string err;  // message of the lane's last launch failure
@@ -182,6 +187,41 @@ void take_batch(pstereo_server* s, std::vector<Request>& out, int limit) {
     }
 }
 
+// The lane's context for a frame of w x h, made (or remade) for the largest
+// frame of the open streams if the HBM budget allows it (lock NOT held;
+// takes it to read the streams and the budget).  False: none.
+bool lane_context(pstereo_server* s, Lane& ln, int w, int h) {
+    if (ln.ctx && ln.cw >= w && ln.ch >= h) return true;
+    int cw = std::max(ln.cw, w), ch = std::max(ln.ch, h);
+    int64_t need;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (const StreamState& st : s->streams)
+            if (st.open) {
+                cw = std::max(cw, st.w);
+                ch = std::max(ch, st.h);
+            }
+        // filtered depth, and two sets of block tables of ~20 bytes per block
+        need = (int64_t)cw * ch + (int64_t)PSTEREO_MAX_BLOCKS * 40;
+        if (s->in_use - ln.ctx_bytes + need > s->budget) return false;
+        s->in_use += need - ln.ctx_bytes;
+    }
+    if (ln.ctx) pstereo_destroy(ln.ctx);  // waits for the device
+    ln.ctx = nullptr;
+    if (pstereo_create(&ln.ctx, s->device, cw, ch) != PSTEREO_OK) {
+        ln.ctx = nullptr;
+        std::lock_guard<std::mutex> g(s->mu);
+        s->in_use -= need;
+        ln.cw = ln.ch = 0;
+        ln.ctx_bytes = 0;
+        return false;
+    }
+    ln.cw = cw;
+    ln.ch = ch;
+    ln.ctx_bytes = need;
+    return true;
+}
+
 // Enqueue one lane's requests (lock NOT held: only the scheduler thread
 // touches lanes and slot memory).  Returns a status code.
 int launch_lane(pstereo_server* s, Lane& ln) {
@@ -216,7 +256,15 @@ int launch_lane(pstereo_server* s, Lane& ln) {
     pstereo_params_init(&p);
     p.stream = ln.st;
     int rc = PSTEREO_OK;
-    if (s->policy == PSTEREO_SERVE_BATCH) {
+    if (s->policy == PSTEREO_SERVE_BATCH && n == 1 && lane_context(s, ln, jobs[0].w, jobs[0].h)) {
+        // a batch of one frame: the per-frame launch sequence, whose
+        // strip-parallel grouping beats the batch's one-workgroup grouping of
+        // a whole frame
+        p.max_disparity = jobs[0].max_disparity;
+        rc = pstereo_synthesize(ln.ctx, jobs[0].frame, jobs[0].w, jobs[0].h, &p, jobs[0].out_left, jobs[0].out_right,
+                                jobs[0].out_anaglyph);
+        if (rc != PSTEREO_OK) return lfail(ln, rc, "frame: %s", pstereo_last_error(ln.ctx));
+    } else if (s->policy == PSTEREO_SERVE_BATCH) {
         rc = pstereo::batch_prepare_internal(ln.batch, jobs.data(), n, &p, scr.data(), false);
         if (rc == PSTEREO_OK) rc = pstereo_batch_launch(ln.batch, ln.st);
         if (rc != PSTEREO_OK) return lfail(ln, rc, "batch: %s", pstereo_batch_last_error(ln.batch));
@@ -304,6 +352,7 @@ void server_free(pstereo_server* s) {
     for (Lane& ln : s->lanes) {
         if (ln.st) (void)hipStreamSynchronize(ln.st);
         if (ln.batch) pstereo_batch_destroy(ln.batch);
+        if (ln.ctx) pstereo_destroy(ln.ctx);
         if (ln.done) (void)hipEventDestroy(ln.done);
         if (ln.st) (void)hipStreamDestroy(ln.st);
     }
