@@ -83,9 +83,12 @@ extern "C" {
                                        enqueued on params->stream (or had finished) before that
                                        previous pipelined call was made; the filter and warp still
                                        follow everything on params->stream.  Calls on the same
-                                       context alternate two sets of block tables.  Ignored with
-                                       PSTEREO_DEPTH_EXTERNAL or PSTEREO_INPAINT_BLOCKS; not for
-                                       stream capture */
+                                       context alternate two sets of block tables.  The two
+                                       streams order each other through stream wait-value packets
+                                       (which the runtime runs as small polling kernels), so a
+                                       profiler that serialises dispatches cannot run such calls.
+                                       Ignored with PSTEREO_DEPTH_EXTERNAL or
+                                       PSTEREO_INPAINT_BLOCKS; not for stream capture */
 
 /* Largest number of depth blocks per frame (region grouping runs in one
  * workgroup's LDS). */
