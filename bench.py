@@ -3,9 +3,10 @@
 One step = one 3840x2160 RGB24 frame through the whole per-frame pipeline
 (block statistics, region grouping, raw depth and cross-bilateral filter, both
 warps with hole fill and the anaglyph) with inputs already resident in HBM:
-one launch sequence per frame, the depth-map stages of frame i+1 on the
-context's second stream while frame i is filtered and warped
-(PSTEREO_PIPELINE).  Prints ONE JSON line with throughput, the HBM roofline
+one launch sequence per frame in three pipelined stages: the depth-map stages
+of frame i+2 on the context's second stream and the depth filter of frame i+1
+on its third while frame i is warped (PSTEREO_PIPELINE_DEEP; --stages 2 keeps
+the filter with the warp, --serial pipelines nothing).  Prints ONE JSON line with throughput, the HBM roofline
 fraction of the kernel that moves the path's algorithmic bytes (the warp; its
 duration from its own dispatch timestamps, HIP events taken by the launch
 itself over the timed region), the whole-path roofline fraction, latency from
@@ -36,6 +37,13 @@ STAGE_BYTES_PER_PX = {"k_blockstats": 3, "k_regions": 0, "k_cbf": 3, "k_warp": 1
 # Host threads for generating inputs and for the oracle's row-parallel mode:
 # the CPUs this process may run on, at most 16 (one GPU's share of the host).
 HOST_THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+PATHS = {1: "plain, serial (one stream)",
+         2: ("plain, pipelined: frame i+1's block statistics and region grouping on the context's second "
+             "stream during frame i's filter and warp (PSTEREO_PIPELINE)"),
+         3: ("plain, three-stage pipelined: frame i+2's block statistics and region grouping on the "
+             "context's second stream and frame i+1's filter on its third during frame i's warp "
+             "(PSTEREO_PIPELINE_DEEP)")}
+WORKLOADS = {1: "4k_serial", 2: "4k_pipelined", 3: "4k_pipelined3"}
 
 
 def _kernel_source_sha() -> str:
@@ -204,16 +212,17 @@ def cpu_baseline(budget_s: float = 4.0):
 
 
 # ------------------------------------------------------------- plain path
-def plain_run(torch, ctx, stream, frames, outs, B, steps, warmup, prewarm_s, every, pipeline):
+def plain_run(torch, ctx, stream, frames, outs, B, steps, warmup, prewarm_s, every, stages):
     """`warmup` untimed steps (after `prewarm_s` seconds of the same work to
     bring the clocks up), then `steps` timed steps bracketed by device
     synchronisation, every `every`-th of them (0 = none) with each kernel's
     dispatch timestamps recorded (a profiled launch costs the stream some
     time, so not every step is profiled).  Returns (seconds, per-stage mean
-    ms over the profiled steps or None, their count)."""
+    ms over the profiled steps or None, their count).  stages: 1 = serial
+    calls, 2 = PSTEREO_PIPELINE, 3 = PSTEREO_PIPELINE_DEEP."""
     from paper_2009_09501_amd import PSTEREO_PROFILE, pstereo_profile_collect
-    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE
-    base = PSTEREO_PIPELINE if pipeline else 0
+    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE, PSTEREO_PIPELINE_DEEP
+    base = {1: 0, 2: PSTEREO_PIPELINE, 3: PSTEREO_PIPELINE_DEEP}[stages]
     nf, no = len(frames), len(outs)
     # one profiled call first: the library creates its profiling events on
     # the first profiled call, which must not fall in the timed region
@@ -269,7 +278,7 @@ def latency_run(torch, ctx, stream, frames, outs, B, samples):
                     "host = call to stream synchronised"}
 
 
-def plain_leg(torch, synth, W, H, B, n_frames, n_outs, steps, warmup, prewarm_s, every, pipeline, seed0):
+def plain_leg(torch, synth, W, H, B, n_frames, n_outs, steps, warmup, prewarm_s, every, stages, seed0):
     """Frames/s, per-stage kernel times and roofline figures of the plain
     path at W x H over n_frames distinct inputs and n_outs output triples."""
     from paper_2009_09501_amd import Context
@@ -282,7 +291,7 @@ def plain_leg(torch, synth, W, H, B, n_frames, n_outs, steps, warmup, prewarm_s,
     stream = torch.cuda.Stream(device=dev)
     try:
         dt, stage_ms, count = plain_run(torch, ctx, stream, frames, outs, B, steps, warmup, prewarm_s, every,
-                                        pipeline)
+                                        stages)
     finally:
         torch.cuda.synchronize()
     px = W * H
@@ -643,12 +652,14 @@ def main() -> int:
     ap.add_argument("--outs", type=int, default=4, help="output triples cycled")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="record each kernel's dispatch timestamps on every N-th timed step (0 = never)")
-    ap.add_argument("--serial", action="store_true", help="headline without PSTEREO_PIPELINE")
+    ap.add_argument("--serial", action="store_true", help="headline with serial calls (no pipelining)")
+    ap.add_argument("--stages", type=int, choices=(2, 3), default=3,
+                    help="pipelined headline: 2 = PSTEREO_PIPELINE, 3 = PSTEREO_PIPELINE_DEEP")
     ap.add_argument("--latency-samples", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="serial,1080p,video,batch,serve,host,inpaint",
-                    help="extra measurements after the headline (serial, 1080p, video, batch, serve, host, "
-                         "inpaint; empty = none)")
+    ap.add_argument("--forms", default="serial,pipelined2,pipelined3,1080p,video,batch,serve,host,inpaint",
+                    help="extra measurements after the headline (serial, pipelined2, pipelined3: the plain 4K "
+                         "path in the other call modes; 1080p, video, batch, serve, host, inpaint; empty = none)")
     ap.add_argument("--host-frames", type=int, default=120)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (to scale HBM byte counters)")
@@ -700,9 +711,9 @@ def main() -> int:
     B = synth.default_disparity(W)
     px = W * H
     every = args.profile_every
-    pipeline = not args.serial
+    stages = 1 if args.serial else args.stages
     head, ctx, stream, frames, outs = plain_leg(torch, synth, W, H, B, args.frames, args.outs, args.steps,
-                                                args.warmup, args.prewarm_ms / 1e3, every, pipeline, 3)
+                                                args.warmup, args.prewarm_ms / 1e3, every, stages, 3)
     lat = latency_run(torch, ctx, stream, frames, outs, B, args.latency_samples)
     ctx.close()
     del frames, outs
@@ -724,9 +735,7 @@ def main() -> int:
         "config": {"workload": "4K 3840x2160 RGB24 single frames, plain per-frame launch sequence "
                                "(blockstats, region grouping, cbf, warp), max disparity 77 px",
                    "frames": head["frames"], "working_set_MB": head["working_set_MB"],
-                   "path": ("plain, pipelined: frame i+1's block statistics and region grouping on the "
-                            "context's second stream during frame i's filter and warp (PSTEREO_PIPELINE)")
-                   if pipeline else "plain, serial (one stream)",
+                   "path": PATHS[stages],
                    "prewarm_ms": args.prewarm_ms},
     }
     if head.get("stage_ms"):
@@ -734,7 +743,7 @@ def main() -> int:
         dom = "k_warp"
         dom_s = st[dom] / 1e3
         achieved = STAGE_BYTES_PER_PX[dom] * px / dom_s / 1e9
-        wl = "4k_pipelined" if pipeline else "4k_serial"
+        wl = WORKLOADS[stages]
         trace = _profile_record("kernels.json", f"{dom}@{wl}")
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -758,15 +767,18 @@ def main() -> int:
     out["latency"] = lat
     forms = [f for f in args.forms.split(",") if f]
     out["forms"] = {}
-    if "serial" in forms and pipeline:
-        r, c, _, _, _ = plain_leg(torch, synth, W, H, B, args.frames, args.outs, args.steps, 30,
-                                  args.prewarm_ms / 1e3, every, False, 3)
-        c.close()
-        r.pop("seconds")
-        out["forms"]["plain_serial_4k"] = r
+    for form, st, key in (("serial", 1, "plain_serial_4k"), ("pipelined2", 2, "plain_pipelined2_4k"),
+                          ("pipelined3", 3, "plain_pipelined3_4k")):
+        if form in forms and st != stages:
+            r, c, _, _, _ = plain_leg(torch, synth, W, H, B, args.frames, args.outs, args.steps, 30,
+                                      args.prewarm_ms / 1e3, every, st, 3)
+            c.close()
+            r.pop("seconds")
+            r["path"] = PATHS[st]
+            out["forms"][key] = r
     if "1080p" in forms:
         r, c, s, f, o = plain_leg(torch, synth, 1920, 1080, 38, args.frames, args.outs, 2 * args.steps, 100,
-                                  args.prewarm_ms / 1e3, every, pipeline, 2)
+                                  args.prewarm_ms / 1e3, every, stages, 2)
         r["latency"] = latency_run(torch, c, s, f, o, 38, args.latency_samples)
         c.close()
         del f, o

@@ -89,6 +89,20 @@ extern "C" {
                                        profiler that serialises dispatches cannot run such calls.
                                        Ignored with PSTEREO_DEPTH_EXTERNAL or
                                        PSTEREO_INPAINT_BLOCKS; not for stream capture */
+#define PSTEREO_PIPELINE_DEEP 0x40u /* three-stage pipelined plain calls (implies PSTEREO_PIPELINE):
+                                       the depth-map stages on the context's second stream, the
+                                       depth filter on a third one and the warp on params->stream,
+                                       so that this call's depth map, the previous call's filter
+                                       and the warp of the call before that run at once.  The
+                                       caller promises that everything writing this call's frame
+                                       was enqueued on params->stream (or had finished) before the
+                                       pipelined call two calls back was made (frames supplied two
+                                       ahead); the warp still follows everything on
+                                       params->stream.  Calls alternate two sets of block tables
+                                       and two filtered-depth images.  A call that changes stream
+                                       or mode, or follows another kind of call, starts the
+                                       pipeline again.  Same exclusions as PSTEREO_PIPELINE; the
+                                       video calls reject it */
 
 /* Largest number of depth blocks per frame (region grouping runs in one
  * workgroup's LDS). */
@@ -215,7 +229,7 @@ int pstereo_profile_collect(pstereo_ctx *ctx, double ms_sum[4], int *count,
  *   frame, w, h, p, out_left, out_right, out_anaglyph: as pstereo_synthesize,
  *                with w * h <= PSTEREO_NOALLOC_MAX_PIXELS (one 4K frame);
  *                larger frames return PSTEREO_E_INVALID
- * PSTEREO_PROFILE, PSTEREO_INPAINT_BLOCKS and PSTEREO_PIPELINE return
+ * PSTEREO_PROFILE, PSTEREO_INPAINT_BLOCKS, PSTEREO_PIPELINE and PSTEREO_PIPELINE_DEEP return
  * PSTEREO_E_UNSUPPORTED (they need a context's events, scratch or stream).
  * Every call on one GPU shares that GPU's array, whose contents the last call
  * left: calls that overlap on one GPU (two host threads, or two streams not

@@ -56,6 +56,12 @@ __global__ void __launch_bounds__(64) k_clear_words(uint32_t* p, int n) {
     for (int i = threadIdx.x; i < n; i += 64) p[i] = 0u;
 }
 
+// The end of the kernels before it on its stream, as a word a wait-value
+// packet polls: it runs once they are done and their stores written back.
+__global__ void __launch_bounds__(64) k_signal(unsigned long long* p, unsigned long long v) {
+    if (threadIdx.x == 0) __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ---------------------------------------------------------------------------
 // host-side launch helpers
 
@@ -110,6 +116,11 @@ LaunchSpec spec_rg_final(const FrameDesc& f) {
 
 hipError_t launch_clear_words(uint32_t* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_signal(unsigned long long* p, unsigned long long v, hipStream_t s) {
+    hipLaunchKernelGGL(k_signal, dim3(1), dim3(64), 0, s, p, v);
     return hipGetLastError();
 }
 

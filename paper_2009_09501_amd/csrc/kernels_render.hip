@@ -10,6 +10,14 @@
 
 namespace pstereo {
 
+// The warp's start mark (three-stage pipelined calls), stored by the first
+// lane of the first workgroup: the kernel runs only once all earlier work on
+// its stream is done.
+__device__ __forceinline__ void warp_start_mark(const FrameDesc& f) {
+    if (f.wmark && blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_store(f.wmark, f.wmark_value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <int R, bool ALIGNED, bool K2>
 __global__ void __launch_bounds__(256) k_cbf(FrameDesc f) {
     __shared__ uint32_t lds[CbfTile<R>::kLdsWords];
@@ -30,6 +38,7 @@ __global__ void __launch_bounds__(256) k_cbf(FrameDesc f) {
 template <bool ALIGNED, int Q>
 __global__ void __launch_bounds__(512) k_warp(FrameDesc f) {
     extern __shared__ uint32_t lds[];
+    warp_start_mark(f);
     warp_rows<ALIGNED, Q>(f, blockIdx.x, f.h, gridDim.x, threadIdx.x, blockDim.x, lds);
 }
 
@@ -39,12 +48,14 @@ __global__ void __launch_bounds__(512) k_warp(FrameDesc f) {
 template <bool ALIGNED>
 __global__ void __launch_bounds__(1024) k_warp_wide(FrameDesc f) {
     extern __shared__ uint32_t lds[];
+    warp_start_mark(f);
     warp_row<ALIGNED, 4>(f, blockIdx.x, threadIdx.x, blockDim.x, lds, true);
 }
 
 template <bool ALIGNED>
 __global__ void __launch_bounds__(256) k_gather(FrameDesc f) {
     extern __shared__ uint32_t lds[];
+    warp_start_mark(f);
     gather_row<ALIGNED>(f, blockIdx.x, threadIdx.x, blockDim.x, lds);
 }
 

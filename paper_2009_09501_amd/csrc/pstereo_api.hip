@@ -83,6 +83,9 @@ hipError_t block_scratch_alloc(BlockScratch& b) {
     return hipMemset(b.rctl, 0, 4 * sizeof(uint32_t));
 }
 
+// One filtered-depth image, rounded up so that the second one stays aligned.
+size_t df_image_bytes(int w, int h) { return align256((size_t)w * h); }
+
 }  // namespace
 
 struct pstereo_ctx {
@@ -93,16 +96,25 @@ struct pstereo_ctx {
     // frame's filter still reads its set
     BlockScratch blk[2];
     uint8_t* d_df = nullptr;  // filtered depth, max_w * max_h bytes
-    // pipelined calls (PSTEREO_PIPELINE): the depth-map stages go on `side`
+    // second filtered-depth image (three-stage pipelined calls alternate the
+    // two), in the same allocation
+    uint8_t* d_df2 = nullptr;
+    // pipelined calls (PSTEREO_PIPELINE): the depth-map stages go on `side`;
+    // three-stage calls (PSTEREO_PIPELINE_DEEP) put the filter on `mid`
     hipStream_t side = nullptr;
+    hipStream_t mid = nullptr;
     // ev_before: the caller's stream at the start of a pipelined call with no
     // pipelined call before it on that stream; pipelined video: the video's
     // stream before the previous frame
     hipEvent_t ev_before = nullptr;
     // pipelined calls, call numbers: [0] the last call whose depth map is
-    // done, [1] the last call whose depth filter has started
+    // done, [1] the last call whose depth filter has started; three-stage
+    // calls also [2] the last call whose filter is done, [3] the last call
+    // whose warp has started
     unsigned long long* d_sig = nullptr;
     bool pipe_valid = false;  // the previous pipelined call was on pipe_stream and its launches all went out
+    bool pipe_deep = false;   // the previous pipelined call was a three-stage one
+    bool pipe_drained = false;  // no kernel of an earlier pipelined call is still to store a mark
     hipStream_t pipe_stream = nullptr;
     long long pipe_n = 0;
     // block-iterative inpainting scratch, allocated on first use
@@ -220,13 +232,15 @@ int pstereo_create(pstereo_ctx** out, int device, int max_w, int max_h) {
         return fail(nullptr, PSTEREO_E_DEVICE, "device setup failed: %s", hipGetErrorString(e));
     }
     if (block_scratch_alloc(c->blk[0]) != hipSuccess || block_scratch_alloc(c->blk[1]) != hipSuccess ||
-        hipMalloc(&c->d_df, (size_t)max_w * max_h) != hipSuccess || hipMalloc(&c->d_sig, 64) != hipSuccess ||
+        hipMalloc(&c->d_df, 2 * df_image_bytes(max_w, max_h)) != hipSuccess || hipMalloc(&c->d_sig, 64) != hipSuccess ||
         hipMemset(c->d_sig, 0, 64) != hipSuccess) {
         (void)hipGetLastError();
         pstereo_destroy(c);
         return fail(nullptr, PSTEREO_E_NOMEM, "scratch allocation failed");
     }
+    c->d_df2 = c->d_df + df_image_bytes(max_w, max_h);
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->mid, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_before, hipEventDisableTiming) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
@@ -250,6 +264,7 @@ int pstereo_destroy(pstereo_ctx* c) {
     (void)hipFree(c->d_sig);
     if (c->ev_before) (void)hipEventDestroy(c->ev_before);
     if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->mid) (void)hipStreamDestroy(c->mid);
     (void)hipFree(c->d_ipc);
     (void)hipFree(c->d_ipt);
     (void)hipFree(c->d_ipn);
@@ -469,24 +484,47 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
 
     // Pipelined call: the depth-map stages (block statistics, region
     // grouping) run on the context's side stream into block-table set
-    // pipe_n % 2 once the depth filter of the previous pipelined call on the
-    // caller's stream has started, so after everything the caller's stream
-    // held before that call, when the caller promises the frame was complete;
-    // the filter and warp follow on the caller's stream once the depth map is
-    // done.  So this frame's depth map is built while the previous frame's
-    // filter and warp run, and the set it writes was last read by the filter
-    // two calls back, which has finished by then.  Both orderings go through
-    // words of the context that a wait-value packet polls (a few us, where an
-    // event pair between streams costs ~12 us, and an event recorded on the
-    // caller's stream at every call holds that stream up): the filter stores
-    // the call's number to the start word as it starts, the grouping's last
-    // kernel to the depth word as it ends.  Both words only grow: the side
-    // stream writes the depth word in order, and the first call on a stream
-    // (whose depth stages wait for its own start, an event) first waits until
-    // the last pipelined call's filter on the previous stream has started, so
-    // no filter of an older call is still to store its start.
-    const bool pipe = (flags & PSTEREO_PIPELINE) && !ext && !inpaint;
+    // pipe_n % 2 once the depth filter of the previous pipelined call has
+    // started.  Two stages: that is after everything the caller's stream
+    // held before the previous call's filter, when the caller promises the
+    // frame was complete; the filter and warp follow on the caller's stream
+    // once the depth map is done.  So this frame's depth map is built while
+    // the previous frame's filter and warp run, and the set it writes was
+    // last read by the filter two calls back, which has finished by then.
+    // Three stages: the filter goes on the context's third stream once the
+    // depth map is done and the previous call's warp has started (so the warp
+    // two calls back, the last reader of the filtered-depth image pipe_n % 2
+    // that it writes, has finished); a small kernel after it marks its end,
+    // and the warp follows on the caller's stream once that mark is there.
+    // Then the depth map of frame i+2, the filter of frame i+1 and the warp
+    // of frame i run together, and a filter's start implies the warp's start
+    // one call earlier, so everything the caller's stream held before the
+    // call two back.  The orderings go through words of the context that a
+    // wait-value packet polls (a few us, where an event pair between streams
+    // costs ~12 us, and an event recorded on the caller's stream at every
+    // call holds that stream up); every wait's releasing kernel was enqueued
+    // before the wait, so the orderings also hold where streams share a
+    // hardware queue.  The words only grow: each is written by one stream in
+    // call order, and the first call on a stream, or in a mode, (whose depth
+    // stages wait for its own start, an event) first waits until the last
+    // pipelined call's last mark -- its filter's start, or its warp's start
+    // for three stages -- is stored, so no kernel of an older call is still
+    // to store one.  A call that fails once its work has begun drains the
+    // streams and gives up its number.
+    const bool deep = (flags & PSTEREO_PIPELINE_DEEP) != 0;
+    const bool pipe = (flags & (PSTEREO_PIPELINE | PSTEREO_PIPELINE_DEEP)) && !ext && !inpaint;
     const unsigned long long pv = (unsigned long long)c->pipe_n + 1;  // this call's number
+    bool first = false;
+    auto pipe_fail = [&](const char* what, hipError_t err) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamSynchronize(c->mid);
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
+        c->pipe_n = (long long)pv;
+        c->pipe_drained = true;
+        if (prof) ev_stage[0] = -1;  // nothing of this call is collected
+        return fail(c, PSTEREO_E_DEVICE, "%s: %s", what, hipGetErrorString(err));
+    };
     if (pipe) {
         const BlockScratch& bs = c->blk[c->pipe_n % 2];
         f.stats = bs.stats;
@@ -497,22 +535,28 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
         f.rfin = bs.rfin;
         f.rbnd = bs.rbnd;
         f.rctl = bs.rctl;
-        const bool first = !c->pipe_valid || c->pipe_stream != s;
+        if (deep) f.df = c->pipe_n % 2 ? c->d_df2 : c->d_df;
+        first = !c->pipe_valid || c->pipe_stream != s || c->pipe_deep != deep;
         c->pipe_valid = false;  // until this call's launches are all enqueued
         if (first) {
-            if ((c->pipe_n > 0 && (e = hipStreamWaitValue64(s, c->d_sig + 1, (unsigned long long)c->pipe_n,
-                                                            hipStreamWaitValueGte, ~0ull)) != hipSuccess) ||
+            if ((c->pipe_n > 0 && !c->pipe_drained &&
+                 (e = hipStreamWaitValue64(s, c->d_sig + (c->pipe_deep ? 3 : 1), (unsigned long long)c->pipe_n,
+                                           hipStreamWaitValueGte, ~0ull)) != hipSuccess) ||
                 (e = hipEventRecord(c->ev_before, s)) != hipSuccess ||
                 (e = hipStreamWaitEvent(c->side, c->ev_before, 0)) != hipSuccess)
-                return fail(c, PSTEREO_E_DEVICE, "pipeline ordering: %s", hipGetErrorString(e));
+                return pipe_fail("pipeline ordering", e);
         } else if ((e = hipStreamWaitValue64(c->side, c->d_sig + 1, pv - 1, hipStreamWaitValueGte, ~0ull)) !=
                    hipSuccess) {
-            return fail(c, PSTEREO_E_DEVICE, "pipeline ordering: %s", hipGetErrorString(e));
+            return pipe_fail("pipeline ordering", e);
         }
         f.sig = c->d_sig;
         f.sig_value = pv;
         f.mark = c->d_sig + 1;
         f.mark_value = pv;
+        if (deep) {
+            f.wmark = c->d_sig + 3;
+            f.wmark_value = pv;
+        }
     } else {
         c->pipe_valid = false;
     }
@@ -525,20 +569,29 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
     for (int i = 0; i < n; ++i) {
         hipStream_t si = s;
         if (pipe && stage[i] <= 1) si = c->side;
-        if (pipe && stage[i] == 2 &&
-            (e = hipStreamWaitValue64(s, c->d_sig, pv, hipStreamWaitValueGte, ~0ull)) != hipSuccess) {
-            if (prof) ev_stage[0] = -1;
-            return fail(c, PSTEREO_E_DEVICE, "pipeline ordering: %s", hipGetErrorString(e));
+        if (pipe && stage[i] == 2) {
+            if (deep) si = c->mid;
+            if ((e = hipStreamWaitValue64(si, c->d_sig, pv, hipStreamWaitValueGte, ~0ull)) != hipSuccess ||
+                (deep && !first &&
+                 (e = hipStreamWaitValue64(si, c->d_sig + 3, pv - 1, hipStreamWaitValueGte, ~0ull)) != hipSuccess))
+                return pipe_fail("pipeline ordering", e);
         }
+        if (pipe && deep && stage[i] == 3 &&
+            (e = hipStreamWaitValue64(s, c->d_sig + 2, pv, hipStreamWaitValueGte, ~0ull)) != hipSuccess)
+            return pipe_fail("pipeline ordering", e);
         // a profiled call takes each kernel's own start and stop times
         e = prof ? pstereo::launch_timed(ls[i], f, si, ev[2 * i], ev[2 * i + 1]) : pstereo::launch(ls[i], f, si);
+        if (e == hipSuccess && pipe && deep && stage[i] == 2) e = pstereo::launch_signal(c->d_sig + 2, pv, si);
         if (e != hipSuccess) {
+            if (pipe) return pipe_fail(names[stage[i]], e);
             if (prof) ev_stage[0] = -1;  // nothing of this call is collected
             return fail(c, PSTEREO_E_DEVICE, "%s launch: %s", names[stage[i]], hipGetErrorString(e));
         }
     }
     if (pipe) {
         c->pipe_valid = true;
+        c->pipe_deep = deep;
+        c->pipe_drained = false;
         c->pipe_stream = s;
         c->pipe_n++;
     }
@@ -752,6 +805,8 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
                                               "PSTEREO_DEPTH_EXTERNAL / PSTEREO_WARP_GATHER)");
     if (pp.out_depth || pp.out_depth_raw || pp.out_hsbs)
         return fail(c, PSTEREO_E_UNSUPPORTED, "video replay takes no depth dumps");
+    if (pp.flags & PSTEREO_PIPELINE_DEEP)
+        return fail(c, PSTEREO_E_UNSUPPORTED, "video replay pipelines two stages (PSTEREO_PIPELINE), not three");
     pstereo_video* v = new (std::nothrow) pstereo_video;
     if (!v) return fail(c, PSTEREO_E_NOMEM, "host allocation failed");
     v->ctx = c;
@@ -964,9 +1019,9 @@ extern "C" int pstereo_synthesize_noalloc(int device, const uint8_t* frame, int 
     int rc = noalloc_setup(device, &d);
     if (rc != PSTEREO_OK) return rc;
     if (pin && pin->struct_size == sizeof(pstereo_params) &&
-        (pin->flags & (PSTEREO_PROFILE | PSTEREO_INPAINT_BLOCKS | PSTEREO_PIPELINE)))
+        (pin->flags & (PSTEREO_PROFILE | PSTEREO_INPAINT_BLOCKS | PSTEREO_PIPELINE | PSTEREO_PIPELINE_DEEP)))
         return fail(nullptr, PSTEREO_E_UNSUPPORTED,
-                    "PSTEREO_PROFILE, PSTEREO_INPAINT_BLOCKS and PSTEREO_PIPELINE need a context");
+                    "PSTEREO_PROFILE, PSTEREO_INPAINT_BLOCKS and PSTEREO_PIPELINE(_DEEP) need a context");
     if (w < 1 || h < 1 || (int64_t)w * h > (int64_t)PSTEREO_NOALLOC_MAX_PIXELS)
         return fail(nullptr, PSTEREO_E_INVALID, "frame %dx%d outside 1..%d pixels of the static scratch", w, h,
                     PSTEREO_NOALLOC_MAX_PIXELS);

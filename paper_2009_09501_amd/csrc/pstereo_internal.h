@@ -53,6 +53,10 @@ struct FrameDesc {
     // its stream is done (null: no mark)
     unsigned long long* mark;
     unsigned long long mark_value;
+    // start-of-warp mark (three-stage pipelined calls): the warp stores
+    // wmark_value to *wmark as it starts (null: no mark)
+    unsigned long long* wmark;
+    unsigned long long wmark_value;
 };
 
 // Launch shape of the warp kernel (one image row per workgroup).
@@ -114,6 +118,8 @@ inline hipError_t launch_timed(const LaunchSpec& ls, const FrameDesc& f, hipStre
 size_t regions_lds_bytes(int nb);
 // Zero n words with a kernel (no memset node, so it can sit in a captured graph).
 hipError_t launch_clear_words(uint32_t* p, int n, hipStream_t s);
+// Store v to *p (system-scope release) once everything before it on s is done.
+hipError_t launch_signal(unsigned long long* p, unsigned long long v, hipStream_t s);
 hipError_t prepare_depth_kernels();
 hipError_t prepare_render_kernels();
 

@@ -29,6 +29,7 @@ PSTEREO_PROFILE = 0x4
 PSTEREO_WARP_GATHER = 0x8
 PSTEREO_INPAINT_BLOCKS = 0x10
 PSTEREO_PIPELINE = 0x20
+PSTEREO_PIPELINE_DEEP = 0x40
 
 PSTEREO_MAX_BLOCKS = 32768
 

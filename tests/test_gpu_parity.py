@@ -162,31 +162,35 @@ def test_zero_base_identity(ctx):
 
 @pytest.mark.parametrize("w,h,seed", [(1920, 1080, 21), (3840, 2160, 22), (7680, 4320, 23)])
 def test_deterministic_repeat(ctx, w, h, seed):
-    """Three runs of one frame, plain and pipelined, each equal to the
-    oracle (4K and 8K take the two warp row shapes: two and four quads per
-    lane)."""
-    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE
+    """Four runs of one frame, plain, pipelined and three-stage pipelined,
+    each equal to the oracle (4K and 8K take the two warp row shapes: two and
+    four quads per lane)."""
+    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE, PSTEREO_PIPELINE_DEEP
     import refs
     f = synth.gen_frame(seed, w, h, 40, 4.0)
     B = synth.default_disparity(w)
     want = refs.views(("still", seed, w, h), f, B)
     dev = torch.device("cuda:0")
     ft = torch.from_numpy(f).to(dev)
-    for run in range(3):
+    for run, fl in enumerate((0, 0, PSTEREO_PIPELINE, PSTEREO_PIPELINE_DEEP)):
         print(f"repeat {w}x{h} run {run}", flush=True)
-        L, R, A = ctx.synthesize(ft, max_disparity=B, flags=PSTEREO_PIPELINE if run == 2 else 0)
+        L, R, A = ctx.synthesize(ft, max_disparity=B, flags=fl)
         torch.cuda.synchronize()
         refs.assert_views((L, R, A), want, f"{w}x{h} run {run}")
 
 
-@pytest.mark.parametrize("variant", ["k2", "gather", "profiled", "r0"])
+@pytest.mark.parametrize("variant", ["k2", "gather", "profiled", "r0", "deep-k2", "deep-gather", "deep-profiled",
+                                     "deep-r0"])
 def test_pipelined_variants(ctx, oracle_mod, variant):
-    """PSTEREO_PIPELINE with 2 px blocks, the Fig. 3 gather, per-kernel
-    profiling and an unfiltered depth map (radius 0): a run of six calls on
-    one stream cycling three frames, every output equal to the oracle."""
-    from paper_2009_09501_amd.pstereo import (PSTEREO_PIPELINE, PSTEREO_PROFILE, PSTEREO_WARP_GATHER,
-                                              pstereo_profile_collect)
+    """PSTEREO_PIPELINE and PSTEREO_PIPELINE_DEEP with 2 px blocks, the
+    Fig. 3 gather, per-kernel profiling and an unfiltered depth map (radius
+    0): a run of six calls on one stream cycling three frames, every output
+    equal to the oracle."""
+    from paper_2009_09501_amd.pstereo import (PSTEREO_PIPELINE, PSTEREO_PIPELINE_DEEP, PSTEREO_PROFILE,
+                                              PSTEREO_WARP_GATHER, pstereo_profile_collect)
     import refs
+    deep = variant.startswith("deep-")
+    variant = variant.removeprefix("deep-")
     w, h = (320, 200) if variant == "k2" else (1280, 720)
     B = synth.default_disparity(w)
     host = [synth.gen_frame(500 + i, w, h, 12, 4.0) for i in range(3)]
@@ -194,8 +198,8 @@ def test_pipelined_variants(ctx, oracle_mod, variant):
     frames = [torch.from_numpy(f).to(dev) for f in host]
     kw = {"K": 2} if variant == "k2" else {"r": 0} if variant == "r0" else {}
     params = {"block_size": 2} if variant == "k2" else {"cbf_radius": 0} if variant == "r0" else {}
-    flags = PSTEREO_PIPELINE | (PSTEREO_WARP_GATHER if variant == "gather" else 0) | \
-        (PSTEREO_PROFILE if variant == "profiled" else 0)
+    flags = (PSTEREO_PIPELINE_DEEP if deep else PSTEREO_PIPELINE) | \
+        (PSTEREO_WARP_GATHER if variant == "gather" else 0) | (PSTEREO_PROFILE if variant == "profiled" else 0)
     st = torch.cuda.Stream()
     torch.cuda.synchronize()
     pstereo_profile_collect(ctx.handle)  # clear
@@ -294,6 +298,55 @@ def test_pipelined_sequence(oracle_mod):
         ctx.close()
 
 
+def test_pipelined_deep_sequence(oracle_mod):
+    """PSTEREO_PIPELINE_DEEP over a run of frames of several sizes, mixed
+    with two-stage pipelined and plain calls, stream changes and a block dump
+    (each restarts the pipeline), then a long three-stage run on one stream
+    and one on the null stream: every output equals the oracle."""
+    from paper_2009_09501_amd import Context, pstereo_debug_blocks
+    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE, PSTEREO_PIPELINE_DEEP
+    import refs
+    dev = torch.device("cuda:0")
+    sizes = [(1920, 1080), (1920, 1080), (640, 360), (1920, 1080), (1280, 720), (333, 191), (1920, 1080),
+             (1920, 1080), (1280, 720), (1920, 1080), (640, 360)]
+    D, P = PSTEREO_PIPELINE_DEEP, PSTEREO_PIPELINE
+    flags = [D, D, D, 0, D, D, D, P, D, D, D]
+    host = [synth.gen_frame(300 + i, w, h, 40, 4.0) for i, (w, h) in enumerate(sizes)]
+    frames = [torch.from_numpy(f).to(dev) for f in host]
+    ctx = Context(0, 1920, 1080)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        outs = []
+        for i, (f, (w, h), fl) in enumerate(zip(frames, sizes, flags)):
+            st = s2 if i in (6, 7) else s1
+            if i == 6:
+                s2.wait_stream(s1)  # the caller orders a stream change
+            if i == 8:
+                s1.wait_stream(s2)
+            print(f"deep pipelined call {i}: {w}x{h} flags {fl}", flush=True)
+            outs.append(ctx.synthesize(f, stream=st, flags=fl, max_disparity=synth.default_disparity(w)))
+            if i == 4:
+                st.synchronize()
+                stt, lab, db = pstereo_debug_blocks(ctx.handle)
+                ref = oracle_mod.synthesize(host[4], synth.default_disparity(1280))
+                assert np.array_equal(stt, ref.stats) and np.array_equal(lab, ref.labels)
+                assert np.array_equal(db, ref.dblk)
+        torch.cuda.synchronize()
+        for i, ((w, h), f, o) in enumerate(zip(sizes, host, outs)):
+            refs.assert_views(o, refs.views(("pipe", 300 + i, w, h), f, synth.default_disparity(w)), f"call {i}")
+        ring = [0, 1, 3, 6]
+        for name, st in (("stream", s1), ("null stream", None)):
+            res = []
+            for i in range(24):
+                res.append(ctx.synthesize(frames[ring[i % 4]], stream=st, flags=D, max_disparity=38))
+            torch.cuda.synchronize()
+            for i, o in enumerate(res):
+                k = ring[i % 4]
+                refs.assert_views(o, refs.views(("pipe", 300 + k, 1920, 1080), host[k], 38), f"{name} frame {i}")
+    finally:
+        ctx.close()
+
+
 def test_misaligned_buffers(ctx, oracle_mod):
     """Frame and outputs at odd byte offsets take the bytewise path."""
     from paper_2009_09501_amd import pstereo_params_init, pstereo_synthesize
@@ -344,10 +397,14 @@ def test_error_codes(ctx):
     big = torch.zeros((1080, 1920, 3), dtype=torch.uint8, device=dev)
     ob = [torch.empty_like(big) for _ in range(3)]
     assert pstereo_synthesize(ctx.handle, big, 1920, 1080, q, *ob, check=False) == PSTEREO_E_INVALID
+    # video replay pipelines two stages only
+    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE_DEEP, PstereoError, pstereo_video_begin
+    with pytest.raises(PstereoError) as ei:
+        pstereo_video_begin(ctx.handle, w, h, pstereo_params_init(flags=PSTEREO_PIPELINE_DEEP))
+    assert ei.value.code == PSTEREO_E_UNSUPPORTED
     # the context still works after errors
     pstereo_synthesize(ctx.handle, f, w, h, p, *o)
     torch.cuda.synchronize()
-    _ = PSTEREO_E_UNSUPPORTED
 
 
 def _block_frame(gw, gh, K, kind):

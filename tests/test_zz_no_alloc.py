@@ -43,7 +43,8 @@ def test_noalloc_equals_context_call_twice():
 
 def test_noalloc_refuses_beyond_its_scratch():
     from paper_2009_09501_amd import pstereo_last_error, pstereo_params_init
-    from paper_2009_09501_amd.pstereo import PSTEREO_E_INVALID, PSTEREO_E_UNSUPPORTED, PSTEREO_PIPELINE
+    from paper_2009_09501_amd.pstereo import (PSTEREO_E_INVALID, PSTEREO_E_UNSUPPORTED, PSTEREO_PIPELINE,
+                                              PSTEREO_PIPELINE_DEEP)
     from paper_2009_09501_amd.pstereo import pstereo_synthesize_noalloc
     dev = torch.device("cuda:0")
     f = torch.zeros((2161, 3840, 3), dtype=torch.uint8, device=dev)
@@ -52,8 +53,8 @@ def test_noalloc_refuses_beyond_its_scratch():
     assert rc == PSTEREO_E_INVALID
     assert "static scratch" in pstereo_last_error(None)
     g = f[:8]
-    rc = pstereo_synthesize_noalloc(0, g, 3840, 8, pstereo_params_init(flags=PSTEREO_PIPELINE), *_outs(g),
-                                    check=False)
-    assert rc == PSTEREO_E_UNSUPPORTED
+    for fl in (PSTEREO_PIPELINE, PSTEREO_PIPELINE_DEEP):
+        rc = pstereo_synthesize_noalloc(0, g, 3840, 8, pstereo_params_init(flags=fl), *_outs(g), check=False)
+        assert rc == PSTEREO_E_UNSUPPORTED
     torch.cuda.synchronize()
     _ = np
