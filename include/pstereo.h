@@ -87,6 +87,10 @@ extern "C" {
                                        streams order each other through stream wait-value packets
                                        (which the runtime runs as small polling kernels), so a
                                        profiler that serialises dispatches cannot run such calls.
+                                       Streams overlap only on distinct hardware queues: the
+                                       first pipelined call on a stream waits for it and checks
+                                       (a few hundred microseconds) that the context's streams
+                                       run beside it, and replaces one that does not.
                                        Ignored with PSTEREO_DEPTH_EXTERNAL or
                                        PSTEREO_INPAINT_BLOCKS; not for stream capture */
 #define PSTEREO_PIPELINE_DEEP 0x40u /* three-stage pipelined plain calls (implies PSTEREO_PIPELINE):

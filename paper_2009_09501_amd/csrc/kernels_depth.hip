@@ -56,6 +56,32 @@ __global__ void __launch_bounds__(64) k_clear_words(uint32_t* p, int n) {
     for (int i = threadIdx.x; i < n; i += 64) p[i] = 0u;
 }
 
+// Whether two streams run beside each other.  k_probe_wait, launched on one
+// stream, waits -- bounded in wall-clock time (s_memrealtime counts at
+// 100 MHz) and in iterations, so it always ends -- for k_probe_post, launched
+// on the other stream after it, to store `token` to w[0]; it then stores 1 to
+// w[1] if it saw that store, 2 if its time ran out.  Streams that share a
+// hardware queue run the two one after the other, so the wait runs out.
+__global__ void __launch_bounds__(64) k_probe_wait(unsigned long long* w, unsigned long long token,
+                                                   unsigned long long limit_ticks) {
+    if (threadIdx.x != 0) return;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    unsigned long long seen = 2;
+    for (int i = 0; i < (1 << 16); ++i) {
+        if (__hip_atomic_load(&w[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == token) {
+            seen = 1;
+            break;
+        }
+        if (__builtin_amdgcn_s_memrealtime() - t0 > limit_ticks) break;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __hip_atomic_store(&w[1], seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ void __launch_bounds__(64) k_probe_post(unsigned long long* w, unsigned long long token) {
+    if (threadIdx.x == 0) __hip_atomic_store(&w[0], token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // The end of the kernels before it on its stream, as a word a wait-value
 // packet polls: it runs once they are done and their stores written back.
 __global__ void __launch_bounds__(64) k_signal(unsigned long long* p, unsigned long long v) {
@@ -116,6 +142,15 @@ LaunchSpec spec_rg_final(const FrameDesc& f) {
 
 hipError_t launch_clear_words(uint32_t* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(unsigned long long* w, unsigned long long token, hipStream_t wait_on, hipStream_t post_on) {
+    // 300 us: far beyond the start-up latency of a kernel on an idle stream
+    hipLaunchKernelGGL(k_probe_wait, dim3(1), dim3(64), 0, wait_on, w, token, 30000ull);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_probe_post, dim3(1), dim3(64), 0, post_on, w, token);
     return hipGetLastError();
 }
 

@@ -115,6 +115,12 @@ struct pstereo_ctx {
     bool pipe_valid = false;  // the previous pipelined call was on pipe_stream and its launches all went out
     bool pipe_deep = false;   // the previous pipelined call was a three-stage one
     bool pipe_drained = false;  // no kernel of an earlier pipelined call is still to store a mark
+    // the caller's stream the context's streams were last checked against
+    // (and whether for three stages), and the check's probe number
+    bool overlap_checked = false;
+    bool overlap_deep = false;
+    hipStream_t overlap_stream = nullptr;
+    unsigned long long probe_token = 0;
     hipStream_t pipe_stream = nullptr;
     long long pipe_n = 0;
     // block-iterative inpainting scratch, allocated on first use
@@ -136,6 +142,59 @@ struct pstereo_ctx {
     std::vector<int8_t> prof_stage;  // [kProfSets][kMaxKernels], -1 past the last kernel
     long long prof_head = 0;
 };
+
+namespace {
+
+// 1 if kernels on streams a and b ran at the same time, 0 if one ran after
+// the other, -1 on a HIP error.  Both streams are drained first; the probe
+// uses context words 4 and 5.
+int streams_overlap(pstereo_ctx* c, hipStream_t a, hipStream_t b) {
+    unsigned long long res = 0;
+    const unsigned long long token = ++c->probe_token;
+    if (hipStreamSynchronize(a) != hipSuccess || hipStreamSynchronize(b) != hipSuccess ||
+        pstereo::launch_probe(c->d_sig + 4, token, a, b) != hipSuccess || hipStreamSynchronize(a) != hipSuccess ||
+        hipStreamSynchronize(b) != hipSuccess ||
+        hipMemcpy(&res, c->d_sig + 5, sizeof res, hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    return res == 1 ? 1 : 0;
+}
+
+// Pipelined calls overlap only if the context's second stream (and, for
+// three stages, its third) runs beside the caller's stream and beside each
+// other.  HIP maps streams onto a few hardware queues (GPU_MAX_HW_QUEUES),
+// fixed when a stream is created; streams that share a queue run their
+// kernels one after the other.  So the first pipelined call on a caller
+// stream probes each pair and replaces a context stream that does not
+// overlap by a newly created one -- the rejected one stays alive meanwhile,
+// so that the new one is placed on another queue -- a few times at most.
+// Where none is found the calls stay correct, only not overlapped.  Drains
+// every stream involved.
+void ensure_overlap(pstereo_ctx* c, hipStream_t s, bool deep) {
+    if (c->overlap_checked && c->overlap_stream == s && (c->overlap_deep || !deep)) return;
+    std::vector<hipStream_t> rejected;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        hipStream_t* bad = nullptr;
+        if (streams_overlap(c, c->side, s) == 0) bad = &c->side;
+        else if (deep && streams_overlap(c, c->mid, s) == 0) bad = &c->mid;
+        else if (deep && streams_overlap(c, c->mid, c->side) == 0) bad = &c->mid;
+        if (!bad) break;
+        hipStream_t fresh = nullptr;
+        if (hipStreamCreateWithFlags(&fresh, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            break;
+        }
+        rejected.push_back(*bad);
+        *bad = fresh;
+    }
+    for (hipStream_t r : rejected) (void)hipStreamDestroy(r);
+    c->overlap_checked = true;
+    c->overlap_stream = s;
+    c->overlap_deep = deep;
+}
+
+}  // namespace
 
 namespace pstereo {
 int ctx_device(const pstereo_ctx* c) { return c->device; }
@@ -536,6 +595,7 @@ int pstereo_synthesize(pstereo_ctx* c, const uint8_t* frame, int w, int h, const
         f.rbnd = bs.rbnd;
         f.rctl = bs.rctl;
         if (deep) f.df = c->pipe_n % 2 ? c->d_df2 : c->d_df;
+        ensure_overlap(c, s, deep);
         first = !c->pipe_valid || c->pipe_stream != s || c->pipe_deep != deep;
         c->pipe_valid = false;  // until this call's launches are all enqueued
         if (first) {
@@ -834,6 +894,7 @@ int pstereo_video_begin(pstereo_ctx* c, int w, int h, const pstereo_params* p, p
         v->gidx[i] = v->pipe && v->stage[i] >= 2 ? 1 : 0;
     }
     hipError_t e = hipSetDevice(c->device);
+    if (v->pipe && e == hipSuccess) ensure_overlap(c, v->stream, false);
     if (v->pipe && e == hipSuccess && (e = hipMalloc(&v->d_sig, 16)) == hipSuccess) e = hipMemset(v->d_sig, 0, 16);
     for (int k = 0; k < pstereo_video::kRing && e == hipSuccess; ++k) {
         FrameDesc arg = video_desc(v, v->tmpl, k);

@@ -120,6 +120,10 @@ size_t regions_lds_bytes(int nb);
 hipError_t launch_clear_words(uint32_t* p, int n, hipStream_t s);
 // Store v to *p (system-scope release) once everything before it on s is done.
 hipError_t launch_signal(unsigned long long* p, unsigned long long v, hipStream_t s);
+// Concurrency probe of two idle streams: a bounded wait on wait_on for a
+// store of token to w[0] from post_on; w[1] receives 1 if the store was seen
+// while waiting, 2 if not (the streams ran one after the other).
+hipError_t launch_probe(unsigned long long* w, unsigned long long token, hipStream_t wait_on, hipStream_t post_on);
 hipError_t prepare_depth_kernels();
 hipError_t prepare_render_kernels();
 
