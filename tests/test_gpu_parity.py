@@ -347,6 +347,50 @@ def test_pipelined_deep_sequence(oracle_mod):
         ctx.close()
 
 
+def test_pipelined_streams_overlap():
+    """Eight contexts made one after another in one process, half of them
+    kept alive, so that their streams land on various hardware queues: on
+    each, two- and three-stage pipelined 4K calls take clearly less time per
+    frame than serial calls (streams sharing the caller's queue would give
+    the serial time; the first pipelined call checks for that)."""
+    import time
+    from paper_2009_09501_amd import Context
+    from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE, PSTEREO_PIPELINE_DEEP
+    dev = torch.device("cuda:0")
+    W, H = 3840, 2160
+    frames = [torch.from_numpy(synth.gen_frame(600 + i, W, H, 40, 4.0)).to(dev) for i in range(4)]
+    outs = [[torch.empty_like(frames[0]) for _ in range(3)] for _ in range(4)]
+    kept = []
+
+    def per_frame(ctx, st, fl, n=200):
+        for i in range(20):
+            ctx.synthesize(frames[i % 4], out=outs[i % 4], stream=st, flags=fl, max_disparity=77)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            ctx.synthesize(frames[i % 4], out=outs[i % 4], stream=st, flags=fl, max_disparity=77)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    try:
+        for trial in range(8):
+            ctx = Context(0, W, H)
+            st = torch.cuda.Stream()
+            ser = per_frame(ctx, st, 0)
+            p2 = per_frame(ctx, st, PSTEREO_PIPELINE)
+            p3 = per_frame(ctx, st, PSTEREO_PIPELINE_DEEP)
+            print(f"context {trial}: us per frame serial {ser * 1e6:.1f}, two stages {p2 * 1e6:.1f}, "
+                  f"three {p3 * 1e6:.1f}", flush=True)
+            assert p2 < 0.85 * ser and p3 < 0.85 * ser, trial
+            if trial % 2:
+                ctx.close()
+            else:
+                kept.append(ctx)
+    finally:
+        for c in kept:
+            c.close()
+
+
 def test_misaligned_buffers(ctx, oracle_mod):
     """Frame and outputs at odd byte offsets take the bytewise path."""
     from paper_2009_09501_amd import pstereo_params_init, pstereo_synthesize
