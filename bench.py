@@ -326,10 +326,10 @@ def video_clip(torch, synth, bank: int):
     return ts, frames
 
 
-def video_leg(torch, synth, clip, steps: int, warmup: int, n_outs: int, pipeline: bool):
-    """4K moving-ellipse video through the replayed kernel graphs (pipelined:
+def video_leg(torch, synth, clip, steps: int, warmup: int, n_outs: int, stages: int):
+    """4K moving-ellipse video through the replayed kernel graphs (stages 2:
     a frame's depth-map graph on the context's second stream during the
-    previous frame's filter and warp): the frames of ``clip`` (frame numbers,
+    previous frame's filter and warp; 1: one stream): the frames of ``clip`` (frame numbers,
     device frames) in order, cycled when ``steps`` exceeds them, frame i into
     output triple i % ``n_outs``."""
     from paper_2009_09501_amd import Context, pstereo_params_init
@@ -341,7 +341,7 @@ def video_leg(torch, synth, clip, steps: int, warmup: int, n_outs: int, pipeline
     ctx = Context(0, W, H)
     stream = torch.cuda.Stream(device=frames[0].device)
     from paper_2009_09501_amd.pstereo import PSTEREO_PIPELINE
-    p = pstereo_params_init(max_disparity=synth.default_disparity(W), flags=PSTEREO_PIPELINE if pipeline else 0)
+    p = pstereo_params_init(max_disparity=synth.default_disparity(W), flags=PSTEREO_PIPELINE if stages == 2 else 0)
     p.stream = stream.cuda_stream
     v = pstereo_video_begin(ctx.handle, W, H, p)
     try:
@@ -371,7 +371,7 @@ def video_leg(torch, synth, clip, steps: int, warmup: int, n_outs: int, pipeline
     return {"fps": round(steps / dt, 2), "ms_per_frame": round(dt / steps * 1e3, 4), "frames_timed": steps,
             "frame_gpu_ms": {"p50": round(_pct(lat, 0.5), 4), "p99": round(_pct(lat, 0.99), 4)},
             "path_hbm_frac": round(BYTES_PER_PX * W * H * steps / dt / 1e9 / HBM_PEAK_GBS, 4),
-            "pipelined": pipeline,
+            "stages": stages,
             "frames": f"VideoSpec(seed 4, 3840x2160, 300 frames, 40 ellipses, sigma 3), {bank} frames resident "
                       f"in HBM ({bank * W * H * 3 / 1e9:.2f} GB): {span}, into {n_outs} output triples"}
 
@@ -788,8 +788,8 @@ def main() -> int:
         clip = video_clip(torch, synth, args.video_bank)
         n_outs = args.video_outs or len(clip[1])
         steps = len(clip[1]) * max(1, round(args.form_steps * 5 / len(clip[1])))
-        out["forms"]["video_graph_4k"] = video_leg(torch, synth, clip, steps, 10, n_outs, True)
-        out["forms"]["video_graph_4k_serial"] = video_leg(torch, synth, clip, steps, 10, n_outs, False)
+        out["forms"]["video_graph_4k"] = video_leg(torch, synth, clip, steps, 10, n_outs, 2)
+        out["forms"]["video_graph_4k_serial"] = video_leg(torch, synth, clip, steps, 10, n_outs, 1)
         del clip
         torch.cuda.empty_cache()
     if "batch" in forms:
