@@ -354,10 +354,13 @@ int pstereo_synthesize_batch(pstereo_ctx *ctx, const pstereo_job *jobs, int n, c
  * row-warp workgroup before quads per lane grow (1, 2, 4); warp_rows (1..8)
  * rows per row-warp workgroup; fused_grid = persistent workgroups (0 = one
  * per compute unit, else 8..65536: every XCD needs workgroups for its
- * queue).  A new tuning takes effect at the next prepare.
+ * queue); bs_rows (staged form) = rows of a block-statistics tile, 256 px
+ * wide (0 = 32 for blocks up to 16 px, 64 above; else 16, 32 or 64, raised
+ * to the block size).  A new tuning takes effect at the next prepare.
  * pstereo_batch_autotune: runs the jobs (outputs are written) under each
  *   candidate tuning -- staged with warp_lanes in {128, 256, 512, 1024} x
- *   warp_rows in {1, 2, 4}, and fused -- timing `reps` launches of each with
+ *   warp_rows in {1, 2, 4}, and fused; then, if a staged candidate won, that
+ *   one with bs_rows 16, 32 and 64 -- timing `reps` launches of each with
  *   HIP events on the prepare stream, and leaves the batch prepared with the
  *   fastest; every timed candidate is reported in trials (up to cap).  The
  *   call synchronises with the stream.
@@ -370,6 +373,7 @@ typedef struct pstereo_batch_tuning {
     int32_t warp_lanes;
     int32_t warp_rows;
     int32_t fused_grid;
+    int32_t bs_rows;
 } pstereo_batch_tuning;
 
 typedef struct pstereo_batch_trial {

@@ -31,9 +31,16 @@ namespace pstereo {
 // waves' shares in LDS.
 constexpr int kBsTileW = 256;  // px: 64 quads, one per lane of a wave
 
-template <int K>
+// Rows per wave of a block-statistics tile by default (the tile is four
+// waves tall).
+__host__ __device__ constexpr int bs_default_rw(int K) { return K <= 16 ? 8 : 16; }
+
+// A 256 x 4 RWT px tile for blocks of K px (4 RWT >= K: a block never spans
+// two tiles).
+template <int K, int RWT = bs_default_rw(K)>
 struct BsTile {
-    static constexpr int RW = K <= 16 ? 8 : 16;                            // rows per wave
+    static_assert(4 * RWT >= K && (RWT == 4 || RWT == 8 || RWT == 16), "block-statistics tile rows");
+    static constexpr int RW = RWT;                                         // rows per wave
     static constexpr int TH = 4 * RW;                                      // tile rows
     static constexpr int QB = K / 4;                                       // lanes per block
     static constexpr int NBR = K >= RW ? 1 : RW / K;                       // block rows per wave
@@ -44,6 +51,11 @@ struct BsTile {
 
 // Tile rows of the block statistics for block size K (2 px blocks: 64).
 __host__ __device__ constexpr int bs_tile_rows(int K) { return K <= 2 ? 64 : K <= 16 ? 32 : 64; }
+// The same with a tuned height (0 = the default; else 16, 32 or 64, raised
+// to K so that a block never spans two tiles; 2 px blocks keep 64).
+__host__ __device__ constexpr int bs_tile_rows_tuned(int K, int rows) {
+    return K <= 2 || rows == 0 ? bs_tile_rows(K) : (rows > K ? rows : K);
+}
 
 // Rounded mean sum / cnt of a block of cnt pixels, (sum + cnt / 2) / cnt: a
 // shift for a whole K x K block (cnt = K * K, a power of two), the division
@@ -80,13 +92,13 @@ __device__ __forceinline__ void bs_quad_luma(uint3 q, uint32_t (&Y)[4]) {
     Y[3] = __builtin_amdgcn_udot4(q.z, wlo << 8, 128u, false) >> 8;
 }
 
-// One 256 x TH tile (tile_x, tile_y) on 256 lanes t = 0..255.  lds:
-// BsTile<K>::kLdsWords words.  Inactive lane groups (active == false) do no
+// One 256 x 4 RWT tile (tile_x, tile_y) on 256 lanes t = 0..255.  lds:
+// BsTile<K, RWT>::kLdsWords words.  Inactive lane groups (active == false) do no
 // memory work but pass the same barriers (blocks spanning waves only).
-template <int K, bool ALIGNED>
+template <int K, bool ALIGNED, int RWT = bs_default_rw(K)>
 __device__ __forceinline__ void bs_tile(const FrameDesc& f, int tile_x, int tile_y, int t, uint32_t* lds,
                                         bool active) {
-    using T = BsTile<K>;
+    using T = BsTile<K, RWT>;
     constexpr int QB = T::QB, NBR = T::NBR, RW = T::RW;
     constexpr uint32_t wlo = 77u | (150u << 8) | (29u << 16);
     const int wave = t >> 6, lane = t & 63;

@@ -202,13 +202,38 @@ __device__ __forceinline__ int frame_of(const int* first, int n, int idx) {
     return lo;
 }
 
-constexpr int kBsLdsMax = BsTile<16>::kLdsWords > BsTile<32>::kLdsWords ? BsTile<16>::kLdsWords
-                                                                          : BsTile<32>::kLdsWords;
+// LDS of the largest block-statistics tile over the block sizes and tile
+// heights the staged form runs.
+constexpr int kBsLdsMax = [] {
+    const int w[] = {BsTile<4, 4>::kLdsWords,  BsTile<4, 8>::kLdsWords,   BsTile<4, 16>::kLdsWords,
+                     BsTile<8, 4>::kLdsWords,  BsTile<8, 8>::kLdsWords,   BsTile<8, 16>::kLdsWords,
+                     BsTile<16, 4>::kLdsWords, BsTile<16, 8>::kLdsWords,  BsTile<16, 16>::kLdsWords,
+                     BsTile<32, 8>::kLdsWords, BsTile<32, 16>::kLdsWords, BsTile<64, 16>::kLdsWords};
+    int m = 1;
+    for (int x : w) m = x > m ? x : m;
+    return m;
+}();
 
-__global__ void __launch_bounds__(256) k_mf_blockstats(const FrameDesc* frames, const int* first, int n) {
-    static_assert(BsTile<4>::kLdsWords <= kBsLdsMax && BsTile<8>::kLdsWords <= kBsLdsMax &&
-                  BsTile<16>::kLdsWords <= kBsLdsMax && BsTile<32>::kLdsWords <= kBsLdsMax &&
-                  BsTile<64>::kLdsWords <= kBsLdsMax, "blockstats LDS");
+// A block-statistics tile of rows th (16, 32 or 64, at least K).
+template <int K>
+__device__ __forceinline__ void bs_tile_rows_of(const FrameDesc& f, int th, int tx, int ty, uint32_t* lds) {
+    if constexpr (K <= 16) {
+        if (th == 16) {
+            bs_tile<K, true, 4>(f, tx, ty, threadIdx.x, lds, true);
+            return;
+        }
+    }
+    if constexpr (K <= 32) {
+        if (th == 32) {
+            bs_tile<K, true, 8>(f, tx, ty, threadIdx.x, lds, true);
+            return;
+        }
+    }
+    bs_tile<K, true, 16>(f, tx, ty, threadIdx.x, lds, true);
+}
+
+// bs_rows: the tuned tile height (0 = each block size's default).
+__global__ void __launch_bounds__(256) k_mf_blockstats(const FrameDesc* frames, const int* first, int n, int bs_rows) {
     __shared__ uint32_t lds[kBsLdsMax];
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
     const int fi = frame_of(first, n, idx);
@@ -216,13 +241,14 @@ __global__ void __launch_bounds__(256) k_mf_blockstats(const FrameDesc* frames, 
     const int local = idx - first[fi];
     const int gx = (f.w + kBsTileW - 1) / kBsTileW;
     const int tx = local % gx, ty = local / gx;
+    const int th = bs_tile_rows_tuned(f.K, bs_rows);
     switch (f.K) {
         case 2: bs_tile_k2(f, tx, ty, threadIdx.x, true); break;
-        case 4: bs_tile<4, true>(f, tx, ty, threadIdx.x, lds, true); break;
-        case 8: bs_tile<8, true>(f, tx, ty, threadIdx.x, lds, true); break;
-        case 16: bs_tile<16, true>(f, tx, ty, threadIdx.x, lds, true); break;
-        case 32: bs_tile<32, true>(f, tx, ty, threadIdx.x, lds, true); break;
-        default: bs_tile<64, true>(f, tx, ty, threadIdx.x, lds, true); break;
+        case 4: bs_tile_rows_of<4>(f, th, tx, ty, lds); break;
+        case 8: bs_tile_rows_of<8>(f, th, tx, ty, lds); break;
+        case 16: bs_tile_rows_of<16>(f, th, tx, ty, lds); break;
+        case 32: bs_tile_rows_of<32>(f, th, tx, ty, lds); break;
+        default: bs_tile_rows_of<64>(f, th, tx, ty, lds); break;
     }
 }
 
@@ -278,7 +304,7 @@ hipError_t launch_staged(const FrameDesc* d_frames, const int* d_first, const St
     const int n = pl.n;
     const int* first_bs = d_first;
     const int* first_cbf = d_first + (n + 1);
-    hipLaunchKernelGGL(k_mf_blockstats, dim3(pl.tiles_bs), dim3(256), 0, s, d_frames, first_bs, n);
+    hipLaunchKernelGGL(k_mf_blockstats, dim3(pl.tiles_bs), dim3(256), 0, s, d_frames, first_bs, n, pl.bs_rows);
     hipLaunchKernelGGL(k_mf_regions, dim3(n), dim3(kRegionThreads), pl.regions_lds, s, d_frames);
     const void* cbf_fn;
     switch (pl.r) {
@@ -304,10 +330,10 @@ hipError_t launch_staged(const FrameDesc* d_frames, const int* d_first, const St
     return hipGetLastError();
 }
 
-int batch_tasks(const FrameDesc& f, int phase, int* items, int* gx) {
+int batch_tasks(const FrameDesc& f, int phase, int* items, int* gx, int bs_rows) {
     switch (phase) {
         case 0: {
-            const int th = bs_tile_rows(f.K);
+            const int th = bs_tile_rows_tuned(f.K, bs_rows);
             *gx = (f.w + kBsTileW - 1) / kBsTileW;
             *items = *gx * ((f.h + th - 1) / th);
             return (*items + 3) / 4;

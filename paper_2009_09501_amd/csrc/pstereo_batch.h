@@ -45,6 +45,7 @@ struct StagedPlan {
     int r = 2;
     bool k2 = false;    // blocks of 2 px (shared by every frame of the batch)
     int warp_rows = 1;  // image rows per warp workgroup
+    int bs_rows = 0;    // block-statistics tile rows (0 = each block size's default)
     int nclass = 0;
     int cls_threads[kMaxWarpClasses];
     int cls_q[kMaxWarpClasses];
@@ -70,7 +71,11 @@ struct JobScratch {
 size_t job_scratch_bytes(int w, int h, int K);
 JobScratch job_scratch_carve(uint8_t* base, int w, int h, int K);
 
-int batch_tasks(const FrameDesc& f, int phase, int* items, int* gx);
+// Stage `phase` (0 block statistics, 1 grouping, 2 filter, 3 warp) of frame
+// f: its items (tiles, or rows for the warp) and tile columns, and the
+// fused kernel's tasks for them; bs_rows: the block-statistics tile height
+// (0 = each block size's default, which the fused kernel uses).
+int batch_tasks(const FrameDesc& f, int phase, int* items, int* gx, int bs_rows = 0);
 bool batch_width_ok(int w);
 hipError_t prepare_batch_kernels();
 hipError_t launch_batch(const BatchDesc& bd, int r, int grid, hipStream_t s);

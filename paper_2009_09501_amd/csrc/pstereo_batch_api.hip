@@ -45,7 +45,7 @@ struct pstereo_batch {
     int qntask[pstereo::kXcds] = {};
     bool prepared = false;
     // tuning and the staged form's tables
-    pstereo_batch_tuning tune{PSTEREO_BATCH_STAGED, 256, 1, 0};
+    pstereo_batch_tuning tune{PSTEREO_BATCH_STAGED, 256, 1, 0, 0};
     int cus = 0;
     int* d_first = nullptr;
     int* h_first = nullptr;
@@ -344,6 +344,7 @@ int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, con
         pl.r = p.cbf_radius;
         pl.k2 = p.block_size == 2;
         pl.warp_rows = b->tune.warp_rows;
+        pl.bs_rows = b->tune.bs_rows;
         int* fb = b->h_first;
         int* fc = b->h_first + (n + 1);
         int nb_max = 1;
@@ -352,7 +353,7 @@ int batch_prepare_internal(pstereo_batch* b, const pstereo_job* jobs, int n, con
             const FrameDesc& f = b->h_frames[i];
             int items, gx;
             fb[i] = pl.tiles_bs;
-            (void)pstereo::batch_tasks(f, 0, &items, &gx);  // block-statistics tiles
+            (void)pstereo::batch_tasks(f, 0, &items, &gx, pl.bs_rows);  // block-statistics tiles
             pl.tiles_bs += items;
             fc[i] = pl.tiles_cbf;
             (void)pstereo::batch_tasks(f, 2, &items, &gx);  // depth-filter tiles
@@ -464,6 +465,8 @@ int pstereo_batch_set_tuning(pstereo_batch* b, const pstereo_batch_tuning* t) {
     if (t->warp_rows < 1 || t->warp_rows > 8) return bfail(b, PSTEREO_E_INVALID, "warp_rows %d outside 1..8", t->warp_rows);
     if (t->fused_grid < 0 || (t->fused_grid > 0 && t->fused_grid < pstereo::kXcds) || t->fused_grid > 65536)
         return bfail(b, PSTEREO_E_INVALID, "fused_grid %d: 0 or 8..65536 (every XCD serves a queue)", t->fused_grid);
+    if (t->bs_rows != 0 && t->bs_rows != 16 && t->bs_rows != 32 && t->bs_rows != 64)
+        return bfail(b, PSTEREO_E_INVALID, "bs_rows %d: 0, 16, 32 or 64", t->bs_rows);
     b->tune = *t;
     b->prepared = false;  // the tables depend on the tuning
     return PSTEREO_OK;
@@ -480,13 +483,14 @@ int pstereo_batch_autotune(pstereo_batch* b, const pstereo_job* jobs, int n, con
                            int* n_trials) {
     if (!b || reps < 1 || reps > 1000 || cap < 0 || (cap > 0 && !trials)) return PSTEREO_E_INVALID;
     // candidates: the staged form over row-workgroup lane caps and rows per
-    // workgroup, and the fused form with one workgroup per compute unit
+    // workgroup, and the fused form with one workgroup per compute unit;
+    // then, if the staged form won, its block-statistics tile heights
     std::vector<pstereo_batch_tuning> cand;
     static const int lanes[4] = {128, 256, 512, 1024};
     static const int rows[3] = {1, 2, 4};
     for (int l : lanes)
-        for (int r : rows) cand.push_back({PSTEREO_BATCH_STAGED, l, r, 0});
-    cand.push_back({PSTEREO_BATCH_FUSED, 256, 1, 0});
+        for (int r : rows) cand.push_back({PSTEREO_BATCH_STAGED, l, r, 0, 0});
+    cand.push_back({PSTEREO_BATCH_FUSED, 256, 1, 0, 0});
     const pstereo_batch_tuning saved = b->tune;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipSetDevice(b->device);
@@ -498,21 +502,22 @@ int pstereo_batch_autotune(pstereo_batch* b, const pstereo_job* jobs, int n, con
     double best_t = -1;
     pstereo_batch_tuning best_c = saved;
     int nt = 0, rc = PSTEREO_OK;
-    for (const pstereo_batch_tuning& c : cand) {
+    // time one candidate; false once an error ends the search
+    auto trial = [&](const pstereo_batch_tuning& c) -> bool {
         b->tune = c;
         int r = pstereo_batch_prepare(b, jobs, n, p);
-        if (r == PSTEREO_E_UNSUPPORTED) continue;  // e.g. a width the fused form cannot take
-        if (r != PSTEREO_OK) { rc = r; break; }
+        if (r == PSTEREO_E_UNSUPPORTED) return true;  // e.g. a width the fused form cannot take
+        if (r != PSTEREO_OK) { rc = r; return false; }
         hipStream_t st = b->stream;
-        if ((r = pstereo_batch_launch(b, nullptr)) != PSTEREO_OK) { rc = r; break; }  // warm-up
-        if (hipEventRecord(e0, st) != hipSuccess) { rc = bfail(b, PSTEREO_E_DEVICE, "event record"); break; }
+        if ((r = pstereo_batch_launch(b, nullptr)) != PSTEREO_OK) { rc = r; return false; }  // warm-up
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = bfail(b, PSTEREO_E_DEVICE, "event record"); return false; }
         for (int k = 0; k < reps && r == PSTEREO_OK; ++k) r = pstereo_batch_launch(b, nullptr);
-        if (r != PSTEREO_OK) { rc = r; break; }
+        if (r != PSTEREO_OK) { rc = r; return false; }
         float ms = 0;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
             rc = bfail(b, PSTEREO_E_DEVICE, "event timing");
-            break;
+            return false;
         }
         const double t = ms / reps;
         if (nt < cap) {
@@ -523,6 +528,17 @@ int pstereo_batch_autotune(pstereo_batch* b, const pstereo_job* jobs, int n, con
         if (best_t < 0 || t < best_t) {
             best_t = t;
             best_c = c;
+        }
+        return true;
+    };
+    bool going = true;
+    for (size_t ci = 0; ci < cand.size() && going; ++ci) going = trial(cand[ci]);
+    if (going && best_t >= 0 && best_c.mode == PSTEREO_BATCH_STAGED) {
+        const pstereo_batch_tuning base = best_c;
+        for (int h : {16, 32, 64}) {
+            pstereo_batch_tuning d = base;
+            d.bs_rows = h;
+            if (!(going = trial(d))) break;
         }
     }
     (void)hipEventDestroy(e0);
@@ -576,7 +592,7 @@ int pstereo_synthesize_batch(pstereo_ctx* ctx, const pstereo_job* jobs, int n, c
         }
         // the staged form with 512-lane row workgroups of 4 rows, the tuning
         // the autotuner picks for the uneven 720p..8K mix
-        b->tune = {PSTEREO_BATCH_STAGED, 512, 4, 0};
+        b->tune = {PSTEREO_BATCH_STAGED, 512, 4, 0, 0};
         *slot = b;
     }
     const int rc = pstereo_batch_run(b, jobs, n, p);

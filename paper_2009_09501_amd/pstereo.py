@@ -94,6 +94,7 @@ class PstereoBatchTuning(ctypes.Structure):
         ("warp_lanes", ctypes.c_int32),
         ("warp_rows", ctypes.c_int32),
         ("fused_grid", ctypes.c_int32),
+        ("bs_rows", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -363,8 +364,8 @@ def pstereo_batch_last_error(b: int) -> str:
 
 # ------------------------------------------------------- torch convenience
 def pstereo_batch_set_tuning(b: int, mode: int = PSTEREO_BATCH_STAGED, warp_lanes: int = 256,
-                             warp_rows: int = 1, fused_grid: int = 0, check: bool = True) -> int:
-    t = PstereoBatchTuning(mode, warp_lanes, warp_rows, fused_grid)
+                             warp_rows: int = 1, fused_grid: int = 0, bs_rows: int = 0, check: bool = True) -> int:
+    t = PstereoBatchTuning(mode, warp_lanes, warp_rows, fused_grid, bs_rows)
     rc = load_library().pstereo_batch_set_tuning(b, ctypes.byref(t))
     return _bcheck(rc, b) if check else rc
 

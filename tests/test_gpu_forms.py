@@ -129,6 +129,8 @@ TUNINGS = {
     "staged": dict(mode=0, warp_lanes=256, warp_rows=1),
     "staged_wide_rows3": dict(mode=0, warp_lanes=1024, warp_rows=3),
     "staged_narrow_rows8": dict(mode=0, warp_lanes=64, warp_rows=8),
+    "staged_bs16": dict(mode=0, warp_lanes=512, warp_rows=2, bs_rows=16),
+    "staged_bs64": dict(mode=0, warp_lanes=256, warp_rows=4, bs_rows=64),
     "fused": dict(mode=1),
 }
 
@@ -244,7 +246,13 @@ def test_batch_autotune_picks_a_candidate_and_stays_exact(ctx):
         jobs = make_jobs(frames, outs)
         best, best_ms, trials = pstereo_batch_autotune(b, jobs, len(frames), p, reps=2)
         print(f"autotune: best {best} {best_ms:.3f} ms over {len(trials)} candidates", flush=True)
-        assert len(trials) == 13
+        # 12 staged candidates and the fused one, then the first pass's
+        # winner with three block-statistics tile heights if it is staged
+        first = min(trials[:13], key=lambda t: t["ms"])
+        assert len(trials) == (16 if first["mode"] == 0 else 13)
+        for t in trials[13:]:
+            assert t["bs_rows"] in (16, 32, 64)
+            assert (t["warp_lanes"], t["warp_rows"]) == (first["warp_lanes"], first["warp_rows"])
         assert best_ms == min(t["ms"] for t in trials)
         assert pstereo_batch_get_tuning(b) == best
         for o in outs:
@@ -277,5 +285,8 @@ def test_batch_rejects(ctx):
         big = torch.zeros((4096, 2048, 3), dtype=torch.uint8, device=dev)
         ob = [torch.empty_like(big) for _ in range(3)]
         assert pstereo_batch_run(b, make_jobs([big], [ob]), 1, None, check=False) == PSTEREO_E_INVALID
+        from paper_2009_09501_amd.pstereo import pstereo_batch_set_tuning
+        for bad in (dict(bs_rows=24), dict(bs_rows=128), dict(warp_rows=9), dict(warp_lanes=96)):
+            assert pstereo_batch_set_tuning(b, check=False, **bad) == PSTEREO_E_INVALID, bad
     finally:
         pstereo_batch_destroy(b)
