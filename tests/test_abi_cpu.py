@@ -8,6 +8,7 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pstereo.h")
 
 
 def _declared():
@@ -64,6 +65,31 @@ def test_completion_struct_layout():
     assert ctypes.sizeof(PstereoCompletion) == 40
     assert [PstereoCompletion.__dict__[f].offset for f in
             ("req_id", "stream_id", "status", "t_submit", "t_launch", "t_done")] == [0, 8, 12, 16, 24, 32]
+
+
+def test_batch_tuning_struct_layout():
+    """pstereo_batch_tuning: the header's int32 fields in order (mode,
+    warp_lanes, warp_rows, fused_grid, bs_rows) and the trial record after
+    it (tuning, then a double)."""
+    from paper_2009_09501_amd.pstereo import PstereoBatchTrial, PstereoBatchTuning
+    hdr = open(HEADER).read()
+    body = re.search(r"typedef struct pstereo_batch_tuning \{(.*?)\} pstereo_batch_tuning;", hdr, re.S).group(1)
+    fields = re.findall(r"int32_t\s+(\w+);", body)
+    assert [f for f, _ in PstereoBatchTuning._fields_] == fields
+    assert ctypes.sizeof(PstereoBatchTuning) == 4 * len(fields)
+    assert PstereoBatchTrial.ms.offset == (4 * len(fields) + 7) // 8 * 8
+
+
+def test_header_constants_match_binding():
+    """Every flag, error code and mode the header #defines has the same value
+    in the Python binding."""
+    import paper_2009_09501_amd.pstereo as ps
+    defs = re.findall(r"#define (PSTEREO_[A-Z0-9_]+) \(?(-?(?:0x[0-9a-fA-F]+|\d+))u?\)?", open(HEADER).read())
+    assert len(defs) >= 20
+    for name, val in defs:
+        if name == "PSTEREO_NOALLOC_MAX_PIXELS":
+            continue
+        assert getattr(ps, name) == int(val, 0), name
 
 
 def test_server_bad_args_without_gpu(lib):
