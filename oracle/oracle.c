@@ -109,7 +109,7 @@ void oracle_disparity_lut(int B, int T, int32_t *P_out, int32_t *oL_out, int32_t
 
 /* ------------------------------------------------- row-range stages */
 /* The row-independent stages below each take a half-open range of image rows
- * [y0, y1); the driver runs them over all rows, either in one call or split
+ * [y0, y1); the whole-frame entry runs them over all rows, either in one call or split
  * into row bands on several threads (the CPU baseline's row-parallel mode).
  * A band's result does not depend on how the rows are split. */
 
