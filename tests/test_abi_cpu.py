@@ -100,3 +100,18 @@ def test_server_bad_args_without_gpu(lib):
     assert lib.pstereo_server_create(0, 1 << 30, 8, 2, 7, ctypes.byref(s)) == -1  # unknown policy
     assert lib.pstereo_server_submit(None, 0, None, None, None, None, None) == -1
     assert lib.pstereo_server_destroy(None) == 0
+
+
+@pytest.mark.parametrize("lang,compiler", [("c", "gcc"), ("c++", "g++")])
+def test_header_compiles_standalone(lang, compiler, tmp_path):
+    """The public header is self-contained C (and C++): a translation unit
+    that includes only it compiles without warnings."""
+    import shutil
+    import subprocess
+    if not shutil.which(compiler):
+        pytest.skip(f"{compiler} not available")
+    src = tmp_path / ("use.c" if lang == "c" else "use.cc")
+    src.write_text('#include "pstereo.h"\nint main(void) { pstereo_params p; return pstereo_params_init(&p); }\n')
+    r = subprocess.run([compiler, "-fsyntax-only", "-Wall", "-Wextra", "-Werror", "-I", os.path.dirname(HEADER),
+                        str(src)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
